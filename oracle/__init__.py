@@ -1,0 +1,341 @@
+"""ORACLE — test infrastructure only.
+
+Plain, slow, obviously-correct CPU FP64 implementations of what the GPU library
+computes. Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg
+of `bench.py` may import this package; the product library never does, and the
+two share no code (the seeded input generators in `workloads.py` are the only
+common module and hold none of the method's arithmetic).
+
+Contents, each following the paper (arXiv 2312.00538):
+  * anova_matvec / anova_columns / anova_dense — the ANOVA Gaussian kernel
+    (Section 3), by direct summation (C, `anova_direct.c`) or dense numpy.
+  * ipm_dense — the interior point method of Algorithm 1 (Section 2) with the
+    Newton system (Section 2, equation "Newton") solved densely.
+  * pivoted_cholesky — Algorithm 2 (Section 4) on the dense matrix.
+  * nystrom — the Nystrom approximation (Section 4) with LDL^T and clamping.
+  * woodbury_apply — the Sherman-Morrison-Woodbury form of the (1,1)-block
+    preconditioner (Section 5).
+  * saddle_preconditioners — the block-triangular preconditioner of Section 5
+    and its block-diagonal SPD analogue.
+  * objectives — dual objective (eq. "kernelsvm"), hinge-loss primal and the
+    relative duality gap used as the stopping measure.
+Readings where the paper is silent are listed in the design notes and repeated
+in the docstrings below.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle_direct.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C direct-sum oracle with gcc (-O2 -fopenmp, no fast-math)."""
+    src = os.path.join(_HERE, "anova_direct.c")
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(src):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               src, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            lib.oracle_anova_direct.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int32,
+                                                P, P, P, ctypes.c_int32, P, ctypes.c_int64, P]
+            lib.oracle_anova_direct.restype = ctypes.c_int
+            lib.oracle_anova_columns.argtypes = [P, ctypes.c_int64, ctypes.c_int32, P, ctypes.c_int32,
+                                                 P, P, P, ctypes.c_int64, P]
+            lib.oracle_anova_columns.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _prep(X, windows, sigma, eta):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    win = np.ascontiguousarray(windows, dtype=np.int32).reshape(-1, 3)
+    P = win.shape[0]
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, np.float64), (P,)))
+    et = np.ones(P) if eta is None else np.ascontiguousarray(np.broadcast_to(np.asarray(eta, np.float64), (P,)))
+    return X, win, sig, et
+
+
+def anova_matvec(X, windows, sigma, v, eta=None, rows=None, threads: int | None = None):
+    """y = sum_l eta_l K_l v by direct summation (Section 3). v: N or N x R.
+    rows: optional target subset; returns len(rows) x R (or N x R)."""
+    X, win, sig, et = _prep(X, windows, sigma, eta)
+    N, d = X.shape
+    v = np.asarray(v, dtype=np.float64)
+    vec = v.ndim == 1
+    V = np.asfortranarray(v.reshape(N, -1))
+    R = V.shape[1]
+    if rows is not None:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        nr = rows.shape[0]
+    else:
+        nr = N
+    Y = np.zeros((nr, R), order="F")
+    lib = _load()
+    old = os.environ.get("OMP_NUM_THREADS")
+    rc = lib.oracle_anova_direct(_ptr(X), N, d, _ptr(win), win.shape[0], _ptr(sig), _ptr(et),
+                                 _ptr(V), R, _ptr(rows) if rows is not None else None, nr, _ptr(Y))
+    if rc != 0:
+        raise ValueError("oracle_anova_direct failed")
+    return Y[:, 0] if vec else Y
+
+
+def anova_columns(X, windows, sigma, cols, eta=None):
+    """Kernel columns K[:, cols] (Section 3 definition), N x len(cols)."""
+    X, win, sig, et = _prep(X, windows, sigma, eta)
+    N, d = X.shape
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros((N, cols.shape[0]), order="F")
+    _load().oracle_anova_columns(_ptr(X), N, d, _ptr(win), win.shape[0], _ptr(sig), _ptr(et),
+                                 _ptr(cols), cols.shape[0], _ptr(out))
+    return out
+
+
+def anova_dense(X, windows, sigma, eta=None):
+    """Dense K = sum_l eta_l K_l with (K_l)_{ij} = exp(-sum_{a in W_l}(X_ia - X_ja)^2 / sigma_l^2)
+    (Section 3). Numpy, explicit differences, row blocks to bound memory."""
+    X, win, sig, et = _prep(X, windows, sigma, eta)
+    N = X.shape[0]
+    K = np.zeros((N, N))
+    blk = max(1, int(2e7 // max(N, 1)))
+    for l in range(win.shape[0]):
+        f = [int(c) for c in win[l] if c >= 0]
+        Xw = X[:, f]
+        for s in range(0, N, blk):
+            diff = Xw[s:s + blk, None, :] - Xw[None, :, :]
+            K[s:s + blk] += et[l] * np.exp(-(diff * diff).sum(-1) / sig[l] ** 2)
+    return K
+
+
+# ----------------------------------------------------------------------------- objectives
+
+def dual_objective(K, y, alpha):
+    """e^T alpha - 1/2 alpha^T Y K Y alpha (eq. "kernelsvm")."""
+    ya = y * alpha
+    return float(alpha.sum() - 0.5 * ya @ (K @ ya))
+
+
+def objectives_from_kya(kya, y, alpha, lam, C):
+    """Dual D, hinge primal Pr and relative gap G = (Pr - D)/(1 + |Pr|), from the
+    product K (Y alpha). Decision values f = K Y alpha - lambda (bias b = -lambda,
+    which follows from the optimality conditions of Section 2)."""
+    quad = float((y * alpha) @ kya)
+    D = float(alpha.sum()) - 0.5 * quad
+    f = kya - lam
+    hinge = np.maximum(0.0, 1.0 - y * f).sum()
+    Pr = 0.5 * quad + C * float(hinge)
+    return D, Pr, (Pr - D) / (1.0 + abs(Pr))
+
+
+# ----------------------------------------------------------------------------- IPM (Algorithm 1)
+
+def initial_point(y, C):
+    """alpha^0_i = C(2 + y_i)/4 if sum(y) >= 0 else C(2 - y_i)/4, lambda^0 = 0, so
+    that xi_alpha^0 = y^T alpha^0 != 0 as Algorithm 1 requires."""
+    if y.sum() >= 0:
+        a = C * (2.0 + y) / 4.0
+    else:
+        a = C * (2.0 - y) / 4.0
+    return a, 0.0
+
+
+def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0=0.99995,
+              mu0=1.0, record=False):
+    """Algorithm 1 (Section 2) with the Newton system (eq. "Newton") solved by a
+    dense LU solve of the (N+1) x (N+1) saddle-point matrix.
+
+    Per iteration: mu <- sigma_bar * mu; Theta = mu (1/alpha^2 + 1/(C-alpha)^2);
+    solve [[YKY + Theta, -y], [-y^T, 0]] [da; dl] =
+          [e - YKY alpha + lambda y + mu/alpha - mu/(C-alpha); y^T alpha];
+    step s = gamma0 * min(1, s_max) with s_max the largest step keeping
+    0 < alpha < C (the same step for lambda); update; recompute the
+    infeasibilities xi_alpha = y^T alpha and xi_lambda (the first Newton block
+    residual at the current mu) and the relative duality gap G.
+    Stop when mu <= tol, |xi_alpha|/|xi_alpha^0| <= tol, G <= tol and
+    ||xi_lambda||/||xi_lambda^0|| <= tol_inf, or after max_ip steps. The
+    xi_lambda ratio keeps the IPM tolerance of Table 1 (1e-1): with a primal
+    barrier Newton step the residual of the barrier terms at active bounds does
+    not vanish as mu -> 0, so that ratio levels off well above 1e-6.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    N = y.shape[0]
+    YKY = y[:, None] * K * y[None, :]
+    alpha, lam = initial_point(y, C)
+    mu = mu0
+
+    def xi_lambda(a, l, m):
+        return 1.0 - YKY @ a + l * y + m / a - m / (C - a)
+
+    xa0 = abs(float(y @ alpha))
+    xl0 = float(np.linalg.norm(xi_lambda(alpha, lam, mu)))
+    xa, xl = xa0, xl0
+    kya = K @ (y * alpha)
+    D, Pr, G = objectives_from_kya(kya, y, alpha, lam, C)
+    it = 0
+    hist = []
+    while it < max_ip:
+        if mu <= tol and xa / xa0 <= tol and xl / xl0 <= tol_inf and G <= tol:
+            break
+        mu = sigma_bar * mu
+        theta = mu * (1.0 / alpha ** 2 + 1.0 / (C - alpha) ** 2)
+        r1 = 1.0 - YKY @ alpha + lam * y + mu / alpha - mu / (C - alpha)
+        r2 = float(y @ alpha)
+        A = np.zeros((N + 1, N + 1))
+        A[:N, :N] = YKY + np.diag(theta)
+        A[:N, N] = -y
+        A[N, :N] = -y
+        sol = np.linalg.solve(A, np.concatenate([r1, [r2]]))
+        da, dl = sol[:N], sol[N]
+        smax = np.inf
+        neg = da < 0
+        pos = da > 0
+        if neg.any():
+            smax = min(smax, float(np.min(-alpha[neg] / da[neg])))
+        if pos.any():
+            smax = min(smax, float(np.min((C - alpha[pos]) / da[pos])))
+        s = gamma0 * min(1.0, smax)
+        alpha = alpha + s * da
+        lam = lam + s * dl
+        xa = abs(float(y @ alpha))
+        xl = float(np.linalg.norm(xi_lambda(alpha, lam, mu)))
+        kya = K @ (y * alpha)
+        D, Pr, G = objectives_from_kya(kya, y, alpha, lam, C)
+        it += 1
+        if record:
+            hist.append(dict(it=it, mu=mu, step=s, xa=xa / xa0, xl=xl / xl0, D=D, G=G))
+    converged = mu <= tol and xa / xa0 <= tol and xl / xl0 <= tol_inf and G <= tol
+    return dict(alpha=alpha, lam=lam, mu=mu, it=it, D=D, Pr=Pr, G=G,
+                xa_rel=xa / xa0, xl_rel=xl / xl0, converged=converged, hist=hist)
+
+
+# ----------------------------------------------------------------------------- Algorithm 2
+
+def pivoted_cholesky(K, k, err_tol=0.0):
+    """Greedy pivoted Cholesky of rank <= k (Algorithm 2, Section 4) on a copy of
+    the dense K: at step j pick the largest remaining diagonal entry (lowest
+    index on ties), swap it to position j symmetrically, take the square root,
+    scale the column below and apply the rank-1 update to the trailing block.
+    Stops when r = k, the largest remaining diagonal is <= 0, or the remaining
+    trace is <= err_tol * trace(K).
+    Returns (L, piv) with L N x r in the ORIGINAL row order, K ~= L L^T, and the
+    pivot indices in the order chosen."""
+    A = np.array(K, dtype=np.float64, copy=True)
+    n = A.shape[0]
+    perm = np.arange(n)
+    trace0 = float(np.trace(A))
+    r = 0
+    for j in range(n):
+        dg = np.diag(A)[j:]
+        l = j + int(np.argmax(dg))
+        if not (A[l, l] > 0 and r < k):
+            break
+        if err_tol > 0 and float(dg.sum()) <= err_tol * trace0:
+            break
+        r += 1
+        if l != j:
+            A[[j, l], :] = A[[l, j], :]
+            A[:, [j, l]] = A[:, [l, j]]
+            perm[[j, l]] = perm[[l, j]]
+        A[j, j] = np.sqrt(A[j, j])
+        A[j + 1:, j] /= A[j, j]
+        c = A[j + 1:, j]
+        A[j + 1:, j + 1:] -= np.outer(c, c)
+    Lp = np.tril(A[:, :r])
+    L = np.zeros_like(Lp)
+    L[perm] = Lp
+    return L, perm[:r].copy()
+
+
+# ----------------------------------------------------------------------------- Nystrom
+
+def ldl_clamped(M, tau):
+    """LDL^T of a symmetric matrix without pivoting; a diagonal entry of D that is
+    smaller than tau is replaced by tau (the stabilisation described for the
+    Nystrom method, Section 4)."""
+    n = M.shape[0]
+    L = np.eye(n)
+    D = np.zeros(n)
+    for j in range(n):
+        dj = M[j, j] - (L[j, :j] ** 2) @ D[:j]
+        if dj < tau:
+            dj = tau
+        D[j] = dj
+        for i in range(j + 1, n):
+            L[i, j] = (M[i, j] - (L[i, :j] * L[j, :j]) @ D[:j]) / dj
+    return L, D
+
+
+def nystrom(K, G, tau_rel=1e-12):
+    """Randomized Nystrom approximation (Section 4): Q = orth(K G),
+    K ~= (KQ)(Q^T K Q)^{-1}(KQ)^T with Q^T K Q = L D L^T (clamped).
+    Returns Zt (N x k) with K ~= Zt Zt^T, Zt = (KQ) L^{-T} D^{-1/2}."""
+    Yk = K @ G
+    Q, _ = np.linalg.qr(Yk)
+    B = K @ Q
+    Cm = Q.T @ B
+    Cm = 0.5 * (Cm + Cm.T)
+    tau = tau_rel * float(np.max(np.diag(Cm)))
+    L, D = ldl_clamped(Cm, tau)
+    W = np.linalg.solve(L, B.T).T          # B L^{-T}
+    return W / np.sqrt(D)[None, :]
+
+
+# ----------------------------------------------------------------------------- Section 5
+
+def woodbury_apply(theta, y, Zt, r):
+    """A_hat^{-1} r for A_hat = Theta + Y Z^T Z Y via the Sherman-Morrison-Woodbury
+    form of Section 5:
+        Theta^{-1} - Theta^{-1} Y Z^T (I_k + Z Y Theta^{-1} Y Z^T)^{-1} Z Y Theta^{-1}.
+    Zt is Z^T (N x k)."""
+    tinv = 1.0 / theta
+    k = Zt.shape[1]
+    M = np.eye(k) + Zt.T @ (Zt * (y * tinv * y)[:, None])
+    w = Zt.T @ (y * tinv * r)
+    t = np.linalg.solve(M, w)
+    return tinv * r - tinv * y * (Zt @ t)
+
+
+def saddle_matrix(K, y, theta):
+    """The Newton matrix A of eq. "Newton": [[YKY + Theta, -y], [-y^T, 0]]."""
+    N = y.shape[0]
+    A = np.zeros((N + 1, N + 1))
+    A[:N, :N] = y[:, None] * K * y[None, :] + np.diag(theta)
+    A[:N, N] = -y
+    A[N, :N] = -y
+    return A
+
+
+def saddle_preconditioners(Ahat, y):
+    """Section 5: block-triangular P = [[Ahat, 0], [-y^T, -1]] and the
+    block-diagonal SPD analogue P_d = diag(Ahat, y^T Ahat^{-1} y)."""
+    N = y.shape[0]
+    Pt = np.zeros((N + 1, N + 1))
+    Pt[:N, :N] = Ahat
+    Pt[N, :N] = -y
+    Pt[N, N] = -1.0
+    Pd = np.zeros((N + 1, N + 1))
+    Pd[:N, :N] = Ahat
+    Pd[N, N] = float(y @ np.linalg.solve(Ahat, y))
+    return Pt, Pd
