@@ -1,0 +1,227 @@
+/*
+ * anova_nfft.h — C ABI of the MI355X (gfx950) library for the ANOVA-kernel
+ * matrix-vector product by NFFT fast summation and the interior point SVM
+ * solver built on it (Wagner, Pearson, Stoll, arXiv 2312.00538).
+ *
+ * Conventions for every entry point
+ *   - Return value: int status, ANOVA_OK (0) on success; nothing is thrown
+ *     across the ABI. On failure anova_last_error() returns a message for the
+ *     calling thread. Outputs are unspecified on error except where noted.
+ *   - "device" pointers address GPU memory (e.g. a torch tensor's data_ptr()
+ *     on the current device); "host" pointers address CPU memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *     GPU work of a call is enqueued on that stream, in stream order.
+ *   - The caller owns every buffer it passes in. The library never keeps a
+ *     caller pointer after a call returns; it owns only the memory behind an
+ *     anova_plan_t (transformed coordinates, window weights, grids, scratch),
+ *     released by anova_plan_destroy.
+ *   - A plan must not be used by two calls at the same time (its scratch
+ *     buffers are shared); distinct plans are independent.
+ */
+#ifndef ANOVA_NFFT_H
+#define ANOVA_NFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define ANOVA_OK              0
+#define ANOVA_INVALID_ARG     1  /* bad size, index, parameter or label       */
+#define ANOVA_OUT_OF_MEMORY   2  /* a device or host allocation failed        */
+#define ANOVA_HIP_ERROR       3  /* a HIP runtime call or kernel launch failed */
+#define ANOVA_NOT_CONVERGED   4  /* iteration cap reached; outputs hold the last iterate */
+#define ANOVA_NUMERICAL       5  /* NaN/Inf, or a factorisation broke down     */
+
+/* arithmetic of the NFFT stages (spreading, grid convolution, gathering) */
+#define ANOVA_PREC_FP64   0  /* everything in FP64                                   */
+#define ANOVA_PREC_MIXED  1  /* FP32 weights, grids and taps; FP64 window sums        */
+
+/* preconditioner of the Krylov solve inside the IPM */
+#define ANOVA_PRECOND_NONE     0  /* unpreconditioned MINRES                           */
+#define ANOVA_PRECOND_PCHOL    1  /* greedy pivoted Cholesky, Algorithm 2 (Section 4)   */
+#define ANOVA_PRECOND_NYSTROM  2  /* randomized Nystrom, Q = orth(K G) (Section 4)      */
+
+#define ANOVA_OPTS_VERSION 1
+#define ANOVA_IPM_OPTS_VERSION 1
+
+typedef struct anova_plan_s* anova_plan_t;
+
+/* NFFT fast-summation options (Section 3: bandwidth N and window parameter m
+ * of the NFFT; the oversampling factor and the periodic regularisation of the
+ * Gaussian are those of the NFFT fast-summation literature the paper cites). */
+typedef struct {
+    int32_t version;     /* ANOVA_OPTS_VERSION                                     */
+    int32_t n_bw;        /* bandwidth N: frequencies -N/2..N/2-1 per axis (even)   */
+    int32_t oversample;  /* FFT length per axis = oversample * n_bw                */
+    int32_t cutoff_m;    /* Kaiser-Bessel half-width m in grid cells (2..4)        */
+    double  eps_b;       /* boundary width of the periodic regularisation, (0,1/2) */
+    int32_t reg_p;       /* smoothness of the regularisation; <= 0 picks per axis  */
+    int32_t precision;   /* ANOVA_PREC_FP64 or ANOVA_PREC_MIXED                    */
+    int32_t seg_points;  /* points per spreading work item; <= 0 = default         */
+    int32_t reserved;
+} anova_opts;
+
+/* Fill `o` with the defaults: n_bw = 32, oversample = 2, cutoff_m = 4,
+ * eps_b = 1/4, reg_p = 0 (automatic), precision = FP64. */
+int anova_opts_default(anova_opts* o);
+
+/* Build a fast-summation plan for the ANOVA Gaussian kernel of Section 3:
+ *     K = sum_{l=1..P} eta_l K_l,
+ *     (K_l)_{ij} = exp(-||x_i^{W_l} - x_j^{W_l}||^2 / sigma_l^2),
+ * each window W_l holding 1..3 features.
+ *   X        device, N x d FP64, row i at X + i*ldx (ldx >= d). Read during the
+ *            call only; the plan keeps transformed copies.
+ *   windows  host, P x 3 int32 feature indices in [0, d), -1 marks an unused
+ *            slot; every window has 1..3 distinct features.
+ *   sigma    host, P FP64 kernel widths (> 0), one per window.
+ *   eta      host, P FP64 window weights, or NULL for eta_l = 1.
+ *   opts     host, NULL for the defaults.
+ *   out      host, receives the plan handle.
+ * Errors: ANOVA_INVALID_ARG (N < 1, d < 1, P < 1, bad window, sigma <= 0,
+ * unsupported options), ANOVA_OUT_OF_MEMORY, ANOVA_HIP_ERROR. The call
+ * synchronises `stream` (it reads back bin counts to lay out the work). */
+int anova_plan_create(const double* X, int64_t N, int32_t d, int64_t ldx,
+                      const int32_t* windows, int32_t P,
+                      const double* sigma, const double* eta,
+                      const anova_opts* opts, void* stream, anova_plan_t* out);
+
+/* y = K x for R right-hand sides (Section 3, "(K_1 + ... + K_P) v"): every
+ * window is evaluated by NFFT fast summation (spread with the Kaiser-Bessel
+ * window, grid convolution with the kernel's Fourier coefficients, gather)
+ * and the windows are summed in FP64 in a fixed order, so results are
+ * bitwise reproducible for a given plan and input.
+ *   x   device, N x R FP64, column r at x + r*ldx_ (ldx_ >= N).
+ *   y   device, N x R FP64 output, column r at y + r*ldy (ldy >= N); must not
+ *       overlap x.
+ * Asynchronous on `stream`. Errors: ANOVA_INVALID_ARG (NULL plan/pointers,
+ * R < 1, leading dimensions < N), ANOVA_HIP_ERROR. */
+int anova_matvec(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_,
+                 double* y, int64_t ldy, void* stream);
+
+/* Release a plan and all device memory it owns (synchronises the device).
+ * NULL is accepted. */
+int anova_plan_destroy(anova_plan_t plan);
+
+/* Plan facts for diagnostics and tests (host struct filled by the call). */
+typedef struct {
+    int64_t n_points;
+    int32_t n_windows;
+    int32_t n_segments;      /* spreading/gathering work items                  */
+    int32_t cutoff_m;
+    int32_t precision;
+    double  eps_b;
+    double  max_kernel_err;  /* max over windows/axes of the 1D regularised-
+                                kernel interpolation error (absolute)           */
+    int64_t grid_cells;      /* occupied grid cells summed over windows          */
+    int64_t device_bytes;    /* device memory owned by the plan                  */
+} anova_plan_info_t;
+int anova_plan_info(anova_plan_t plan, anova_plan_info_t* info);
+
+/* Stage timing for measurement tools. Between anova_profile_begin and
+ * anova_profile_end, every anova_matvec on the plan also records HIP events on
+ * the caller's stream between its stages (no extra synchronisation):
+ *   0 permute input, 1 spread, 2 fold slabs, 3 grid convolution (3 axis
+ *   passes), 4 gather, 5 window sum.
+ * anova_profile_end synchronises on the last event and writes, for each
+ * stage s < nstage, the mean duration per right-hand-side pass in ms
+ * (stage_ms, host) and the number of passes measured (*passes, host).
+ * Errors: ANOVA_INVALID_ARG, ANOVA_HIP_ERROR. */
+#define ANOVA_NSTAGES 6
+int anova_profile_begin(anova_plan_t plan);
+int anova_profile_end(anova_plan_t plan, double* stage_ms, int32_t nstage, int32_t* passes);
+
+/* ------------------------------------------------------------------ IPM
+ * Interior point method of Algorithm 1 (Section 2) for the soft-margin SVM
+ * dual (Section 1, eq. "kernelsvm"):
+ *     max e^T a - 1/2 a^T Y K Y a  s.t. 0 <= a <= C, y^T a = 0,
+ * with K the plan's ANOVA kernel. Each Newton system (Section 2, eq.
+ * "Newton") is solved by MINRES preconditioned with the block-diagonal SPD
+ * matrix diag(A_hat, y^T A_hat^{-1} y), A_hat = Theta + Y Z^T Z Y, applied
+ * through the Sherman-Morrison-Woodbury identity (Section 5), with the
+ * low-rank factor Z^T from Algorithm 2 or the Nystrom method (Section 4). */
+typedef struct {
+    int32_t version;     /* ANOVA_IPM_OPTS_VERSION                               */
+    int32_t max_ip;      /* IPM iteration cap (Table 1: 50)                      */
+    int32_t max_kry;     /* MINRES iterations per Newton solve (Table 1: 100)    */
+    int32_t precond;     /* ANOVA_PRECOND_*                                      */
+    double  tol;         /* on mu, |y^T a|/|y^T a0| and the relative duality gap */
+    double  tol_inf;     /* on ||xi_lambda||/||xi_lambda^0|| (Table 1: 1e-1)    */
+    double  tol_kry;     /* upper bound of the MINRES relative tolerance (1e-3)  */
+    double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */
+    double  gamma0;      /* step-to-boundary factor (Algorithm 1: 0.99995)       */
+    double  mu0;         /* initial barrier parameter (Algorithm 1: 1.0)         */
+    int32_t rank;        /* low-rank factor rank k                               */
+    int32_t reserved;
+    double  err_tol;     /* pivoted-Cholesky trace tolerance (Table 1: 1e-5)     */
+    uint64_t seed;       /* Gaussian test matrix of the Nystrom method           */
+} anova_ipm_opts;
+
+typedef struct {
+    int32_t ip_iters;
+    int32_t kry_iters_total;
+    int32_t kry_iters_max;
+    int32_t rank_used;
+    int32_t status;
+    int32_t matvecs;
+    double  mu;
+    double  rel_gap;         /* (Pr - D)/(1 + |Pr|) with the plan's operator     */
+    double  dual_obj;        /* D = e^T a - 1/2 a^T Y K Y a                      */
+    double  primal_obj;      /* 1/2 a^T Y K Y a + C sum max(0, 1 - y_i f_i)      */
+    double  xi_alpha_rel;
+    double  xi_lambda_rel;
+    double  t_setup_ms;      /* preconditioner build                             */
+    double  t_solve_ms;      /* whole call                                       */
+} anova_ipm_stats;
+
+/* Fill `o` with the defaults: Table 1 values (max_ip = 50 raised to 100,
+ * max_kry = 100, tol_kry = 1e-3, sigma_bar = 0.6, gamma0 = 0.99995,
+ * mu0 = 1, err_tol = 1e-5), tol = 1e-6, tol_inf = 1e-1, precond = PCHOL,
+ * rank = 200, seed = 0. */
+int anova_ipm_opts_default(anova_ipm_opts* o);
+
+/* Train: alpha (device, N FP64 out), lambda (host, 1 FP64 out; the bias of
+ * the decision function f(x) = sum_j alpha_j y_j k(x, x_j) - lambda).
+ *   labels  device, N FP64 values in {-1, +1}, both classes present.
+ *   C       box bound (> 0).
+ *   opts    host or NULL (defaults); stats host or NULL.
+ * Synchronises `stream` (host-driven iteration). Errors: ANOVA_INVALID_ARG,
+ * ANOVA_OUT_OF_MEMORY, ANOVA_HIP_ERROR, ANOVA_NUMERICAL; ANOVA_NOT_CONVERGED
+ * when max_ip is reached, with alpha/lambda/stats holding the last iterate. */
+int svm_ipm_solve(anova_plan_t plan, const double* labels, double C,
+                  const anova_ipm_opts* opts, double* alpha, double* lambda,
+                  anova_ipm_stats* stats, void* stream);
+
+/* Greedy pivoted Cholesky of the plan's kernel (Algorithm 2, Section 4),
+ * column by column with exact kernel columns: K ~= L L^T.
+ *   rank     maximum rank k; err_tol stops early when the remaining trace is
+ *            <= err_tol * trace(K).
+ *   L        device, N x rank FP64 output, column j at L + j*ldl (ldl >= N);
+ *            columns >= *rank_used are unspecified.
+ *   piv      host, rank int64 output, pivot indices in the order chosen.
+ *   rank_used host output.
+ * Synchronises `stream`. Errors: ANOVA_INVALID_ARG, ANOVA_HIP_ERROR. */
+int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol,
+                           double* L, int64_t ldl, int64_t* piv, int32_t* rank_used,
+                           void* stream);
+
+/* Randomized Nystrom factor (Section 4): Q = orth(K G) and
+ * K ~= (KQ)(Q^T K Q)^{-1}(KQ)^T = Z^T Z, with Q^T K Q = L D L^T and diagonal
+ * entries of D below 1e-12 * max(diag(Q^T K Q)) raised to that value.
+ *   G    device, N x k FP64 test matrix (column j at G + j*ldg); drawn by the
+ *        caller so that the factor is reproducible.
+ *   Zt   device, N x k FP64 output Z^T (column j at Zt + j*ldz).
+ * Synchronises `stream`. Errors: ANOVA_INVALID_ARG (k < 1 or k > N),
+ * ANOVA_NUMERICAL (orthonormalisation broke down), ANOVA_HIP_ERROR. */
+int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg,
+                  double* Zt, int64_t ldz, void* stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* anova_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ANOVA_NFFT_H */

@@ -1,0 +1,188 @@
+// extern "C" entry points: argument checks, exception-to-status translation
+// and the thread-local error message.
+#include <chrono>
+#include <cstring>
+#include <memory>
+
+#include "plan.hpp"
+#include "solver.hpp"
+
+namespace anv {
+static thread_local std::string g_last_error;
+void set_last_error(const std::string& m) { g_last_error = m; }
+}  // namespace anv
+
+using anv::Error;
+
+template <class F>
+static int guarded(F&& f) {
+    try {
+        anv::set_last_error("");
+        return f();
+    } catch (const Error& e) {
+        anv::set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        anv::set_last_error("host allocation failed");
+        return ANOVA_OUT_OF_MEMORY;
+    } catch (const std::exception& e) {
+        anv::set_last_error(e.what());
+        return ANOVA_HIP_ERROR;
+    }
+}
+
+struct anova_plan_s {
+    std::unique_ptr<anv::Plan> p;
+};
+
+extern "C" {
+
+int anova_opts_default(anova_opts* o) {
+    if (!o) return ANOVA_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->version = ANOVA_OPTS_VERSION;
+    o->n_bw = 32;
+    o->oversample = 2;
+    o->cutoff_m = 4;
+    o->eps_b = 0.25;
+    o->reg_p = 0;
+    o->precision = ANOVA_PREC_FP64;
+    o->seg_points = 0;
+    return ANOVA_OK;
+}
+
+int anova_plan_create(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows,
+                      int32_t P, const double* sigma, const double* eta, const anova_opts* opts,
+                      void* stream, anova_plan_t* out) {
+    return guarded([&] {
+        ANV_CHECK(out != nullptr, "NULL output handle");
+        *out = nullptr;
+        auto h = std::make_unique<anova_plan_s>();
+        h->p.reset(anv::create_plan(X, N, d, ldx, windows, P, sigma, eta, opts,
+                                    static_cast<hipStream_t>(stream)));
+        *out = h.release();
+        return ANOVA_OK;
+    });
+}
+
+int anova_matvec(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_, double* y, int64_t ldy,
+                 void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(x && y, "NULL vector");
+        ANV_CHECK(R >= 1, "R < 1");
+        ANV_CHECK(ldx_ >= plan->p->N && ldy >= plan->p->N, "leading dimension < N");
+        anv::enqueue_matvec(*plan->p, x, R, ldx_, y, ldy, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
+int anova_plan_destroy(anova_plan_t plan) {
+    return guarded([&] {
+        if (plan) {
+            (void)hipDeviceSynchronize();
+            delete plan;
+        }
+        return ANOVA_OK;
+    });
+}
+
+int anova_plan_info(anova_plan_t plan, anova_plan_info_t* info) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p && info, "NULL argument");
+        const anv::Plan& p = *plan->p;
+        std::memset(info, 0, sizeof(*info));
+        info->n_points = p.N;
+        info->n_windows = p.P;
+        info->n_segments = int32_t(p.segs_h.size());
+        info->cutoff_m = p.prm.m;
+        info->precision = p.precision;
+        info->eps_b = p.prm.eps_b;
+        info->max_kernel_err = p.max_kerr;
+        info->grid_cells = p.grid_total;
+        info->device_bytes = p.device_bytes();
+        return ANOVA_OK;
+    });
+}
+
+int anova_profile_begin(anova_plan_t plan) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        anv::profile_begin(*plan->p);
+        return ANOVA_OK;
+    });
+}
+
+int anova_profile_end(anova_plan_t plan, double* stage_ms, int32_t nstage, int32_t* passes) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(stage_ms && nstage >= 0, "NULL stage_ms");
+        int n = anv::profile_end(*plan->p, stage_ms, nstage);
+        if (passes) *passes = n;
+        return ANOVA_OK;
+    });
+}
+
+int anova_ipm_opts_default(anova_ipm_opts* o) {
+    if (!o) return ANOVA_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->version = ANOVA_IPM_OPTS_VERSION;
+    o->max_ip = 100;
+    o->max_kry = 100;
+    o->precond = ANOVA_PRECOND_PCHOL;
+    o->tol = 1e-6;
+    o->tol_inf = 1e-1;
+    o->tol_kry = 1e-3;
+    o->sigma_bar = 0.6;
+    o->gamma0 = 0.99995;
+    o->mu0 = 1.0;
+    o->rank = 200;
+    o->err_tol = 1e-5;
+    o->seed = 0;
+    return ANOVA_OK;
+}
+
+int svm_ipm_solve(anova_plan_t plan, const double* labels, double C, const anova_ipm_opts* opts,
+                  double* alpha, double* lambda, anova_ipm_stats* stats, void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        anova_ipm_opts o;
+        anova_ipm_opts_default(&o);
+        if (opts) {
+            ANV_CHECK(opts->version == ANOVA_IPM_OPTS_VERSION, "anova_ipm_opts.version mismatch");
+            o = *opts;
+        }
+        return anv::ipm_solve(*plan->p, labels, C, o, alpha, lambda, stats,
+                              static_cast<hipStream_t>(stream));
+    });
+}
+
+int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol, double* L, int64_t ldl,
+                           int64_t* piv, int32_t* rank_used, void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(L && piv && rank_used, "NULL output");
+        ANV_CHECK(rank >= 1 && rank <= plan->p->N, "rank must be in [1, N]");
+        ANV_CHECK(ldl >= plan->p->N, "ldl < N");
+        ANV_CHECK(err_tol >= 0.0, "err_tol < 0");
+        *rank_used = anv::pivoted_cholesky(*plan->p, rank, err_tol, L, ldl, piv,
+                                           static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
+int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg, double* Zt, int64_t ldz,
+                  void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(G && Zt, "NULL pointer");
+        ANV_CHECK(k >= 1 && k <= plan->p->N, "k must be in [1, N]");
+        ANV_CHECK(ldg >= plan->p->N && ldz >= plan->p->N, "leading dimension < N");
+        anv::nystrom_factor(*plan->p, G, k, ldg, Zt, ldz, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
+const char* anova_last_error(void) { return anv::g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// The fast-summation plan: everything that depends only on (X, windows, sigma).
+#pragma once
+#include <array>
+#include <memory>
+
+#include "common.hpp"
+
+namespace anv {
+
+struct Plan {
+    int64_t N = 0;
+    int32_t d = 0, P = 0;
+    int32_t W = 8;              // taps per axis = 2m
+    NfftParams prm;
+    int32_t precision = ANOVA_PREC_FP64;
+    int32_t seg_points = 256;
+    std::vector<int32_t> win;   // P x 3 as given
+    std::vector<double> sigma, eta;
+    std::vector<std::array<int32_t, 3>> slot_feat;  // feature per slot, -1 = dummy
+    std::vector<std::array<AxisCoef, 3>> axes;
+    std::vector<WinDev> wins_h;
+    DevBuf<WinDev> wins_d;
+
+    // per (window, sorted position): point index, base z cell, Kaiser-Bessel weights
+    DevBuf<int32_t> perm;       // [P*N] sorted position -> point
+    DevBuf<int32_t> pos;        // [P*N] point -> sorted position
+    DevBuf<int32_t> zq;         // [P*N]
+    DevBuf<double> wts64;       // [P*N][3][W]
+    DevBuf<float> wts32;        // same, mixed precision
+
+    std::vector<Segment> segs_h;
+    DevBuf<Segment> segs;
+    DevBuf<int2> fold;          // per (window, column, layer): covering segment range
+    int64_t fold_total = 0;
+    DevBuf<double> tmat;        // Toeplitz matrices, row-major E x E per (window, slot)
+    int64_t tmat_total = 0;
+    int64_t grid_total = 0;     // occupied cells summed over windows
+    int64_t grid_max = 0;       // largest window grid
+    int64_t slab_total = 0;
+
+    // original windowed coordinates [N][P][3] (exact kernel columns)
+    DevBuf<double> xw;
+
+    // matvec scratch
+    DevBuf<double> vs, fs;      // [P*N]
+    DevBuf<double> g64, h64, c64a, c64b;  // grids [grid_total]
+    DevBuf<float> g32, h32, c32a, c32b;
+    DevBuf<double> slab64;
+    DevBuf<float> slab32;
+
+    // stage timing (measurement hook)
+    bool profiling = false;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+    void record_stage_event(hipStream_t st);
+
+    double max_kerr = 0.0;
+    ~Plan();
+    int64_t device_bytes() const;
+};
+
+Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows,
+                  int32_t P, const double* sigma, const double* eta, const anova_opts* opts,
+                  hipStream_t stream);
+
+// y[:, r] = K x[:, r] for r < R (device pointers, column-major with leading dims).
+void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
+                    hipStream_t stream);
+
+void profile_begin(Plan& pl);
+int profile_end(Plan& pl, double* stage_ms, int nstage);  // returns passes measured
+
+}  // namespace anv

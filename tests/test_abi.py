@@ -1,0 +1,78 @@
+"""The C-ABI library loads on the CPU and exports every entry point that
+include/anova_nfft.h declares; option defaults match Table 1; argument checks
+that run before any device work return INVALID_ARG (no GPU needed)."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import paper_2312_00538_amd as lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "anova_nfft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lib.LIB_PATH):
+        from paper_2312_00538_amd import build
+        build.build(verbose=False)
+    return lib.load_library()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert len(names) >= 10
+    assert sorted(names) == sorted(lib.EXPORTED)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_defaults_follow_table1(L):
+    t = json.load(open(os.path.join(ROOT, "tests", "golden", "table1_parameters.json")))
+    o = lib.default_ipm_opts()
+    assert o.sigma_bar == t["barrier_reduction"]
+    assert o.gamma0 == t["step_to_boundary"]
+    assert o.mu0 == t["mu0"]
+    assert o.max_kry == t["max_krylov_iterations"]
+    assert o.tol_kry == t["krylov_tolerance"]
+    assert o.err_tol == t["cholesky_err_tol"]
+    assert o.tol_inf == t["ipm_tolerance"]
+    n = lib.default_opts()
+    assert (n.n_bw, n.oversample, n.cutoff_m, n.eps_b) == (32, 2, 4, 0.25)
+
+
+def test_invalid_arguments_are_rejected_before_device_work(L):
+    h = ctypes.c_void_p()
+    o = lib.default_opts()
+    import numpy as np
+    win = np.array([[0, 1, 2]], dtype=np.int32)
+    sig = np.array([1.0])
+    fake = ctypes.c_void_p(0x1000)
+    args = lambda N, d, ldx, w, P, s: (fake, N, d, ldx, w.ctypes.data_as(ctypes.c_void_p), P,
+                                       s.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(o), None,
+                                       ctypes.byref(h))
+    assert L.anova_plan_create(*args(0, 3, 3, win, 1, sig)) == lib.INVALID_ARG
+    assert L.anova_plan_create(*args(10, 3, 2, win, 1, sig)) == lib.INVALID_ARG
+    bad = np.array([[0, 0, 1]], dtype=np.int32)
+    assert L.anova_plan_create(*args(10, 3, 3, bad, 1, sig)) == lib.INVALID_ARG
+    assert b"repeated" in L.anova_last_error()
+    bad = np.array([[0, 5, -1]], dtype=np.int32)
+    assert L.anova_plan_create(*args(10, 3, 3, bad, 1, sig)) == lib.INVALID_ARG
+    empty = np.array([[-1, -1, -1]], dtype=np.int32)
+    assert L.anova_plan_create(*args(10, 3, 3, empty, 1, sig)) == lib.INVALID_ARG
+    assert L.anova_plan_create(*args(10, 3, 3, win, 1, np.array([0.0]))) == lib.INVALID_ARG
+    o.cutoff_m = 9
+    assert L.anova_plan_create(*args(10, 3, 3, win, 1, sig)) == lib.INVALID_ARG
+    o.cutoff_m = 4
+    o.version = 99
+    assert L.anova_plan_create(*args(10, 3, 3, win, 1, sig)) == lib.INVALID_ARG
+    assert L.anova_matvec(None, fake, 1, 10, fake, 10, None) == lib.INVALID_ARG
+    assert L.anova_plan_destroy(None) == lib.OK
