@@ -154,7 +154,8 @@ typedef struct {
     double  gamma0;      /* step-to-boundary factor (Algorithm 1: 0.99995)       */
     double  mu0;         /* initial barrier parameter (Algorithm 1: 1.0)         */
     int32_t rank;        /* low-rank factor rank k                               */
-    int32_t reserved;
+    int32_t mu_rule;     /* 0: sigma_it = 1 - (1 - sigma_bar) * (previous step);
+                            1: constant sigma_bar (Section 2 allows either)      */
     double  err_tol;     /* pivoted-Cholesky trace tolerance (Table 1: 1e-5)     */
     uint64_t seed;       /* Gaussian test matrix of the Nystrom method           */
 } anova_ipm_opts;
@@ -179,7 +180,7 @@ typedef struct {
 /* Fill `o` with the defaults: Table 1 values (max_ip = 50 raised to 100,
  * max_kry = 100, tol_kry = 1e-3, sigma_bar = 0.6, gamma0 = 0.99995,
  * mu0 = 1, err_tol = 1e-5), tol = 1e-6, tol_inf = 1e-1, precond = PCHOL,
- * rank = 200, seed = 0. */
+ * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0. */
 int anova_ipm_opts_default(anova_ipm_opts* o);
 
 /* Train: alpha (device, N FP64 out), lambda (host, 1 FP64 out; the bias of

@@ -162,11 +162,11 @@ def initial_point(y, C):
 
 
 def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0=0.99995,
-              mu0=1.0, record=False):
+              mu0=1.0, mu_rule="adaptive", record=False):
     """Algorithm 1 (Section 2) with the Newton system (eq. "Newton") solved by a
     dense LU solve of the (N+1) x (N+1) saddle-point matrix.
 
-    Per iteration: mu <- sigma_bar * mu; Theta = mu (1/alpha^2 + 1/(C-alpha)^2);
+    Per iteration: mu <- sigma_it * mu; Theta = mu (1/alpha^2 + 1/(C-alpha)^2);
     solve [[YKY + Theta, -y], [-y^T, 0]] [da; dl] =
           [e - YKY alpha + lambda y + mu/alpha - mu/(C-alpha); y^T alpha];
     step s = gamma0 * min(1, s_max) with s_max the largest step keeping
@@ -178,6 +178,12 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
     xi_lambda ratio keeps the IPM tolerance of Table 1 (1e-1): with a primal
     barrier Newton step the residual of the barrier terms at active bounds does
     not vanish as mu -> 0, so that ratio levels off well above 1e-6.
+
+    Barrier reduction (Section 2 allows a constant factor or one that changes
+    every iteration): mu_rule="constant" uses sigma_it = sigma_bar;
+    mu_rule="adaptive" uses sigma_it = 1 - (1 - sigma_bar) * s_prev with s_prev
+    the previous step length (s_prev = 1 before the first step), i.e. sigma_bar
+    after full steps and little reduction after steps cut short by the box.
     """
     y = np.asarray(y, dtype=np.float64)
     N = y.shape[0]
@@ -195,10 +201,14 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
     D, Pr, G = objectives_from_kya(kya, y, alpha, lam, C)
     it = 0
     hist = []
+    s_prev = 1.0
     while it < max_ip:
         if mu <= tol and xa / xa0 <= tol and xl / xl0 <= tol_inf and G <= tol:
             break
-        mu = sigma_bar * mu
+        if mu_rule == "constant":
+            mu = sigma_bar * mu
+        else:
+            mu = (1.0 - (1.0 - sigma_bar) * s_prev) * mu
         theta = mu * (1.0 / alpha ** 2 + 1.0 / (C - alpha) ** 2)
         r1 = 1.0 - YKY @ alpha + lam * y + mu / alpha - mu / (C - alpha)
         r2 = float(y @ alpha)
@@ -216,6 +226,7 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
         if pos.any():
             smax = min(smax, float(np.min((C - alpha[pos]) / da[pos])))
         s = gamma0 * min(1.0, smax)
+        s_prev = s
         alpha = alpha + s * da
         lam = lam + s * dl
         xa = abs(float(y @ alpha))

@@ -51,7 +51,7 @@ class IpmOpts(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("max_ip", ctypes.c_int32), ("max_kry", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("tol", ctypes.c_double), ("tol_inf", ctypes.c_double),
                 ("tol_kry", ctypes.c_double), ("sigma_bar", ctypes.c_double), ("gamma0", ctypes.c_double),
-                ("mu0", ctypes.c_double), ("rank", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("mu0", ctypes.c_double), ("rank", ctypes.c_int32), ("mu_rule", ctypes.c_int32),
                 ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 

@@ -30,6 +30,11 @@ __global__ void k_permute(const double* __restrict__ x, const int32_t* __restric
     vs[t] = x[perm[t]];
 }
 
+// One wavefront per work item. The loop is software-pipelined by one point:
+// the z weights, input value and base layer of the next point (wave-uniform,
+// scalar loads) and its per-lane x and y weights (vector loads) are requested
+// before the current point is accumulated. The inner loop uses no LDS, so the
+// scalar-load counter only ever waits for the point about to be used.
 template <int W, class WT>
 __global__ __launch_bounds__(64) void k_spread(const Segment* __restrict__ segs,
                                                const WinDev* __restrict__ wins,
@@ -50,9 +55,29 @@ __global__ __launch_bounds__(64) void k_spread(const Segment* __restrict__ segs,
 #pragma unroll
     for (int c = 0; c < W; ++c) acc[c] = WT(0);
     int zr = sg.z0;
-    for (int j = 0; j < sg.count; ++j) {
-        const int64_t g = base + j;
-        const int zj = zq[g];
+    int64_t g = base;
+    const int64_t gend = base + sg.count;
+    int nz = zq[g];
+    WT nv = WT(vs[g]);
+    WT nw[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
+    WT nwx = wts[g * (3 * W) + a], nwy = wts[g * (3 * W) + W + b];
+    for (; g < gend;) {
+        const int zj = nz;
+        const WT v = nv, wxa = nwx, wyb = nwy;
+        WT wz[W];
+#pragma unroll
+        for (int c = 0; c < W; ++c) wz[c] = nw[c];
+        ++g;
+        if (g < gend) {
+            nz = zq[g];
+            nv = WT(vs[g]);
+#pragma unroll
+            for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
+            nwx = wts[g * (3 * W) + a];
+            nwy = wts[g * (3 * W) + W + b];
+        }
         while (zr < zj) {  // layer zr is complete: no later point of the run reaches it
             if (active) out[(zr - sg.z0) * lanes + lane] = acc[0];
 #pragma unroll
@@ -60,10 +85,9 @@ __global__ __launch_bounds__(64) void k_spread(const Segment* __restrict__ segs,
             acc[W - 1] = WT(0);
             ++zr;
         }
-        const WT* w = wts + g * (3 * W);
-        const WT coef = WT(vs[g]) * w[a] * w[W + b];
+        const WT coef = v * wxa * wyb;
 #pragma unroll
-        for (int c = 0; c < W; ++c) acc[c] += coef * w[2 * W + c];
+        for (int c = 0; c < W; ++c) acc[c] += coef * wz[c];
     }
     if (active) {
 #pragma unroll
@@ -71,36 +95,36 @@ __global__ __launch_bounds__(64) void k_spread(const Segment* __restrict__ segs,
     }
 }
 
-// g[cell] = sum over the work items whose slabs cover the cell, in a fixed order
+// g[cell] = sum over the work items whose slabs cover the cell. One wavefront
+// per cell; lane (a, b) reads the partial sums that column (gx - a, gy - b)
+// wrote for its footprint position (a, b), and the lanes are combined by a
+// fixed butterfly, so the order of additions never changes.
 template <class WT>
-__global__ void k_fold(const Segment* __restrict__ segs, const WinDev* __restrict__ wins,
-                       const int2* __restrict__ fold, const WT* __restrict__ slab,
-                       int64_t grid_max, WT* __restrict__ grid) {
+__global__ __launch_bounds__(256) void k_fold(const WinDev* __restrict__ wins,
+                                              const int2* __restrict__ fold,
+                                              const int64_t* __restrict__ sbase,
+                                              const WT* __restrict__ slab, WT* __restrict__ grid) {
     const int l = blockIdx.y;
-    const WinDev wd = wins[l];
+    const WinDev& wd = wins[l];
     const int64_t cells = int64_t(wd.E[0]) * wd.E[1] * wd.E[2];
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t c = int64_t(blockIdx.x) * (blockDim.x / 64) + threadIdx.x / 64;
     if (c >= cells) return;
+    const int lane = threadIdx.x % 64;
     const int gz = int(c % wd.E[2]);
     const int gy = int((c / wd.E[2]) % wd.E[1]);
     const int gx = int(c / (int64_t(wd.E[2]) * wd.E[1]));
     double acc = 0.0;
-    for (int a = 0; a < wd.Wslot[0]; ++a) {
-        const int cx = gx - a;
-        if (cx < 0 || cx >= wd.nb[0]) continue;
-        for (int b = 0; b < wd.Wslot[1]; ++b) {
-            const int cy = gy - b;
-            if (cy < 0 || cy >= wd.nb[1]) continue;
-            const int64_t col = int64_t(cx) * wd.nb[1] + cy;
-            const int2 r = fold[wd.fold_off + col * wd.E[2] + gz];
-            const int lane = a * wd.Wslot[1] + b;
-            for (int s = r.x; s < r.y; ++s) {
-                const Segment sg = segs[s];
-                acc += double(slab[sg.off + int64_t(gz - sg.z0) * wd.lanes + lane]);
-            }
+    if (lane < wd.lanes) {
+        const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
+        const int cx = gx - a, cy = gy - b;
+        if (cx >= 0 && cx < wd.nb[0] && cy >= 0 && cy < wd.nb[1]) {
+            const int2 r = fold[wd.fold_off + (int64_t(cx) * wd.nb[1] + cy) * wd.E[2] + gz];
+            for (int s = r.x; s < r.y; ++s) acc += double(slab[sbase[s] + int64_t(gz) * wd.lanes + lane]);
         }
     }
-    grid[wd.grid_off + c] = WT(acc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) grid[wd.grid_off + c] = WT(acc);
 }
 
 // out = T_axis applied along one axis of every window grid (layout [x][y][z])
@@ -123,8 +147,11 @@ __global__ void k_conv_axis(const WinDev* __restrict__ wins, const double* __res
     out[wd.grid_off + c] = WT(acc);
 }
 
-constexpr int kBatch = 32;
-
+// One wavefront per work item. Lane (a, b) keeps the 2m grid values of its line
+// (cx + a, cy + b, zr .. zr + 2m - 1) in registers. Loads are pipelined one
+// point ahead as in the spread. Each point's per-lane partial product goes to
+// LDS and after every chunk of points the wave sums them per point in lane
+// order (one transposed reduction instead of a shuffle tree per point).
 template <int W, class WT>
 __global__ __launch_bounds__(64) void k_gather(const Segment* __restrict__ segs,
                                                const WinDev* __restrict__ wins,
@@ -132,7 +159,8 @@ __global__ __launch_bounds__(64) void k_gather(const Segment* __restrict__ segs,
                                                const WT* __restrict__ wts,
                                                const WT* __restrict__ h, int64_t N,
                                                double* __restrict__ fs) {
-    __shared__ double red[kBatch][65];
+    constexpr int CH = 32;
+    __shared__ double red[CH][65];
     const Segment sg = segs[blockIdx.x];
     const WinDev& wd = wins[sg.win];
     const int lanes = wd.lanes;
@@ -150,22 +178,41 @@ __global__ __launch_bounds__(64) void k_gather(const Segment* __restrict__ segs,
     int zr = sg.z0;
 #pragma unroll
     for (int c = 0; c < W; ++c) ring[c] = active ? hcol[zr + c] : WT(0);
-    for (int j0 = 0; j0 < sg.count; j0 += kBatch) {
-        const int nb = min(kBatch, sg.count - j0);
+    WT nxt = (active && zr + W < Ez) ? hcol[zr + W] : WT(0);
+    int64_t g = base;
+    const int64_t gend = base + sg.count;
+    int nz = zq[g];
+    WT nw[W];
+#pragma unroll
+    for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
+    WT nwx = wts[g * (3 * W) + a], nwy = wts[g * (3 * W) + W + b];
+    for (int j0 = 0; j0 < sg.count; j0 += CH) {
+        const int nb = min(CH, sg.count - j0);
         for (int jj = 0; jj < nb; ++jj) {
-            const int64_t g = base + j0 + jj;
-            const int zj = zq[g];
+            const int zj = nz;
+            const WT wxa = nwx, wyb = nwy;
+            WT wz[W];
+#pragma unroll
+            for (int c = 0; c < W; ++c) wz[c] = nw[c];
+            ++g;
+            if (g < gend) {
+                nz = zq[g];
+#pragma unroll
+                for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
+                nwx = wts[g * (3 * W) + a];
+                nwy = wts[g * (3 * W) + W + b];
+            }
             while (zr < zj) {
 #pragma unroll
                 for (int c = 0; c < W - 1; ++c) ring[c] = ring[c + 1];
+                ring[W - 1] = nxt;
                 ++zr;
-                ring[W - 1] = active ? hcol[zr + W - 1] : WT(0);
+                nxt = (active && zr + W < Ez) ? hcol[zr + W] : WT(0);
             }
-            const WT* w = wts + g * (3 * W);
             WT s = WT(0);
 #pragma unroll
-            for (int c = 0; c < W; ++c) s += w[2 * W + c] * ring[c];
-            red[jj][lane] = active ? double(s * w[a] * w[W + b]) : 0.0;
+            for (int c = 0; c < W; ++c) s += wz[c] * ring[c];
+            red[jj][lane] = active ? double(s * wxa * wyb) : 0.0;
         }
         __syncthreads();
         if (lane < nb) {
@@ -201,8 +248,8 @@ void run_matvec(Plan& pl, const double* x, double* y, WT* wts, WT* slab, WT* g, 
                        pl.zq.p, wts, pl.vs.p, N, slab);
     const dim3 gg(nblocks(pl.grid_max), unsigned(pl.P));
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_fold<WT>, gg, dim3(kThreads), 0, st, pl.segs.p, pl.wins_d.p, pl.fold.p,
-                       slab, pl.grid_max, g);
+    hipLaunchKernelGGL(k_fold<WT>, dim3(unsigned((pl.grid_max + 3) / 4), unsigned(pl.P)), dim3(256), 0,
+                       st, pl.wins_d.p, pl.fold.p, pl.sbase.p, slab, g);
     if (prof) pl.record_stage_event(st);
     hipLaunchKernelGGL(k_conv_axis<WT>, gg, dim3(kThreads), 0, st, pl.wins_d.p, pl.tmat.p, 0, g, ca);
     hipLaunchKernelGGL(k_conv_axis<WT>, gg, dim3(kThreads), 0, st, pl.wins_d.p, pl.tmat.p, 1, ca, cb);

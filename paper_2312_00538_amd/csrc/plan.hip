@@ -70,8 +70,7 @@ struct AxisMap {
 // fractional part t = nu - floor(nu) in [0, 1).
 __global__ void k_bin(const double* __restrict__ xw, int64_t N, int32_t P,
                       const AxisMap* __restrict__ amap, int32_t n_os, int32_t m,
-                      int32_t* __restrict__ q, double* __restrict__ tf,
-                      int32_t* __restrict__ qext) {
+                      int32_t* __restrict__ q, double* __restrict__ tf) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= N * P) return;
     int l = int(t / N);
@@ -89,8 +88,33 @@ __global__ void k_bin(const double* __restrict__ xw, int64_t N, int32_t P,
         }
         q[t * 3 + s] = qq;
         tf[t * 3 + s] = fr;
-        atomicMin(&qext[(l * 3 + s) * 2 + 0], qq);
-        atomicMax(&qext[(l * 3 + s) * 2 + 1], qq);
+    }
+}
+
+// per (window, slot): min and max base cell, reduced per block before one atomic
+__global__ void k_qext(const int32_t* __restrict__ q, int64_t N, int32_t* __restrict__ qext) {
+    __shared__ int smin[256], smax[256];
+    const int ls = blockIdx.y;  // window * 3 + slot
+    const int l = ls / 3, s = ls % 3;
+    int lo = INT32_MAX, hi = INT32_MIN;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += int64_t(gridDim.x) * blockDim.x) {
+        int v = q[(int64_t(l) * N + i) * 3 + s];
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) {
+            smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + k]);
+            smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + k]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMin(&qext[ls * 2 + 0], smin[0]);
+        atomicMax(&qext[ls * 2 + 1], smax[0]);
     }
 }
 
@@ -152,7 +176,7 @@ inline unsigned nblocks(int64_t n, int t = kThreads) { return unsigned((n + t - 
 }  // namespace
 
 int64_t Plan::device_bytes() const {
-    return int64_t(wins_d.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
+    return int64_t(wins_d.bytes() + sbase.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
                    wts32.bytes() + segs.bytes() + fold.bytes() + tmat.bytes() + xw.bytes() +
                    vs.bytes() + fs.bytes() + g64.bytes() + h64.bytes() + c64a.bytes() +
                    c64b.bytes() + g32.bytes() + h32.bytes() + c32a.bytes() + c32b.bytes() +
@@ -272,7 +296,10 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     }
     upload(qext, qext_h, st);
     hipLaunchKernelGGL(k_bin, dim3(nblocks(N * P)), dim3(kThreads), 0, st, pl->xw.p, N, P, amap_d.p,
-                       n_os, m, qbuf.p, tbuf.p, qext.p);
+                       n_os, m, qbuf.p, tbuf.p);
+    ANV_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_qext, dim3(unsigned(std::min<int64_t>(64, (N + 255) / 256)), unsigned(3 * P)),
+                       dim3(256), 0, st, qbuf.p, N, qext.p);
     ANV_HIP(hipGetLastError());
     ANV_HIP(hipMemcpyAsync(qext_h.data(), qext.p, qext.bytes(), hipMemcpyDeviceToHost, st));
     ANV_HIP(hipStreamSynchronize(st));
@@ -411,6 +438,10 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     pl->fold_total = int64_t(fold_h.size());
     upload(pl->segs, pl->segs_h, st);
     upload(pl->fold, fold_h, st);
+    std::vector<int64_t> sb_h(pl->segs_h.size());
+    for (size_t s = 0; s < sb_h.size(); ++s)
+        sb_h[s] = pl->segs_h[s].off - int64_t(pl->segs_h[s].z0) * pl->wins_h[pl->segs_h[s].win].lanes;
+    upload(pl->sbase, sb_h, st);
     upload(pl->wins_d, pl->wins_h, st);
 
     // 7. matvec scratch

@@ -31,6 +31,7 @@ struct Plan {
     std::vector<Segment> segs_h;
     DevBuf<Segment> segs;
     DevBuf<int2> fold;          // per (window, column, layer): covering segment range
+    DevBuf<int64_t> sbase;      // per segment: slab offset - z0 * lanes
     int64_t fold_total = 0;
     DevBuf<double> tmat;        // Toeplitz matrices, row-major E x E per (window, slot)
     int64_t tmat_total = 0;

@@ -1,17 +1,811 @@
-// (filled in below)
+// Low-rank kernel factors (Section 4), the preconditioned Krylov solve of the
+// Newton system (Sections 2 and 5) and the interior point method (Algorithm 1).
+//
+// All solver arithmetic is FP64 on the device. Reductions are deterministic:
+// every block folds its part in a fixed tree order and a single block then adds
+// the block partials in block order, so a solve is bitwise reproducible.
+// The host drives the iterations and reads back a few scalars per step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
 #include "solver.hpp"
 
 namespace anv {
 
-int ipm_solve(Plan&, const double*, double, const anova_ipm_opts&, double*, double*,
-              anova_ipm_stats*, hipStream_t) {
-    throw Error(ANOVA_INVALID_ARG, "svm_ipm_solve: not built yet");
+namespace {
+
+constexpr int kT = 256;        // threads per block of the vector kernels
+constexpr int kRedBlocks = 512; // blocks of the partial-sum reductions
+inline unsigned nblk(int64_t n, int t = kT) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
+
+// ------------------------------------------------------------------ reductions
+template <int NS>
+__device__ void block_sums(double (&v)[NS], double* __restrict__ out) {
+    __shared__ double sh[NS][kT];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) sh[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) out[blockIdx.x * NS + q] = sh[q][0];
+    }
 }
-int pivoted_cholesky(Plan&, int, double, double*, int64_t, int64_t*, hipStream_t) {
-    throw Error(ANOVA_INVALID_ARG, "pivoted Cholesky: not built yet");
+
+// fold block partials [nb][ns] in block order: out[q] = sum_b part[b][q]
+__global__ void k_fold_partials(const double* __restrict__ part, int nb, int ns, double* __restrict__ out) {
+    int q = threadIdx.x;
+    if (q >= ns) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b * ns + q];
+    out[q] = s;
 }
+
+// up to 4 dot products sum_i a_q[i] * b_q[i] over [0, n)
+struct DotArgs {
+    const double* a[4];
+    const double* b[4];
+};
+template <int NS>
+__global__ void k_dots(DotArgs d, int64_t n, double* __restrict__ part) {
+    double v[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) v[q] = 0.0;
+    for (int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) v[q] += d.a[q][i] * d.b[q][i];
+    }
+    block_sums<NS>(v, part);
+}
+
+// ------------------------------------------------------------------ kernel columns
+// col[i] = sum_l eta_l exp(-sum_a (x_ia - x_pa)^2 / sigma_l^2) - sum_{j<r} L_ij L_pj,
+// L[:, r] = col / sqrt(col_p), d -= L[:, r]^2. (Column form of Algorithm 2.)
+__global__ void k_pchol_column(const double* __restrict__ xw, int64_t N, int32_t P,
+                               const double* __restrict__ inv_s2, const double* __restrict__ eta,
+                               int64_t p, int r, double* __restrict__ L, double* __restrict__ dres,
+                               double pivval) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= N) return;
+    const double* xi = xw + i * P * 3;
+    const double* xp = xw + p * P * 3;
+    double kv = 0.0;
+    for (int l = 0; l < P; ++l) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double df = xi[3 * l + a] - xp[3 * l + a];
+            s += df * df;
+        }
+        kv += eta[l] * exp(-s * inv_s2[l]);
+    }
+    for (int j = 0; j < r; ++j) kv -= L[j * N + i] * L[j * N + p];
+    double lv = kv / sqrt(pivval);
+    L[int64_t(r) * N + i] = lv;
+    double dn = dres[i] - lv * lv;
+    dres[i] = (i == p) ? 0.0 : dn;
+}
+
+// residual diagonal of the pivot: K_pp - sum_j L_pj^2 (one thread)
+__global__ void k_pivot_value(const double* __restrict__ L, int64_t N, int64_t p, int r, double kpp,
+                              double* __restrict__ out) {
+    double v = kpp;
+    for (int j = 0; j < r; ++j) v -= L[j * N + p] * L[j * N + p];
+    out[0] = v;
+}
+
+// block partials of (max value, its lowest index, sum) of d
+__global__ void k_argmax_sum(const double* __restrict__ d, int64_t n, double* __restrict__ pval,
+                             int64_t* __restrict__ pidx, double* __restrict__ psum) {
+    __shared__ double sv[kT], ss[kT];
+    __shared__ int64_t si[kT];
+    double best = -INFINITY, sum = 0.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
+        double v = d[i];
+        sum += v;
+        if (v > best) {  // indices increase along the stride, so '>' keeps the lowest
+            best = v;
+            bi = i;
+        }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    ss[threadIdx.x] = sum;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            double v2 = sv[threadIdx.x + s];
+            int64_t i2 = si[threadIdx.x + s];
+            if (v2 > sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x])) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+            ss[threadIdx.x] += ss[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        pval[blockIdx.x] = sv[0];
+        pidx[blockIdx.x] = si[0];
+        psum[blockIdx.x] = ss[0];
+    }
+}
+
+__global__ void k_argmax_final(const double* __restrict__ pval, const int64_t* __restrict__ pidx,
+                               const double* __restrict__ psum, int nb, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double best = -INFINITY, sum = 0.0;
+    int64_t bi = INT64_MAX;
+    for (int b = 0; b < nb; ++b) {
+        if (pval[b] > best || (pval[b] == best && pidx[b] < bi)) {
+            best = pval[b];
+            bi = pidx[b];
+        }
+        sum += psum[b];
+    }
+    out[0] = best;
+    out[1] = double(bi);
+    out[2] = sum;
+}
+
+__global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// ------------------------------------------------------------------ low-rank products
+// w[j] = sum_i Z[j*N + i] * u[i] (block j, fixed-order block reduction)
+__global__ void k_gemv_t(const double* __restrict__ Z, int64_t N, const double* __restrict__ u,
+                         double* __restrict__ w) {
+    const int j = blockIdx.x;
+    const double* zc = Z + int64_t(j) * N;
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < N; i += kT) v[0] += zc[i] * u[i];
+    __shared__ double sh[kT];
+    sh[threadIdx.x] = v[0];
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) w[j] = sh[0];
+}
+
+// M = I + sum_i Z_i Z_i^T / theta_i (k x k, lower+upper), one block per (a, b) tile row
+// of 16 x 16 outputs; partial sums over row chunks folded in order.
+constexpr int kSy = 16;
+__global__ void k_syrk_partial(const double* __restrict__ Z, int64_t N, int k,
+                               const double* __restrict__ theta, int64_t chunk,
+                               double* __restrict__ part) {
+    // block: (tile a, tile b, chunk c); threads 16 x 16
+    const int ta = blockIdx.x, tb = blockIdx.y, c = blockIdx.z;
+    const int ia = ta * kSy + threadIdx.x / kSy, ib = tb * kSy + threadIdx.x % kSy;
+    __shared__ double za[64][kSy], zb[64][kSy], wt[64];
+    const int64_t i0 = int64_t(c) * chunk, i1 = std::min<int64_t>(N, i0 + chunk);
+    double acc = 0.0;
+    for (int64_t ib0 = i0; ib0 < i1; ib0 += 64) {
+        for (int e = threadIdx.x; e < 64 * kSy; e += kT) {
+            int rr = e / kSy, cc = e % kSy;
+            int64_t i = ib0 + rr;
+            int ca = ta * kSy + cc, cb = tb * kSy + cc;
+            za[rr][cc] = (i < i1 && ca < k) ? Z[int64_t(ca) * N + i] : 0.0;
+            zb[rr][cc] = (i < i1 && cb < k) ? Z[int64_t(cb) * N + i] : 0.0;
+        }
+        for (int e = threadIdx.x; e < 64; e += kT) {
+            int64_t i = ib0 + e;
+            wt[e] = (i < i1) ? 1.0 / theta[i] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int rr = 0; rr < 64; ++rr) acc += za[rr][threadIdx.x / kSy] * zb[rr][threadIdx.x % kSy] * wt[rr];
+        __syncthreads();
+    }
+    if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc;
+}
+
+__global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, double* __restrict__ M) {
+    int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (e >= int64_t(k) * k) return;
+    double s = (e / k == e % k) ? 1.0 : 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * k * k + e];
+    M[e] = s;
+}
+
+// in-place Cholesky of the k x k SPD matrix M (row-major, lower triangle used),
+// one block; status[0] = 0 ok, 1 = non-positive pivot
+__global__ void k_chol(double* __restrict__ M, int k, int* __restrict__ status) {
+    __shared__ double piv;
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (threadIdx.x == 0) {
+            double v = M[j * k + j];
+            if (!(v > 0.0)) {
+                bad = 1;
+                v = 1e-300;
+            }
+            piv = sqrt(v);
+            M[j * k + j] = piv;
+        }
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) M[i * k + j] /= piv;
+        __syncthreads();
+        // trailing update of the lower triangle, row by row
+        for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
+            int i = j + 1 + e / (k - j - 1), c = j + 1 + e % (k - j - 1);
+            if (c <= i) M[i * k + c] -= M[i * k + j] * M[c * k + j];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) status[0] = bad;
+}
+
+// t = (L L^T)^{-1} w with L the Cholesky factor in M (one block, in place on t)
+__global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double* __restrict__ w,
+                             double* __restrict__ t) {
+    extern __shared__ double sx[];
+    for (int i = threadIdx.x; i < k; i += blockDim.x) sx[i] = w[i];
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {  // forward: L z = w
+        if (threadIdx.x == 0) sx[j] /= Lm[j * k + j];
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) sx[i] -= Lm[i * k + j] * sx[j];
+        __syncthreads();
+    }
+    for (int j = k - 1; j >= 0; --j) {  // backward: L^T t = z
+        if (threadIdx.x == 0) sx[j] /= Lm[j * k + j];
+        __syncthreads();
+        for (int i = threadIdx.x; i < j; i += blockDim.x) sx[i] -= Lm[j * k + i] * sx[j];
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x) t[i] = sx[i];
+}
+
+// ------------------------------------------------------------------ IPM vector kernels
+// theta = mu (1/a^2 + 1/(C - a)^2)
+__global__ void k_theta(const double* __restrict__ a, int64_t N, double C, double mu,
+                        double* __restrict__ th) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= N) return;
+    double ai = a[i], bi = C - ai;
+    th[i] = mu * (1.0 / (ai * ai) + 1.0 / (bi * bi));
+}
+
+// u = y * a (the vector the kernel is applied to: K Y a)
+__global__ void k_mul(const double* __restrict__ y, const double* __restrict__ a, int64_t N,
+                      double* __restrict__ u) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) u[i] = y[i] * a[i];
+}
+
+// Newton right-hand side: r1 = e - y*kya + lam y + mu/a - mu/(C-a); r[N] = y^T a (host value)
+__global__ void k_rhs(const double* __restrict__ y, const double* __restrict__ a,
+                      const double* __restrict__ kya, int64_t N, double lam, double mu, double C,
+                      double r2, double* __restrict__ r) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) r[i] = 1.0 - y[i] * kya[i] + lam * y[i] + mu / a[i] - mu / (C - a[i]);
+    if (i == N) r[N] = r2;
+}
+
+// IPM statistics after a step: sums of [alpha, (y a) . kya, hinge, xi_lambda^2, y.a]
+__global__ void k_ipm_stats(const double* __restrict__ y, const double* __restrict__ a,
+                            const double* __restrict__ kya, int64_t N, double lam, double mu, double C,
+                            double* __restrict__ part) {
+    double v[5] = {0, 0, 0, 0, 0};
+    for (int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x; i < N; i += int64_t(gridDim.x) * kT) {
+        double yi = y[i], ai = a[i], ki = kya[i];
+        v[0] += ai;
+        v[1] += yi * ai * ki;
+        double m = 1.0 - yi * (ki - lam);
+        v[2] += m > 0.0 ? m : 0.0;
+        double xl = 1.0 - yi * ki + lam * yi + mu / ai - mu / (C - ai);
+        v[3] += xl * xl;
+        v[4] += yi * ai;
+    }
+    block_sums<5>(v, part);
+}
+
+// largest step in (0, inf] keeping 0 < a + s da < C: block partial minima
+__global__ void k_step_partial(const double* __restrict__ a, const double* __restrict__ da, int64_t N,
+                               double C, double* __restrict__ part) {
+    __shared__ double sh[kT];
+    double m = INFINITY;
+    for (int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x; i < N; i += int64_t(gridDim.x) * kT) {
+        double d = da[i];
+        if (d < 0.0) m = fmin(m, -a[i] / d);
+        else if (d > 0.0) m = fmin(m, (C - a[i]) / d);
+    }
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_min_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double m = INFINITY;
+    for (int b = 0; b < nb; ++b) m = fmin(m, part[b]);
+    out[0] = m;
+}
+
+__global__ void k_step(double* __restrict__ a, const double* __restrict__ da, int64_t N, double s) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) a[i] += s * da[i];
+}
+
+// ------------------------------------------------------------------ Newton operator, MINRES
+// p = (A z) * sc - cprev * rprev, with A = [[Y K Y + Theta, -y], [-y^T, 0]] and
+// kyz = K (y * z[0:N]) already computed; p[N] gets -y^T z[0:N] * sc - cprev*rprev[N]
+// from the host-provided dot value.
+__global__ void k_newton_out(const double* __restrict__ y, const double* __restrict__ th,
+                             const double* __restrict__ z, const double* __restrict__ kyz, int64_t N,
+                             double sc, double cprev, const double* __restrict__ rprev,
+                             double lastv, double* __restrict__ p) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) {
+        double v = y[i] * kyz[i] + th[i] * z[i] - y[i] * z[N];
+        p[i] = v * sc - cprev * rprev[i];
+    } else if (i == N) {
+        p[N] = lastv * sc - cprev * rprev[N];
+    }
+}
+
+__global__ void k_axpy(double* __restrict__ x, const double* __restrict__ v, int64_t n, double s) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) x[i] += s * v[i];
+}
+
+// d_new = (z / beta - e * d2 - dl * d1) / gam; x += phi * d_new; rotates d2 <- d1 <- d_new
+__global__ void k_minres_update(const double* __restrict__ z, int64_t n, double inv_beta, double e,
+                                double dl, double inv_gam, double phi, double* __restrict__ d1,
+                                double* __restrict__ d2, double* __restrict__ x) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= n) return;
+    double dn = (z[i] * inv_beta - e * d2[i] - dl * d1[i]) * inv_gam;
+    d2[i] = d1[i];
+    d1[i] = dn;
+    x[i] += phi * dn;
+}
+
+// Woodbury apply, first half: u = y * r / theta (written to tmp)
+__global__ void k_wb_in(const double* __restrict__ y, const double* __restrict__ th,
+                        const double* __restrict__ r, int64_t N, double* __restrict__ u) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) u[i] = y[i] * r[i] / th[i];
+}
+
+// second half: out = r / theta - (y / theta) * (Z t); out[N] = r[N] / s
+__global__ void k_wb_out(const double* __restrict__ y, const double* __restrict__ th,
+                         const double* __restrict__ r, const double* __restrict__ Z, int64_t N, int k,
+                         const double* __restrict__ t, double inv_s, int has_last,
+                         double* __restrict__ out) {
+    __shared__ double ts[1024];
+    for (int j = threadIdx.x; j < k; j += kT) ts[j] = t[j];
+    __syncthreads();
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) {
+        double zt = 0.0;
+        for (int j = 0; j < k; ++j) zt += Z[int64_t(j) * N + i] * ts[j];
+        double ti = 1.0 / th[i];
+        out[i] = r[i] * ti - y[i] * ti * zt;
+    } else if (i == N && has_last) {
+        out[N] = r[N] * inv_s;
+    }
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) b[i] = a[i];
+}
+
+// ------------------------------------------------------------------ host helpers
+struct Reducer {
+    DevBuf<double> part, out;
+    double* host = nullptr;
+    Reducer() {
+        part.alloc(size_t(kRedBlocks) * 8);
+        out.alloc(8);
+        ANV_HIP(hipHostMalloc(&host, 8 * sizeof(double)));
+    }
+    ~Reducer() {
+        if (host) (void)hipHostFree(host);
+    }
+    unsigned blocks(int64_t n) const { return unsigned(std::min<int64_t>(kRedBlocks, nblk(n))); }
+    // sums of NS dot products of length n, read back to host (synchronises)
+    template <int NS>
+    const double* dots(const DotArgs& d, int64_t n, hipStream_t st) {
+        unsigned nb = blocks(n);
+        hipLaunchKernelGGL(k_dots<NS>, dim3(nb), dim3(kT), 0, st, d, n, part.p);
+        hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(64), 0, st, part.p, int(nb), NS, out.p);
+        ANV_HIP(hipMemcpyAsync(host, out.p, NS * sizeof(double), hipMemcpyDeviceToHost, st));
+        ANV_HIP(hipStreamSynchronize(st));
+        return host;
+    }
+    double dot(const double* a, const double* b, int64_t n, hipStream_t st) {
+        DotArgs d{};
+        d.a[0] = a;
+        d.b[0] = b;
+        return dots<1>(d, n, st)[0];
+    }
+};
+
+struct Workspace {
+    int64_t N = 0;
+    int k = 0;
+    DevBuf<double> Z;                     // N x k column-major low-rank factor Z^T
+    DevBuf<double> M, Mpart, w, t;        // capacitance and its factor
+    DevBuf<int> status;
+    DevBuf<double> tmp, kyz;              // N
+    int nchunk = 0;
+    int64_t chunk = 0;
+};
+
+// kernel matvec of one vector (device pointers, length N)
+void kmv(Plan& pl, const double* x, double* y, hipStream_t st) { enqueue_matvec(pl, x, 1, pl.N, y, pl.N, st); }
+
+// A_hat^{-1} applied to r (first N entries); out[N] = r[N]/s when has_last
+void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, const double* r,
+                    double s, bool has_last, double* out, hipStream_t st) {
+    const int64_t N = pl.N;
+    if (ws.k > 0) {
+        hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
+        hipLaunchKernelGGL(k_gemv_t, dim3(ws.k), dim3(kT), 0, st, ws.Z.p, N, ws.tmp.p, ws.w.p);
+        hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.w.p,
+                           ws.t.p);
+    }
+    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z.p, N, ws.k, ws.t.p,
+                       1.0 / s, has_last ? 1 : 0, out);
+}
+
+void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t st) {
+    if (ws.k == 0) return;
+    const int k = ws.k;
+    const int tiles = (k + kSy - 1) / kSy;
+    hipLaunchKernelGGL(k_syrk_partial, dim3(tiles, tiles, ws.nchunk), dim3(kT), 0, st, ws.Z.p, pl.N, k, th,
+                       ws.chunk, ws.Mpart.p);
+    hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k,
+                       ws.M.p);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, ws.M.p, k, ws.status.p);
+    int bad = 0;
+    ANV_HIP(hipMemcpyAsync(&bad, ws.status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    ANV_HIP(hipStreamSynchronize(st));
+    if (bad) throw Error(ANOVA_NUMERICAL, "capacitance matrix is not positive definite");
+}
+
+void setup_factor_storage(Workspace& ws, int64_t N, int k) {
+    ws.N = N;
+    ws.k = k;
+    if (k > 0) {
+        ws.M.alloc(size_t(k) * k);
+        ws.w.alloc(k);
+        ws.t.alloc(k);
+        ws.status.alloc(1);
+        ws.chunk = 8192;
+        ws.nchunk = int((N + ws.chunk - 1) / ws.chunk);
+        ws.nchunk = std::min(ws.nchunk, 256);
+        ws.chunk = (N + ws.nchunk - 1) / ws.nchunk;
+        ws.Mpart.alloc(size_t(ws.nchunk) * k * k);
+    }
+    ws.tmp.alloc(N + 1);
+    ws.kyz.alloc(N + 1);
+}
+
+// greedy pivoted Cholesky into a column-major N x ldl buffer; returns rank
+int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st) {
+    const int64_t N = pl.N;
+    const int P = pl.P;
+    ANV_CHECK(ldl == N, "internal: pivoted Cholesky storage must have ldl == N");
+    std::vector<double> inv_s2(P), eta(P);
+    double kpp = 0.0;
+    for (int l = 0; l < P; ++l) {
+        inv_s2[l] = 1.0 / (pl.sigma[l] * pl.sigma[l]);
+        eta[l] = pl.eta[l];
+        kpp += eta[l];
+    }
+    ANV_CHECK(kpp > 0.0, "pivoted Cholesky needs a positive kernel diagonal (sum of eta > 0)");
+    DevBuf<double> is2, et, dres, pv, ps, fin;
+    DevBuf<int64_t> pi;
+    is2.alloc(P);
+    et.alloc(P);
+    ANV_HIP(hipMemcpyAsync(is2.p, inv_s2.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+    ANV_HIP(hipMemcpyAsync(et.p, eta.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+    dres.alloc(N);
+    hipLaunchKernelGGL(k_fill, dim3(nblk(N)), dim3(kT), 0, st, dres.p, N, kpp);
+    const unsigned nb = unsigned(std::min<int64_t>(kRedBlocks, nblk(N)));
+    pv.alloc(nb);
+    ps.alloc(nb);
+    pi.alloc(nb);
+    fin.alloc(4);
+    double* hfin = nullptr;
+    ANV_HIP(hipHostMalloc(&hfin, 4 * sizeof(double)));
+    const double trace0 = kpp * double(N);
+    int r = 0;
+    try {
+        for (; r < rank; ++r) {
+            hipLaunchKernelGGL(k_argmax_sum, dim3(nb), dim3(kT), 0, st, dres.p, N, pv.p, pi.p, ps.p);
+            hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, pv.p, pi.p, ps.p, int(nb), fin.p);
+            ANV_HIP(hipMemcpyAsync(hfin, fin.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+            ANV_HIP(hipStreamSynchronize(st));
+            const double best = hfin[0], rest = hfin[2];
+            const int64_t p = int64_t(hfin[1]);
+            if (!(best > 0.0)) break;
+            if (err_tol > 0.0 && rest <= err_tol * trace0) break;
+            hipLaunchKernelGGL(k_pivot_value, dim3(1), dim3(1), 0, st, L, N, p, r, kpp, fin.p + 3);
+            ANV_HIP(hipMemcpyAsync(hfin + 3, fin.p + 3, sizeof(double), hipMemcpyDeviceToHost, st));
+            ANV_HIP(hipStreamSynchronize(st));
+            const double pivval = hfin[3];
+            if (!(pivval > 0.0)) break;
+            hipLaunchKernelGGL(k_pchol_column, dim3(nblk(N)), dim3(kT), 0, st, pl.xw.p, N, P, is2.p, et.p, p,
+                               r, L, dres.p, pivval);
+            ANV_HIP(hipGetLastError());
+            piv[r] = p;
+        }
+    } catch (...) {
+        (void)hipHostFree(hfin);
+        throw;
+    }
+    (void)hipHostFree(hfin);
+    ANV_HIP(hipStreamSynchronize(st));
+    return r;
+}
+
+}  // namespace
+
+int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st) {
+    if (ldl == pl.N) return pchol_into(pl, rank, err_tol, L, ldl, piv, st);
+    DevBuf<double> tmp;
+    tmp.alloc(size_t(pl.N) * rank);
+    int r = pchol_into(pl, rank, err_tol, tmp.p, pl.N, piv, st);
+    if (r > 0)
+        ANV_HIP(hipMemcpy2DAsync(L, ldl * sizeof(double), tmp.p, pl.N * sizeof(double), pl.N * sizeof(double), r,
+                                 hipMemcpyDeviceToDevice, st));
+    ANV_HIP(hipStreamSynchronize(st));
+    return r;
+}
+
 void nystrom_factor(Plan&, const double*, int, int64_t, double*, int64_t, hipStream_t) {
     throw Error(ANOVA_INVALID_ARG, "Nystrom: not built yet");
+}
+
+// ------------------------------------------------------------------ Algorithm 1
+int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o, double* alpha,
+              double* lambda_out, anova_ipm_stats* stats, hipStream_t st) {
+    using clk = std::chrono::steady_clock;
+    const auto t_start = clk::now();
+    const int64_t N = pl.N;
+    ANV_CHECK(labels && alpha && lambda_out, "NULL argument");
+    ANV_CHECK(std::isfinite(C) && C > 0.0, "C must be > 0");
+    ANV_CHECK(o.max_ip >= 1 && o.max_kry >= 1, "iteration caps must be >= 1");
+    ANV_CHECK(o.sigma_bar > 0.0 && o.sigma_bar < 1.0, "sigma_bar must be in (0, 1)");
+    ANV_CHECK(o.gamma0 > 0.0 && o.gamma0 < 1.0, "gamma0 must be in (0, 1)");
+    ANV_CHECK(o.mu0 > 0.0 && o.tol > 0.0 && o.tol_inf > 0.0 && o.tol_kry > 0.0, "tolerances must be > 0");
+    ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
+    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
+                  o.precond == ANOVA_PRECOND_NYSTROM,
+              "unknown preconditioner");
+    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
+              "rank must be in [1, min(N, 1024)]");
+
+    // labels: must be +-1 with both classes present
+    std::vector<double> yh(N);
+    ANV_HIP(hipMemcpyAsync(yh.data(), labels, N * sizeof(double), hipMemcpyDeviceToHost, st));
+    ANV_HIP(hipStreamSynchronize(st));
+    double ysum = 0.0;
+    int64_t npos = 0;
+    for (double v : yh) {
+        ANV_CHECK(v == 1.0 || v == -1.0, "labels must be +1 or -1");
+        ysum += v;
+        npos += v > 0;
+    }
+    ANV_CHECK(npos > 0 && npos < N, "both classes must be present");
+
+    Reducer red;
+    Workspace ws;
+    std::vector<int64_t> piv;
+    int rank_used = 0;
+    const auto t_setup0 = clk::now();
+    if (o.precond == ANOVA_PRECOND_PCHOL) {
+        ws.Z.alloc(size_t(N) * o.rank);
+        piv.resize(o.rank);
+        rank_used = pchol_into(pl, o.rank, o.err_tol, ws.Z.p, N, piv.data(), st);
+        setup_factor_storage(ws, N, rank_used);
+    } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
+        throw Error(ANOVA_INVALID_ARG, "Nystrom preconditioner: not built yet");
+    } else {
+        setup_factor_storage(ws, N, 0);
+    }
+    const double t_setup_ms = std::chrono::duration<double, std::milli>(clk::now() - t_setup0).count();
+
+    // state
+    DevBuf<double> ya, kya, th, rhs, sol, xk, rprev, rcur, zcur, zold, pv, d1, d2, ytmp;
+    const int64_t n1 = N + 1;
+    for (auto* b : {&ya, &kya, &th, &ytmp}) b->alloc(N);
+    for (auto* b : {&rhs, &sol, &xk, &rprev, &rcur, &zcur, &zold, &pv, &d1, &d2}) b->alloc(n1);
+    // initial point: alpha_i = C(2 + y_i)/4 if sum(y) >= 0 else C(2 - y_i)/4; lambda = 0
+    {
+        std::vector<double> a0(N);
+        for (int64_t i = 0; i < N; ++i) a0[i] = (ysum >= 0.0) ? C * (2.0 + yh[i]) / 4.0 : C * (2.0 - yh[i]) / 4.0;
+        ANV_HIP(hipMemcpyAsync(alpha, a0.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
+    }
+    double lam = 0.0, mu = o.mu0;
+    int matvecs = 0;
+
+    DevBuf<double> spart, sout;
+    spart.alloc(size_t(kRedBlocks) * 5);
+    sout.alloc(8);
+    double* sh = nullptr;
+    ANV_HIP(hipHostMalloc(&sh, 8 * sizeof(double)));
+    struct HostFree {
+        double* p;
+        ~HostFree() { if (p) (void)hipHostFree(p); }
+    } sh_guard{sh};
+    const unsigned rb = red.blocks(N);
+
+    auto eval_stats = [&](double& xa, double& xl, double& D, double& Pr, double& G) {
+        hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, N, ya.p);
+        kmv(pl, ya.p, kya.p, st);
+        ++matvecs;
+        hipLaunchKernelGGL(k_ipm_stats, dim3(rb), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, spart.p);
+        hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(64), 0, st, spart.p, int(rb), 5, sout.p);
+        ANV_HIP(hipMemcpyAsync(sh, sout.p, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
+        ANV_HIP(hipStreamSynchronize(st));
+        const double quad = sh[1];
+        D = sh[0] - 0.5 * quad;
+        Pr = 0.5 * quad + C * sh[2];
+        G = (Pr - D) / (1.0 + std::fabs(Pr));
+        xl = std::sqrt(sh[3]);
+        xa = std::fabs(sh[4]);
+    };
+
+    double xa0, xl0, D, Pr, G;
+    eval_stats(xa0, xl0, D, Pr, G);
+    double xa = xa0, xl = xl0;
+    ANV_CHECK(xa0 > 0.0 && xl0 > 0.0, "initial infeasibilities vanish");
+    int it = 0, kry_total = 0, kry_max = 0;
+    int status = ANOVA_NOT_CONVERGED;
+    double s_prev = 1.0;
+    for (;;) {
+        if (!(std::isfinite(mu) && std::isfinite(G) && std::isfinite(xl))) {
+            status = ANOVA_NUMERICAL;
+            break;
+        }
+        if (mu <= o.tol && xa / xa0 <= o.tol && xl / xl0 <= o.tol_inf && G <= o.tol) {
+            status = ANOVA_OK;
+            break;
+        }
+        if (it >= o.max_ip) break;
+        // Section 2: a constant reduction factor, or one that changes every iteration;
+        // the default scales the reduction by the previous step length
+        mu *= (o.mu_rule == 1) ? o.sigma_bar : 1.0 - (1.0 - o.sigma_bar) * s_prev;
+        hipLaunchKernelGGL(k_theta, dim3(nblk(N)), dim3(kT), 0, st, alpha, N, C, mu, th.p);
+        const double r2 = red.dot(labels, alpha, N, st);
+        hipLaunchKernelGGL(k_rhs, dim3(nblk(n1)), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, r2,
+                           rhs.p);
+        // preconditioner for this iteration: diag(A_hat, s), s = y^T A_hat^{-1} y
+        double s_last = 1.0;
+        const bool prec = o.precond != ANOVA_PRECOND_NONE;
+        if (prec) {
+            refresh_capacitance(pl, ws, th.p, st);
+            woodbury_apply(pl, ws, labels, th.p, labels, 1.0, false, ytmp.p, st);
+            s_last = red.dot(labels, ytmp.p, N, st);
+            if (!(s_last > 0.0)) {
+                status = ANOVA_NUMERICAL;
+                break;
+            }
+        }
+        auto precond = [&](const double* r, double* out) {
+            if (prec)
+                woodbury_apply(pl, ws, labels, th.p, r, s_last, true, out, st);
+            else
+                hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, r, out, n1);
+        };
+        // ---- preconditioned MINRES on A sol = rhs (Lanczos in the M-inner product + Givens QR)
+        const double rtol = std::max(1e-10, std::min(o.tol_kry, 0.1 * G));
+        const int kcap = prec ? o.max_kry : std::max<int64_t>(o.max_kry, 2 * n1);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, sol.p, n1, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, rprev.p, n1, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d1.p, n1, 0.0);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d2.p, n1, 0.0);
+        hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, rhs.p, rcur.p, n1);
+        precond(rcur.p, zcur.p);
+        double beta = std::sqrt(std::max(0.0, red.dot(rcur.p, zcur.p, n1, st)));
+        const double beta1 = beta;
+        double beta_prev = 0.0, c = -1.0, s = 0.0, dbar = 0.0, eps_next = 0.0, phibar = beta1;
+        int kit = 0;
+        double* rp = rprev.p;
+        double* rc = rcur.p;
+        double* zc = zcur.p;
+        double* zo = zold.p;
+        double* pp = pv.p;
+        if (beta1 > 0.0) {
+            while (kit < kcap) {
+                ++kit;
+                // p = A (z / beta) - (beta / beta_prev) r_prev
+                hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+                kmv(pl, ws.tmp.p, ws.kyz.p, st);
+                ++matvecs;
+                const double ytz = red.dot(labels, zc, N, st);
+                const double cprev = kit > 1 ? beta / beta_prev : 0.0;
+                hipLaunchKernelGGL(k_newton_out, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N,
+                                   1.0 / beta, cprev, rp, -ytz, pp);
+                const double a = red.dot(zc, pp, n1, st) / beta;
+                hipLaunchKernelGGL(k_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, -a / beta);
+                // rotate r_prev <- r_cur <- p; z_old <- z_cur; z_cur <- M^{-1} r_cur
+                std::swap(rp, rc);
+                std::swap(rc, pp);
+                std::swap(zo, zc);
+                precond(rc, zc);
+                beta_prev = beta;
+                beta = std::sqrt(std::max(0.0, red.dot(rc, zc, n1, st)));
+                const double eps_cur = eps_next;
+                const double delta = c * dbar + s * a;
+                const double gbar = s * dbar - c * a;
+                eps_next = s * beta;
+                dbar = -c * beta;
+                double gam = std::hypot(gbar, beta);
+                if (gam == 0.0) gam = 1e-300;
+                c = gbar / gam;
+                s = beta / gam;
+                const double phi = c * phibar;
+                phibar = s * phibar;
+                hipLaunchKernelGGL(k_minres_update, dim3(nblk(n1)), dim3(kT), 0, st, zo, n1, 1.0 / beta_prev,
+                                   eps_cur, delta, 1.0 / gam, phi, d1.p, d2.p, sol.p);
+                if (!(phibar > rtol * beta1) || !(beta > 0.0)) break;
+            }
+        }
+        kry_total += kit;
+        kry_max = std::max(kry_max, kit);
+        // ---- step to the boundary (Algorithm 1): s = gamma0 * min(1, s_max), same for lambda
+        hipLaunchKernelGGL(k_step_partial, dim3(rb), dim3(kT), 0, st, alpha, sol.p, N, C, spart.p);
+        hipLaunchKernelGGL(k_min_final, dim3(1), dim3(64), 0, st, spart.p, int(rb), sout.p);
+        double smax_dl[2];
+        ANV_HIP(hipMemcpyAsync(&smax_dl[0], sout.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        ANV_HIP(hipMemcpyAsync(&smax_dl[1], sol.p + N, sizeof(double), hipMemcpyDeviceToHost, st));
+        ANV_HIP(hipStreamSynchronize(st));
+        const double step = o.gamma0 * std::min(1.0, smax_dl[0]);
+        s_prev = step;
+        hipLaunchKernelGGL(k_step, dim3(nblk(N)), dim3(kT), 0, st, alpha, sol.p, N, step);
+        lam += step * smax_dl[1];
+        ++it;
+        eval_stats(xa, xl, D, Pr, G);
+    }
+    ANV_HIP(hipStreamSynchronize(st));
+    *lambda_out = lam;
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->ip_iters = it;
+        stats->kry_iters_total = kry_total;
+        stats->kry_iters_max = kry_max;
+        stats->rank_used = rank_used;
+        stats->status = status;
+        stats->matvecs = matvecs;
+        stats->mu = mu;
+        stats->rel_gap = G;
+        stats->dual_obj = D;
+        stats->primal_obj = Pr;
+        stats->xi_alpha_rel = xa / xa0;
+        stats->xi_lambda_rel = xl / xl0;
+        stats->t_setup_ms = t_setup_ms;
+        stats->t_solve_ms = std::chrono::duration<double, std::milli>(clk::now() - t_start).count();
+    }
+    if (status == ANOVA_NUMERICAL) throw Error(ANOVA_NUMERICAL, "IPM produced NaN/Inf or lost positive definiteness");
+    if (status == ANOVA_NOT_CONVERGED) set_last_error("IPM iteration cap reached");
+    return status;
 }
 
 }  // namespace anv

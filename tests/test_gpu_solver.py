@@ -1,0 +1,131 @@
+"""GPU parity of the low-rank factor (Algorithm 2, Section 4) and of the
+interior point solve (Algorithm 1, Sections 2 and 5) against the FP64 oracle.
+
+IPM bar: the GPU solve stops with its own relative duality gap <= 1e-6; its
+alpha, evaluated by the oracle in the EXACT QP (dense kernel), has
+G_exact <= 1e-6 and a dual objective within 1e-6 (relative) of the oracle's
+dense-KKT solve. alpha itself is not unique in general, so decision values are
+compared with a looser bound and lambda only through them."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import device, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def _plan(p, dev, **kw):
+    import paper_2312_00538_amd as lib
+    return lib.Plan(to_dev(p.X, dev), p.windows, p.sigma, **kw)
+
+
+def test_pivoted_cholesky_matches_algorithm2(dev):
+    p = workloads.gaussian_mixture(seed=3, N=300, d=9, sigma=0.3)
+    pl = _plan(p, dev)
+    L, piv = pl.pivoted_cholesky(40)
+    L = L.cpu().numpy()
+    K = oracle.anova_dense(p.X, p.windows, p.sigma)
+    Lo, pivo = oracle.pivoted_cholesky(K, 40)
+    print("pivots gpu", piv[:10], "oracle", pivo[:10])
+    assert list(piv) == list(pivo)
+    assert np.allclose(L, Lo, rtol=1e-9, atol=1e-11)
+
+
+def test_pivoted_cholesky_error_tolerance(dev):
+    p = workloads.small_plain(seed=2, N=400)
+    pl = _plan(p, dev)
+    L, piv = pl.pivoted_cholesky(200, err_tol=1e-5)
+    K = oracle.anova_dense(p.X, p.windows, p.sigma)
+    Lo, pivo = oracle.pivoted_cholesky(K, 200, err_tol=1e-5)
+    print("rank gpu", L.shape[1], "oracle", Lo.shape[1])
+    assert L.shape[1] == Lo.shape[1] < 200
+    L = L.cpu().numpy()
+    assert np.trace(K - L @ L.T) <= 1e-5 * np.trace(K) * (1 + 1e-9)
+
+
+def _check_solve(p, C, dev, rank=200, tol_d=1e-6, **kw):
+    import paper_2312_00538_amd as lib
+    pl = _plan(p, dev)
+    y = to_dev(p.labels, dev)
+    alpha, lam, st = pl.solve(y, C, rank=rank, **kw)
+    a = alpha.cpu().numpy()
+    print("stats", st)
+    assert st["status"] == 0 and st["rel_gap"] <= 1e-6
+    assert (a > 0).all() and (a < C).all()
+    K = oracle.anova_dense(p.X, p.windows, p.sigma)
+    ref = oracle.ipm_dense(K, p.labels, C)
+    assert ref["converged"]
+    kya = K @ (p.labels * a)
+    D, Pr, G = oracle.objectives_from_kya(kya, p.labels, a, lam, C)
+    print(f"G_exact {G:.3e}  D {D:.12g}  oracle D {ref['D']:.12g}  rel {abs(D - ref['D']) / abs(ref['D']):.2e}")
+    assert G <= 1e-6
+    assert abs(D - ref["D"]) <= tol_d * abs(ref["D"])
+    f_gpu = kya - lam
+    f_ref = K @ (p.labels * ref["alpha"]) - ref["lam"]
+    assert np.max(np.abs(f_gpu - f_ref)) <= 1e-3 * max(1.0, np.max(np.abs(f_ref)))
+    return a, lam, st
+
+
+def test_ipm_small_plain_parity(dev):
+    p = workloads.small_plain(seed=0, N=2000, d=9)
+    _check_solve(p, 1.0, dev)
+
+
+@pytest.mark.parametrize("seed,N,C,sigma", [(1, 600, 10.0, 0.8), (2, 999, 0.5, 0.4)])
+def test_ipm_mixture_parity(dev, seed, N, C, sigma):
+    p = workloads.gaussian_mixture(seed=seed, N=N, d=20, noise=0.1, sigma=sigma, C=C)
+    _check_solve(p, C, dev)
+
+
+def test_ipm_two_points_closed_form(dev):
+    import paper_2312_00538_amd as lib
+    X = np.array([[0.0, 0.1, 0.0], [0.1, -0.05, 0.2]])
+    y = np.array([1.0, -1.0])
+    pl = lib.Plan(to_dev(X, dev), np.array([[0, 1, 2]]), 0.3)
+    alpha, lam, st = pl.solve(to_dev(y, dev), 100.0, rank=2)
+    K = oracle.anova_dense(X, np.array([[0, 1, 2]]), 0.3)
+    a = 1.0 / (K[0, 0] - K[0, 1])
+    assert np.allclose(alpha.cpu().numpy(), a, rtol=1e-4)
+    assert abs(lam) <= 1e-4
+
+
+def test_ipm_deterministic(dev):
+    p = workloads.small_plain(seed=5, N=700)
+    pl = _plan(p, dev)
+    y = to_dev(p.labels, dev)
+    a1, l1, _ = pl.solve(y, 1.0, rank=100)
+    a2, l2, _ = pl.solve(y, 1.0, rank=100)
+    assert np.array_equal(a1.cpu().numpy(), a2.cpu().numpy()) and l1 == l2
+
+
+def test_ipm_unpreconditioned_first_steps(dev):
+    import paper_2312_00538_amd as lib
+    p = workloads.small_plain(seed=0, N=300)
+    pl = _plan(p, dev)
+    alpha, lam, st = pl.solve(to_dev(p.labels, dev), 1.0, precond=lib.PRECOND_NONE, max_ip=3,
+                              allow_not_converged=True)
+    print(st)
+    assert st["status"] == lib.NOT_CONVERGED and st["ip_iters"] == 3
+    assert np.isfinite(alpha.cpu().numpy()).all()
+
+
+def test_ipm_rejects_bad_labels(dev):
+    import paper_2312_00538_amd as lib
+    p = workloads.small_plain(seed=0, N=50)
+    pl = _plan(p, dev)
+    with pytest.raises(lib.AnovaError) as e:
+        pl.solve(to_dev(np.ones(50), dev), 1.0)
+    assert e.value.status == lib.INVALID_ARG
+    bad = p.labels.copy()
+    bad[3] = 0.5
+    with pytest.raises(lib.AnovaError):
+        pl.solve(to_dev(bad, dev), 1.0)
+    with pytest.raises(lib.AnovaError):
+        pl.solve(to_dev(p.labels, dev), -1.0)
