@@ -41,7 +41,42 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-rows", type=int, default=128)
+    ap.add_argument("--ipm-small-solves", type=int, default=20)
+    ap.add_argument("--ipm-full-solves", type=int, default=5)
+    ap.add_argument("--ipm-full-N", type=int, default=500_000)
     return ap.parse_args()
+
+
+def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
+    """Wall-clock per svm_ipm_solve call (API call to return, preconditioner
+    build included) over seeds 0..n-1; plan creation timed separately."""
+    t_solve, t_plan, stats = [], [], []
+    for seed in range(n):
+        p = make(seed)
+        X = torch.as_tensor(p.X, device=dev)
+        y = torch.as_tensor(p.labels, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = lib.Plan(X, p.windows, p.sigma)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        alpha, lam, st = plan.solve(y, p.C, precond=precond, rank=rank, allow_not_converged=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_plan.append(1e3 * (t1 - t0))
+        t_solve.append(1e3 * (t2 - t1))
+        stats.append(st)
+        del plan
+    ts = np.array(t_solve)
+    return {"workload": label, "solves": n, "p50_ms": float(np.percentile(ts, 50)),
+            "p99_ms": float(np.percentile(ts, 99)), "mean_ms": float(ts.mean()),
+            "plan_ms_p50": float(np.percentile(t_plan, 50)),
+            "precond_setup_ms_p50": float(np.percentile([s["t_setup_ms"] for s in stats], 50)),
+            "converged": int(sum(s["status"] == 0 for s in stats)),
+            "ip_iters_p50": float(np.percentile([s["ip_iters"] for s in stats], 50)),
+            "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
+            "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
+            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom"}[precond]}
 
 
 def cpu_baseline(p, seconds):
@@ -139,7 +174,7 @@ def main():
            "peak_GBps": HBM_PEAK_GBS}
 
     out = {
-        "metric": "ANOVA-NFFT matvec points*windows/s at rel.err<=1e-4",
+        "metric": "ANOVA-NFFT matvec points*windows/s at rel.err<=1e-4; IPM solve p50/p99 ms",
         "value": value,
         "unit": "points*windows/s",
         "n_gpus": 1,
@@ -161,6 +196,17 @@ def main():
         "roofline": roof,
         "hbm": hbm,
     }
+    ipm = []
+    if a.ipm_small_solves > 0:
+        ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.small_plain(seed=s, N=2000, d=9, R=0),
+                               a.ipm_small_solves, lib.PRECOND_PCHOL, 200,
+                               "plain-small: N=2000 d=9, 3 windows, sigma=1, C=1"))
+    if a.ipm_full_solves > 0:
+        ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
+                               a.ipm_full_solves, lib.PRECOND_NYSTROM, 200,
+                               f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
+                               "Nystrom rank 200"))
+    out["ipm"] = ipm
     if rel_err > 1e-4:
         out["value"] = 0.0
         out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4"

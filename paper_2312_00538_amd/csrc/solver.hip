@@ -182,10 +182,10 @@ __global__ void k_gemv_t(const double* __restrict__ Z, int64_t N, const double* 
     if (threadIdx.x == 0) w[j] = sh[0];
 }
 
-// M = I + sum_i Z_i Z_i^T / theta_i (k x k, lower+upper), one block per (a, b) tile row
-// of 16 x 16 outputs; partial sums over row chunks folded in order.
+// part[c] = sum_{i in chunk c} A_i B_i^T / theta_i (k x k; theta NULL = 1): one block per
+// 16 x 16 output tile and row chunk; the chunk partials are folded in order.
 constexpr int kSy = 16;
-__global__ void k_syrk_partial(const double* __restrict__ Z, int64_t N, int k,
+__global__ void k_gram_partial(const double* __restrict__ Z, const double* __restrict__ Zb, int64_t N, int k,
                                const double* __restrict__ theta, int64_t chunk,
                                double* __restrict__ part) {
     // block: (tile a, tile b, chunk c); threads 16 x 16
@@ -200,11 +200,11 @@ __global__ void k_syrk_partial(const double* __restrict__ Z, int64_t N, int k,
             int64_t i = ib0 + rr;
             int ca = ta * kSy + cc, cb = tb * kSy + cc;
             za[rr][cc] = (i < i1 && ca < k) ? Z[int64_t(ca) * N + i] : 0.0;
-            zb[rr][cc] = (i < i1 && cb < k) ? Z[int64_t(cb) * N + i] : 0.0;
+            zb[rr][cc] = (i < i1 && cb < k) ? Zb[int64_t(cb) * N + i] : 0.0;
         }
         for (int e = threadIdx.x; e < 64; e += kT) {
             int64_t i = ib0 + e;
-            wt[e] = (i < i1) ? 1.0 / theta[i] : 0.0;
+            wt[e] = (i < i1) ? (theta ? 1.0 / theta[i] : 1.0) : 0.0;
         }
         __syncthreads();
 #pragma unroll 8
@@ -214,10 +214,11 @@ __global__ void k_syrk_partial(const double* __restrict__ Z, int64_t N, int k,
     if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc;
 }
 
-__global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, double* __restrict__ M) {
+__global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, double diag,
+                            double* __restrict__ M) {
     int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
     if (e >= int64_t(k) * k) return;
-    double s = (e / k == e % k) ? 1.0 : 0.0;
+    double s = (e / k == e % k) ? diag : 0.0;
     for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * k * k + e];
     M[e] = s;
 }
@@ -413,6 +414,65 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int
     if (i < n) b[i] = a[i];
 }
 
+// out = Y T: Y N x k column-major, T k x kc row-major, out N x kc column-major.
+// Block: 256 rows x 16 output columns; T's 16-column panel is staged in LDS.
+__global__ void k_gemm_nk(const double* __restrict__ Y, int64_t N, int k, const double* __restrict__ T, int kc,
+                          double* __restrict__ out) {
+    extern __shared__ double tp_raw[];  // k x 16 panel of T
+    double (*tp)[16] = reinterpret_cast<double (*)[16]>(tp_raw);
+    const int j0 = blockIdx.y * 16;
+    for (int e = threadIdx.x; e < k * 16; e += kT) {
+        int m = e / 16, jj = e % 16;
+        tp[m][jj] = (j0 + jj < kc) ? T[int64_t(m) * kc + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= N) return;
+    double acc[16];
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) acc[jj] = 0.0;
+    for (int m = 0; m < k; ++m) {
+        const double y = Y[int64_t(m) * N + i];
+#pragma unroll
+        for (int jj = 0; jj < 16; ++jj) acc[jj] += y * tp[m][jj];
+    }
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj)
+        if (j0 + jj < kc) out[int64_t(j0 + jj) * N + i] = acc[jj];
+}
+
+// Gaussian test matrix: Philox4x32-10 (Salmon et al., SC'11) on the counter
+// (row, column, 0, 0) with the seed as key, two 32-bit words -> a 53-bit uniform
+// in (0, 1), Box-Muller with the next two words.
+__device__ inline void philox_round(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    const uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+    const uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+    const uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+    const uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+}
+__device__ inline void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c, k0, k1);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+__global__ void k_gaussian(double* __restrict__ G, int64_t N, int k, uint64_t seed) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    uint32_t c[4] = {uint32_t(i), uint32_t(uint64_t(i) >> 32), uint32_t(j), 0u};
+    philox4x32_10(c, uint32_t(seed), uint32_t(seed >> 32));
+    const double u1 = (double((uint64_t(c[0]) << 21) ^ (c[1] >> 11)) + 0.5) * 0x1.0p-53;
+    const double u2 = (double((uint64_t(c[2]) << 21) ^ (c[3] >> 11)) + 0.5) * 0x1.0p-53;
+    G[int64_t(j) * N + i] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+}
+
 // ------------------------------------------------------------------ host helpers
 struct Reducer {
     DevBuf<double> part, out;
@@ -476,9 +536,9 @@ void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t 
     if (ws.k == 0) return;
     const int k = ws.k;
     const int tiles = (k + kSy - 1) / kSy;
-    hipLaunchKernelGGL(k_syrk_partial, dim3(tiles, tiles, ws.nchunk), dim3(kT), 0, st, ws.Z.p, pl.N, k, th,
-                       ws.chunk, ws.Mpart.p);
-    hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k,
+    hipLaunchKernelGGL(k_gram_partial, dim3(tiles, tiles, ws.nchunk), dim3(kT), 0, st, ws.Z.p, ws.Z.p, pl.N, k,
+                       th, ws.chunk, ws.Mpart.p);
+    hipLaunchKernelGGL(k_gram_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, ws.M.p, k, ws.status.p);
     int bad = 0;
@@ -564,6 +624,142 @@ int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64
     return r;
 }
 
+// ---- small dense helpers (host, FP64, k <= 1024)
+// lower Cholesky in place (row-major); returns false on a non-positive pivot
+bool host_chol(std::vector<double>& A, int k) {
+    for (int j = 0; j < k; ++j) {
+        double d = A[size_t(j) * k + j];
+        for (int m = 0; m < j; ++m) d -= A[size_t(j) * k + m] * A[size_t(j) * k + m];
+        if (!(d > 0.0)) return false;
+        d = std::sqrt(d);
+        A[size_t(j) * k + j] = d;
+        for (int i = j + 1; i < k; ++i) {
+            double v = A[size_t(i) * k + j];
+            for (int m = 0; m < j; ++m) v -= A[size_t(i) * k + m] * A[size_t(j) * k + m];
+            A[size_t(i) * k + j] = v / d;
+        }
+    }
+    return true;
+}
+// T = L^{-T} (row-major k x k upper triangular), L lower from host_chol
+std::vector<double> inv_lower_transposed(const std::vector<double>& L, int k) {
+    std::vector<double> X(size_t(k) * k, 0.0);  // X = L^{-1}, lower
+    for (int c = 0; c < k; ++c) {
+        X[size_t(c) * k + c] = 1.0 / L[size_t(c) * k + c];
+        for (int i = c + 1; i < k; ++i) {
+            double v = 0.0;
+            for (int m = c; m < i; ++m) v -= L[size_t(i) * k + m] * X[size_t(m) * k + c];
+            X[size_t(i) * k + c] = v / L[size_t(i) * k + i];
+        }
+    }
+    std::vector<double> T(size_t(k) * k);
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) T[size_t(i) * k + j] = X[size_t(j) * k + i];
+    return T;
+}
+
+struct Gram {
+    DevBuf<double> part, M;
+    int nchunk = 1;
+    int64_t chunk = 1;
+    void setup(int64_t N, int k) {
+        chunk = 8192;
+        nchunk = int(std::min<int64_t>(256, (N + chunk - 1) / chunk));
+        chunk = (N + nchunk - 1) / nchunk;
+        part.alloc(size_t(nchunk) * k * k);
+        M.alloc(size_t(k) * k);
+    }
+    // host copy of A^T B (k x k, row-major)
+    std::vector<double> run(const double* A, const double* B, int64_t N, int k, hipStream_t st) {
+        const int tiles = (k + kSy - 1) / kSy;
+        hipLaunchKernelGGL(k_gram_partial, dim3(tiles, tiles, nchunk), dim3(kT), 0, st, A, B, N, k,
+                           (const double*)nullptr, chunk, part.p);
+        hipLaunchKernelGGL(k_gram_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, part.p, nchunk, k, 0.0, M.p);
+        std::vector<double> h(size_t(k) * k);
+        ANV_HIP(hipMemcpyAsync(h.data(), M.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        ANV_HIP(hipStreamSynchronize(st));
+        return h;
+    }
+};
+
+// Q <- orth(Y) in place by shifted Cholesky-QR followed by two Cholesky-QR passes
+void orthonormalize(DevBuf<double>& Y, DevBuf<double>& tmp, int64_t N, int k, hipStream_t st) {
+    Gram gr;
+    gr.setup(N, k);
+    DevBuf<double> T;
+    T.alloc(size_t(k) * k);
+    for (int pass = 0; pass < 3; ++pass) {
+        std::vector<double> A = gr.run(Y.p, Y.p, N, k, st);
+        double tr = 0.0;
+        for (int j = 0; j < k; ++j) tr += A[size_t(j) * k + j];
+        ANV_CHECK(std::isfinite(tr), "non-finite Gram matrix in orthonormalisation");
+        if (!(tr > 0.0)) throw Error(ANOVA_NUMERICAL, "orthonormalisation: zero matrix");
+        // first pass: shift 11 (N k + k(k+1)) u ||Y||_F^2 (shifted Cholesky-QR); later passes
+        // shift only if the unshifted factorisation breaks down
+        double shift = pass == 0 ? 11.0 * (double(N) * k + double(k) * (k + 1)) * 0x1.0p-53 * tr : 0.0;
+        std::vector<double> L;
+        for (int attempt = 0; attempt < 8; ++attempt) {
+            L = A;
+            for (int j = 0; j < k; ++j) L[size_t(j) * k + j] += shift;
+            if (host_chol(L, k)) break;
+            shift = shift > 0.0 ? shift * 100.0 : 1e-14 * tr;
+            if (attempt == 7) throw Error(ANOVA_NUMERICAL, "orthonormalisation: Cholesky-QR broke down");
+        }
+        std::vector<double> Th = inv_lower_transposed(L, k);
+        ANV_HIP(hipMemcpyAsync(T.p, Th.data(), Th.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((k + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
+                           Y.p, N, k, T.p, k, tmp.p);
+        std::swap(Y.p, tmp.p);
+    }
+    ANV_HIP(hipStreamSynchronize(st));
+}
+
+// Z^T (N x k, column-major, ld N) = (K Q) L^{-T} D^{-1/2} with Q^T K Q = L D L^T (clamped)
+void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st) {
+    const int64_t N = pl.N;
+    DevBuf<double> tmp;
+    tmp.alloc(size_t(N) * k);
+    orthonormalize(Y, tmp, N, k, st);                    // Y := Q
+    enqueue_matvec(pl, Y.p, k, N, tmp.p, N, st);          // tmp := B = K Q
+    Gram gr;
+    gr.setup(N, k);
+    std::vector<double> Cm = gr.run(Y.p, tmp.p, N, k, st);  // Q^T K Q
+    double dmax = 0.0;
+    for (int i = 0; i < k; ++i) {
+        for (int j = 0; j < i; ++j) {
+            double v = 0.5 * (Cm[size_t(i) * k + j] + Cm[size_t(j) * k + i]);
+            Cm[size_t(i) * k + j] = Cm[size_t(j) * k + i] = v;
+        }
+        dmax = std::max(dmax, Cm[size_t(i) * k + i]);
+    }
+    ANV_CHECK(std::isfinite(dmax), "non-finite Q^T K Q");
+    const double tau = 1e-12 * dmax;
+    // LDL^T without pivoting; D entries below tau are raised to tau (Section 4)
+    std::vector<double> L(size_t(k) * k, 0.0), D(k);
+    for (int j = 0; j < k; ++j) {
+        double dj = Cm[size_t(j) * k + j];
+        for (int m = 0; m < j; ++m) dj -= L[size_t(j) * k + m] * L[size_t(j) * k + m] * D[m];
+        if (!(dj >= tau)) dj = tau;
+        D[j] = dj;
+        L[size_t(j) * k + j] = 1.0;
+        for (int i = j + 1; i < k; ++i) {
+            double v = Cm[size_t(i) * k + j];
+            for (int m = 0; m < j; ++m) v -= L[size_t(i) * k + m] * L[size_t(j) * k + m] * D[m];
+            L[size_t(i) * k + j] = v / dj;
+        }
+    }
+    std::vector<double> T = inv_lower_transposed(L, k);   // L^{-T}
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) T[size_t(i) * k + j] /= std::sqrt(D[j]);
+    DevBuf<double> Td;
+    Td.alloc(size_t(k) * k);
+    ANV_HIP(hipMemcpyAsync(Td.p, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((k + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
+                       tmp.p, N, k, Td.p, k, Zt);
+    ANV_HIP(hipGetLastError());
+    ANV_HIP(hipStreamSynchronize(st));
+}
+
 }  // namespace
 
 int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st) {
@@ -578,8 +774,25 @@ int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl,
     return r;
 }
 
-void nystrom_factor(Plan&, const double*, int, int64_t, double*, int64_t, hipStream_t) {
-    throw Error(ANOVA_INVALID_ARG, "Nystrom: not built yet");
+void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, int64_t ldz, hipStream_t st) {
+    const int64_t N = pl.N;
+    ANV_CHECK(k <= 1024, "k must be <= 1024");
+    DevBuf<double> Y, Gc;
+    Y.alloc(size_t(N) * k);
+    Gc.alloc(size_t(N) * k);
+    ANV_HIP(hipMemcpy2DAsync(Gc.p, N * sizeof(double), G, ldg * sizeof(double), N * sizeof(double), k,
+                             hipMemcpyDeviceToDevice, st));
+    enqueue_matvec(pl, Gc.p, k, N, Y.p, N, st);          // Y = K G
+    if (ldz == N) {
+        nystrom_core(pl, Y, k, Zt, st);
+    } else {
+        DevBuf<double> Z;
+        Z.alloc(size_t(N) * k);
+        nystrom_core(pl, Y, k, Z.p, st);
+        ANV_HIP(hipMemcpy2DAsync(Zt, ldz * sizeof(double), Z.p, N * sizeof(double), N * sizeof(double), k,
+                                 hipMemcpyDeviceToDevice, st));
+        ANV_HIP(hipStreamSynchronize(st));
+    }
 }
 
 // ------------------------------------------------------------------ Algorithm 1
@@ -625,7 +838,15 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         rank_used = pchol_into(pl, o.rank, o.err_tol, ws.Z.p, N, piv.data(), st);
         setup_factor_storage(ws, N, rank_used);
     } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
-        throw Error(ANOVA_INVALID_ARG, "Nystrom preconditioner: not built yet");
+        rank_used = o.rank;
+        ws.Z.alloc(size_t(N) * o.rank);
+        DevBuf<double> Gd, Y;
+        Gd.alloc(size_t(N) * o.rank);
+        Y.alloc(size_t(N) * o.rank);
+        hipLaunchKernelGGL(k_gaussian, dim3(nblk(N), unsigned(o.rank)), dim3(kT), 0, st, Gd.p, N, o.rank, o.seed);
+        enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
+        nystrom_core(pl, Y, o.rank, ws.Z.p, st);
+        setup_factor_storage(ws, N, rank_used);
     } else {
         setup_factor_storage(ws, N, 0);
     }
