@@ -93,6 +93,7 @@ struct WinDev {          // per-window geometry read by the kernels
     int64_t grid_off;    // offset of this window's grid in the grid buffers
     int64_t fold_off;    // offset of this window's fold index
     int64_t t_off[3];    // offsets of the Toeplitz matrices (E x E, row-major)
+    int64_t tgt_off;     // offset of this window in the fold's target-major buffer
     double eta;
     int32_t pad;
 };

@@ -6,14 +6,17 @@
 //   sum      y_j = sum_l eta_l f_j^{(l)}          (fixed window order, FP64)
 //
 // Work decomposition (gfx950, wave64). Points of a window are sorted by
-// (column (cx, cy), layer cz) of their base cell. One wavefront handles one
-// work item: a run of consecutive sorted points of one column. Lane (a, b) owns
-// the grid line (cx + a, cy + b, *) of the 2m x 2m footprint shared by all
-// points of the column, and keeps the 2m cells along z that the current point
-// touches in registers; as the run advances in z, finished cells are written
-// (spread) or new cells are loaded (gather). No atomics anywhere: each work
-// item writes its own slab of partial sums, and the fold kernel adds the slabs
-// that cover a cell in a fixed order, so results are reproducible bit for bit.
+// (column (cx, cy), layer cz) of their base cell. A work item is a run of
+// consecutive sorted points of one column. For 3-feature windows a wavefront
+// takes 64/W work items (W = 2m taps per axis), one per group of W lanes: lane
+// (group, a) owns the x-tap a of its item's footprint and keeps the W x W block
+// (y-tap b, z-cell c) of grid values in registers, so each point's weights are
+// needed by only W lanes (staged in LDS once per round of W points). As the run
+// advances in z, finished z-cells are written (spread) or new ones loaded
+// (gather). 1- and 2-feature windows use one lane per work item. No atomics
+// anywhere: each work item writes its own slab of partial sums and the fold
+// kernel adds the slabs that cover a cell in a fixed order, so results are
+// reproducible bit for bit.
 #include "plan.hpp"
 
 namespace anv {
@@ -30,107 +33,291 @@ __global__ void k_permute(const double* __restrict__ x, const int32_t* __restric
     vs[t] = x[perm[t]];
 }
 
-// One wavefront per work item. The loop is software-pipelined by one point:
-// the z weights, input value and base layer of the next point (wave-uniform,
-// scalar loads) and its per-lane x and y weights (vector loads) are requested
-// before the current point is accumulated. The inner loop uses no LDS, so the
-// scalar-load counter only ever waits for the point about to be used.
+// 3-feature windows: one work item (a long run of one column) per wavefront.
+// The run is swept layer by layer; within a layer its points are dealt to the
+// 64/W lane groups, W points... one per group per step. Lane (group, a) keeps
+// the W x W block (y-tap b, z-cell c) of its group's partial sums; when a layer
+// is complete the groups' values for it are added in group order through LDS
+// and the wave writes one slab row [a][b]. Point data are staged in LDS in
+// chunks of 64 consecutive points.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_spread(const Segment* __restrict__ segs,
-                                               const WinDev* __restrict__ wins,
-                                               const int32_t* __restrict__ zq,
-                                               const WT* __restrict__ wts,
-                                               const double* __restrict__ vs, int64_t N,
-                                               WT* __restrict__ slab) {
-    const Segment sg = segs[blockIdx.x];
-    const int lanes = wins[sg.win].lanes;
-    const int wy = wins[sg.win].Wslot[1];
+__global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ wave_items,
+                                                   const Segment* __restrict__ segs,
+                                                   const int32_t* __restrict__ lstart,
+                                                   const int32_t* __restrict__ lstart_off,
+                                                   const WT* __restrict__ wts,
+                                                   const double* __restrict__ vs, int64_t N,
+                                                   WT* __restrict__ slab) {
+    constexpr int G = 64 / W;                 // lane groups
+    constexpr int REC = 3 * W;
+    constexpr int CH = 64;                    // staged points
+    constexpr int PADR = 16 / int(sizeof(WT)); // record padding, spreads groups over LDS banks
+    constexpr int RS = REC + PADR;
+    __shared__ WT stw[CH * RS];
+    __shared__ WT stv[CH];
+    __shared__ WT red[G][W * W];
+    const int sid = wave_items[blockIdx.x];
+    const Segment sg = segs[sid];
     const int lane = threadIdx.x;
-    const bool active = lane < lanes;
-    const int a = active ? lane / wy : 0;
-    const int b = active ? lane % wy : 0;
+    const int g = lane / W, a = lane % W;
+    const bool lane_ok = g < G;
     const int64_t base = int64_t(sg.win) * N + sg.start;
+    const int32_t* ls = lstart + lstart_off[sid];
+    WT acc[W][W];
+#pragma unroll
+    for (int b = 0; b < W; ++b)
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[b][c] = WT(0);
     WT* out = slab + sg.off;
-    WT acc[W];
+    int cbase = -CH;
+    auto flush = [&](int layer, int c) {  // sum acc[.][c] over groups -> slab row `layer`
+        if (lane_ok) {
 #pragma unroll
-    for (int c = 0; c < W; ++c) acc[c] = WT(0);
-    int zr = sg.z0;
-    int64_t g = base;
-    const int64_t gend = base + sg.count;
-    int nz = zq[g];
-    WT nv = WT(vs[g]);
-    WT nw[W];
-#pragma unroll
-    for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
-    WT nwx = wts[g * (3 * W) + a], nwy = wts[g * (3 * W) + W + b];
-    for (; g < gend;) {
-        const int zj = nz;
-        const WT v = nv, wxa = nwx, wyb = nwy;
-        WT wz[W];
-#pragma unroll
-        for (int c = 0; c < W; ++c) wz[c] = nw[c];
-        ++g;
-        if (g < gend) {
-            nz = zq[g];
-            nv = WT(vs[g]);
-#pragma unroll
-            for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
-            nwx = wts[g * (3 * W) + a];
-            nwy = wts[g * (3 * W) + W + b];
+            for (int b = 0; b < W; ++b) red[g][a * W + b] = acc[b][c];
         }
-        while (zr < zj) {  // layer zr is complete: no later point of the run reaches it
-            if (active) out[(zr - sg.z0) * lanes + lane] = acc[0];
+        __syncthreads();
+        if (lane < W * W) {
+            WT t = WT(0);
 #pragma unroll
-            for (int c = 0; c < W - 1; ++c) acc[c] = acc[c + 1];
-            acc[W - 1] = WT(0);
+            for (int q = 0; q < G; ++q) t += red[q][lane];
+            out[int64_t(layer) * (W * W) + lane] = t;
+        }
+        __syncthreads();
+    };
+    for (int z = sg.z0; z <= sg.z1; ++z) {
+        const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+        for (int k = p; k < q; k += G) {
+            if (k + G > cbase + CH) {  // stage points k .. k+63
+                __syncthreads();
+                cbase = k;
+                if (cbase + lane < sg.count) {
+                    const int64_t gi = base + cbase + lane;
+                    const WT* r = wts + gi * REC;
+#pragma unroll
+                    for (int e = 0; e < REC; ++e) stw[lane * RS + e] = r[e];
+                    stv[lane] = WT(vs[gi]);
+                }
+                __syncthreads();
+            }
+            const int pt = k + g;
+            if (lane_ok && pt < q) {
+                const WT* w = &stw[(pt - cbase) * RS];
+                const WT vx = stv[pt - cbase] * w[a];
+                WT wz[W];
+#pragma unroll
+                for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const WT cb = vx * w[W + b];
+#pragma unroll
+                    for (int c = 0; c < W; ++c) acc[b][c] += cb * wz[c];
+                }
+            }
+        }
+        flush(z - sg.z0, 0);
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
+#pragma unroll
+            for (int c = 0; c < W - 1; ++c) acc[b][c] = acc[b][c + 1];
+            acc[b][W - 1] = WT(0);
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < W - 1; ++c) flush(sg.z1 + 1 + c - sg.z0, c);
+}
+
+// 1- and 2-feature windows: one lane per work item; WY = W for two features
+// (y taps in registers), 1 for one feature. Slab layout [layer][b].
+template <int W, int WY, class WT>
+__global__ __launch_bounds__(64) void k_spread_lane(const int32_t* __restrict__ wave_items,
+                                                    const Segment* __restrict__ segs,
+                                                    const int32_t* __restrict__ zq,
+                                                    const WT* __restrict__ wts,
+                                                    const double* __restrict__ vs, int64_t N,
+                                                    WT* __restrict__ slab) {
+    const int sid = wave_items[blockIdx.x * 64 + threadIdx.x];
+    if (sid < 0) return;
+    const Segment sg = segs[sid];
+    const int64_t base = int64_t(sg.win) * N + sg.start;
+    WT acc[WY][W];
+#pragma unroll
+    for (int b = 0; b < WY; ++b)
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[b][c] = WT(0);
+    int zr = sg.z0;
+    WT* out = slab + sg.off;
+    for (int k = 0; k < sg.count; ++k) {
+        const int64_t gi = base + k;
+        const int zj = zq[gi];
+        while (zr < zj) {
+#pragma unroll
+            for (int b = 0; b < WY; ++b) out[int64_t(zr - sg.z0) * WY + b] = acc[b][0];
+#pragma unroll
+            for (int b = 0; b < WY; ++b) {
+#pragma unroll
+                for (int c = 0; c < W - 1; ++c) acc[b][c] = acc[b][c + 1];
+                acc[b][W - 1] = WT(0);
+            }
             ++zr;
         }
-        const WT coef = v * wxa * wyb;
+        const WT* w = wts + gi * (3 * W);
+        const WT v = WT(vs[gi]);
+        WT wz[W];
 #pragma unroll
-        for (int c = 0; c < W; ++c) acc[c] += coef * wz[c];
-    }
-    if (active) {
+        for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
 #pragma unroll
-        for (int c = 0; c < W; ++c) out[(zr - sg.z0 + c) * lanes + lane] = acc[c];
-    }
-}
-
-// g[cell] = sum over the work items whose slabs cover the cell. One wavefront
-// per cell; lane (a, b) reads the partial sums that column (gx - a, gy - b)
-// wrote for its footprint position (a, b), and the lanes are combined by a
-// fixed butterfly, so the order of additions never changes.
-template <class WT>
-__global__ __launch_bounds__(256) void k_fold(const WinDev* __restrict__ wins,
-                                              const int2* __restrict__ fold,
-                                              const int64_t* __restrict__ sbase,
-                                              const WT* __restrict__ slab, WT* __restrict__ grid) {
-    const int l = blockIdx.y;
-    const WinDev& wd = wins[l];
-    const int64_t cells = int64_t(wd.E[0]) * wd.E[1] * wd.E[2];
-    const int64_t c = int64_t(blockIdx.x) * (blockDim.x / 64) + threadIdx.x / 64;
-    if (c >= cells) return;
-    const int lane = threadIdx.x % 64;
-    const int gz = int(c % wd.E[2]);
-    const int gy = int((c / wd.E[2]) % wd.E[1]);
-    const int gx = int(c / (int64_t(wd.E[2]) * wd.E[1]));
-    double acc = 0.0;
-    if (lane < wd.lanes) {
-        const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
-        const int cx = gx - a, cy = gy - b;
-        if (cx >= 0 && cx < wd.nb[0] && cy >= 0 && cy < wd.nb[1]) {
-            const int2 r = fold[wd.fold_off + (int64_t(cx) * wd.nb[1] + cy) * wd.E[2] + gz];
-            for (int s = r.x; s < r.y; ++s) acc += double(slab[sbase[s] + int64_t(gz) * wd.lanes + lane]);
+        for (int b = 0; b < WY; ++b) {
+            const WT cb = v * w[W + b];
+#pragma unroll
+            for (int c = 0; c < W; ++c) acc[b][c] += cb * wz[c];
         }
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) grid[wd.grid_off + c] = WT(acc);
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b) out[int64_t(zr - sg.z0 + c) * WY + b] = acc[b][c];
 }
 
-// out = T_axis applied along one axis of every window grid (layout [x][y][z])
+// Fold, step A: one wavefront per (window, column, layer). Lane (a, b) adds, in
+// item order, the slab values that the column's work items wrote for layer L
+// at footprint position (a, b), and stores the sum under its TARGET line
+// (cx + a, cy + b): tgt[window][target x][target y][a, b][layer]. Every
+// (target, (a, b)) has exactly one source column, so no two lanes write the
+// same element.
+template <class WT>
+__global__ __launch_bounds__(256) void k_fold_cols(const WinDev* __restrict__ wins, int32_t P,
+                                                   int64_t fold_total, const int2* __restrict__ fold,
+                                                   const int64_t* __restrict__ sbase,
+                                                   const WT* __restrict__ slab, WT* __restrict__ tgt) {
+    const int64_t f = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+    if (f >= fold_total) return;
+    int l = 0;
+    while (l + 1 < P && wins[l + 1].fold_off <= f) ++l;
+    const WinDev& wd = wins[l];
+    const int lane = threadIdx.x % 64;
+    const int64_t fl = f - wd.fold_off;
+    const int L = int(fl % wd.E[2]);
+    const int64_t col = fl / wd.E[2];
+    const int cx = int(col / wd.nb[1]), cy = int(col % wd.nb[1]);
+    const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
+    const int2 r = fold[f];
+    double acc = 0.0;
+    // the items' slab offsets are fetched 64 at a time by one vector load and
+    // broadcast, so the slab reads of a batch are all in flight together
+    for (int s0 = r.x; s0 < r.y; s0 += 64) {
+        const int n = min(64, r.y - s0);
+        const int64_t myoff = lane < n ? sbase[s0 + lane] : 0;
+        const int64_t row = int64_t(L) * wd.lanes + lane;
+        const bool act = lane < wd.lanes;  // lanes beyond the footprint only relay offsets
+        int q = 0;
+        for (; q + 4 <= n; q += 4) {
+            const int64_t o0 = __shfl(myoff, q, 64), o1 = __shfl(myoff, q + 1, 64);
+            const int64_t o2 = __shfl(myoff, q + 2, 64), o3 = __shfl(myoff, q + 3, 64);
+            const WT v0 = act ? slab[o0 + row] : WT(0);
+            const WT v1 = act ? slab[o1 + row] : WT(0);
+            const WT v2 = act ? slab[o2 + row] : WT(0);
+            const WT v3 = act ? slab[o3 + row] : WT(0);
+            acc += double(v0);
+            acc += double(v1);
+            acc += double(v2);
+            acc += double(v3);
+        }
+        for (; q < n; ++q) {
+            const int64_t o = __shfl(myoff, q, 64);
+            acc += act ? double(slab[o + row]) : 0.0;
+        }
+    }
+    if (lane >= wd.lanes) return;
+    const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + lane) * wd.E[2] + L;
+    tgt[wd.tgt_off + t] = WT(acc);
+}
+
+// Fold step B fused with the y and z passes of the grid convolution. One block
+// per (x slice, window): the slice's cells are summed over the footprint
+// positions of their target line in (a, b) order, then T_y and T_z are applied
+// in LDS and the slice is written as g1[x][y][z].
+template <class WT>
+__global__ __launch_bounds__(256) void k_fold_conv_yz(const WinDev* __restrict__ wins,
+                                                      const double* __restrict__ tmat,
+                                                      const WT* __restrict__ tgt, WT* __restrict__ g1) {
+    extern __shared__ double sm[];
+    const int l = blockIdx.y;
+    const WinDev& wd = wins[l];
+    const int x = blockIdx.x;
+    if (x >= wd.E[0]) return;
+    const int Ey = wd.E[1], Ez = wd.E[2];
+    const int S = Ey * Ez;
+    double* s0 = sm;           // slice [y][z]
+    double* s1 = sm + S;       // after the y pass
+    double* ty = s1 + S;       // T_y
+    double* tz = ty + Ey * Ey; // T_z
+    for (int e = threadIdx.x; e < Ey * Ey; e += blockDim.x) ty[e] = tmat[wd.t_off[1] + e];
+    for (int e = threadIdx.x; e < Ez * Ez; e += blockDim.x) tz[e] = tmat[wd.t_off[2] + e];
+    const int cxmax = wd.nb[0];
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {
+        const int y = e / Ez, z = e % Ez;
+        const WT* tl = tgt + wd.tgt_off + (int64_t(x) * Ey + y) * wd.lanes * Ez + z;
+        double acc = 0.0;
+        for (int a = 0; a < wd.Wslot[0]; ++a) {
+            const int cx = x - a;
+            if (cx < 0 || cx >= cxmax) continue;
+            for (int b = 0; b < wd.Wslot[1]; ++b) {
+                const int cy = y - b;
+                if (cy < 0 || cy >= wd.nb[1]) continue;
+                acc += double(tl[int64_t(a * wd.Wslot[1] + b) * Ez]);
+            }
+        }
+        s0[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {  // y pass
+        const int y = e / Ez, z = e % Ez;
+        double acc = 0.0;
+        for (int k = 0; k < Ey; ++k) acc += ty[y * Ey + k] * s0[k * Ez + z];
+        s1[e] = acc;
+    }
+    __syncthreads();
+    WT* out = g1 + wd.grid_off + int64_t(x) * S;
+    for (int e = threadIdx.x; e < S; e += blockDim.x) {  // z pass
+        const int y = e / Ez, z = e % Ez;
+        double acc = 0.0;
+        for (int k = 0; k < Ez; ++k) acc += tz[z * Ez + k] * s1[y * Ez + k];
+        out[e] = WT(acc);
+    }
+}
+
+// x pass of the grid convolution, one block per (y slice, window); the result
+// is stored as h[x][z][y], the layout the gather reads.
+template <class WT>
+__global__ __launch_bounds__(256) void k_conv_x(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
+                                                const WT* __restrict__ g1, WT* __restrict__ h) {
+    extern __shared__ double sm[];
+    const int l = blockIdx.y;
+    const WinDev& wd = wins[l];
+    const int y = blockIdx.x;
+    if (y >= wd.E[1]) return;
+    const int Ex = wd.E[0], Ey = wd.E[1], Ez = wd.E[2];
+    double* sl = sm;            // [x][z] at this y
+    double* tx = sm + Ex * Ez;  // T_x
+    for (int e = threadIdx.x; e < Ex * Ex; e += blockDim.x) tx[e] = tmat[wd.t_off[0] + e];
+    for (int e = threadIdx.x; e < Ex * Ez; e += blockDim.x) {
+        const int x = e / Ez, z = e % Ez;
+        sl[e] = double(g1[wd.grid_off + (int64_t(x) * Ey + y) * Ez + z]);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < Ex * Ez; e += blockDim.x) {
+        const int x = e / Ez, z = e % Ez;
+        double acc = 0.0;
+        for (int k = 0; k < Ex; ++k) acc += tx[x * Ex + k] * sl[k * Ez + z];
+        h[wd.grid_off + (int64_t(x) * Ez + z) * Ey + y] = WT(acc);
+    }
+}
+
+// out = T_axis applied along one axis of every window grid (layout [x][y][z]);
+// with zy_out the result is stored as [x][z][y], the layout the gather reads.
 template <class WT>
 __global__ void k_conv_axis(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
-                            int axis, const WT* __restrict__ in, WT* __restrict__ out) {
+                            int axis, const WT* __restrict__ in, WT* __restrict__ out, int zy_out) {
     const int l = blockIdx.y;
     const WinDev wd = wins[l];
     const int64_t cells = int64_t(wd.E[0]) * wd.E[1] * wd.E[2];
@@ -144,83 +331,153 @@ __global__ void k_conv_axis(const WinDev* __restrict__ wins, const double* __res
     const double* T = tmat + wd.t_off[axis] + int64_t(i) * E;
     double acc = 0.0;
     for (int k = 0; k < E; ++k) acc += T[k] * double(in[base + int64_t(k) * stride]);
-    out[wd.grid_off + c] = WT(acc);
+    int64_t o = c;
+    if (zy_out) {
+        const int gz = int(c % wd.E[2]);
+        const int gy = int((c / wd.E[2]) % wd.E[1]);
+        const int64_t gx = c / (int64_t(wd.E[2]) * wd.E[1]);
+        o = (gx * wd.E[2] + gz) * wd.E[1] + gy;
+    }
+    out[wd.grid_off + o] = WT(acc);
 }
 
-// One wavefront per work item. Lane (a, b) keeps the 2m grid values of its line
-// (cx + a, cy + b, zr .. zr + 2m - 1) in registers. Loads are pipelined one
-// point ahead as in the spread. Each point's per-lane partial product goes to
-// LDS and after every chunk of points the wave sums them per point in lane
-// order (one transposed reduction instead of a shuffle tree per point).
+// 3-feature windows, one work item per wavefront as in the spread. Every lane
+// group keeps the same W x W block h(cx + a, cy + b, z .. z + W - 1) (h stored
+// as [x][z][y]) for the current layer; per step each group takes one point of
+// the layer, lane a forms the share of x-tap a and the W lanes add their shares
+// with a fixed xor butterfly.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_gather(const Segment* __restrict__ segs,
-                                               const WinDev* __restrict__ wins,
-                                               const int32_t* __restrict__ zq,
-                                               const WT* __restrict__ wts,
-                                               const WT* __restrict__ h, int64_t N,
-                                               double* __restrict__ fs) {
-    constexpr int CH = 32;
-    __shared__ double red[CH][65];
-    const Segment sg = segs[blockIdx.x];
+__global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ wave_items,
+                                                   const Segment* __restrict__ segs,
+                                                   const int32_t* __restrict__ lstart,
+                                                   const int32_t* __restrict__ lstart_off,
+                                                   const WinDev* __restrict__ wins,
+                                                   const WT* __restrict__ wts,
+                                                   const WT* __restrict__ h, int64_t N,
+                                                   double* __restrict__ fs) {
+    constexpr int G = 64 / W;
+    constexpr int REC = 3 * W;
+    constexpr int CH = 64;
+    constexpr int PADR = 16 / int(sizeof(WT));
+    constexpr int RS = REC + PADR;
+    __shared__ WT stw[CH * RS];
+    const int sid = wave_items[blockIdx.x];
+    const Segment sg = segs[sid];
     const WinDev& wd = wins[sg.win];
-    const int lanes = wd.lanes;
-    const int wy = wd.Wslot[1];
     const int lane = threadIdx.x;
-    const bool active = lane < lanes;
-    const int a = active ? lane / wy : 0;
-    const int b = active ? lane % wy : 0;
+    const int g = lane / W, a = lane % W;
+    const bool lane_ok = g < G;
+    const int64_t base = int64_t(sg.win) * N + sg.start;
+    const int32_t* ls = lstart + lstart_off[sid];
     const int cx = sg.col / wd.nb[1];
     const int cy = sg.col % wd.nb[1];
-    const int Ez = wd.E[2];
-    const WT* hcol = h + wd.grid_off + (int64_t(cx + a) * wd.E[1] + (cy + b)) * Ez;
+    const int Ey = wd.E[1];
+    const WT* hp = h + wd.grid_off + int64_t(cx + (lane_ok ? a : 0)) * wd.E[2] * Ey + cy;
+    WT hr[W][W];
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < W; ++b) hr[b][c] = hp[int64_t(sg.z0 + c) * Ey + b];
+    int cbase = -CH;
+    for (int z = sg.z0; z <= sg.z1; ++z) {
+        const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+        for (int k = p; k < q; k += G) {
+            if (k + G > cbase + CH) {
+                __syncthreads();
+                cbase = k;
+                if (cbase + lane < sg.count) {
+                    const WT* r = wts + (base + cbase + lane) * REC;
+#pragma unroll
+                    for (int e = 0; e < REC; ++e) stw[lane * RS + e] = r[e];
+                }
+                __syncthreads();
+            }
+            const int pt = k + g;
+            const bool act = lane_ok && pt < q;
+            double part = 0.0;
+            if (act) {
+                const WT* w = &stw[(pt - cbase) * RS];
+                WT wz[W];
+#pragma unroll
+                for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
+                WT sy = WT(0);
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    WT t = WT(0);
+#pragma unroll
+                    for (int c = 0; c < W; ++c) t += wz[c] * hr[b][c];
+                    sy += w[W + b] * t;
+                }
+                part = double(w[a] * sy);
+            }
+            if constexpr ((W & (W - 1)) == 0) {
+#pragma unroll
+                for (int o = W / 2; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+            } else {
+                double tot = 0.0;
+#pragma unroll
+                for (int q2 = 0; q2 < W; ++q2) tot += __shfl(part, g * W + q2, 64);
+                part = tot;
+            }
+            if (act && a == 0) fs[base + pt] = part;
+        }
+        if (z < sg.z1) {
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+#pragma unroll
+                for (int c = 0; c < W - 1; ++c) hr[b][c] = hr[b][c + 1];
+                hr[b][W - 1] = hp[int64_t(z + W) * Ey + b];
+            }
+        }
+    }
+}
+
+// 1- and 2-feature windows: one lane per work item.
+template <int W, int WY, class WT>
+__global__ __launch_bounds__(64) void k_gather_lane(const int32_t* __restrict__ wave_items,
+                                                    const Segment* __restrict__ segs,
+                                                    const WinDev* __restrict__ wins,
+                                                    const int32_t* __restrict__ zq,
+                                                    const WT* __restrict__ wts,
+                                                    const WT* __restrict__ h, int64_t N,
+                                                    double* __restrict__ fs) {
+    const int sid = wave_items[blockIdx.x * 64 + threadIdx.x];
+    if (sid < 0) return;
+    const Segment sg = segs[sid];
+    const WinDev& wd = wins[sg.win];
+    const int cx = sg.col / wd.nb[1];
+    const int cy = sg.col % wd.nb[1];
+    const int Ey = wd.E[1];
+    const WT* hp = h + wd.grid_off + int64_t(cx) * wd.E[2] * Ey + cy;
     const int64_t base = int64_t(sg.win) * N + sg.start;
-    WT ring[W];
+    WT hr[WY][W];
     int zr = sg.z0;
 #pragma unroll
-    for (int c = 0; c < W; ++c) ring[c] = active ? hcol[zr + c] : WT(0);
-    WT nxt = (active && zr + W < Ez) ? hcol[zr + W] : WT(0);
-    int64_t g = base;
-    const int64_t gend = base + sg.count;
-    int nz = zq[g];
-    WT nw[W];
+    for (int c = 0; c < W; ++c)
 #pragma unroll
-    for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
-    WT nwx = wts[g * (3 * W) + a], nwy = wts[g * (3 * W) + W + b];
-    for (int j0 = 0; j0 < sg.count; j0 += CH) {
-        const int nb = min(CH, sg.count - j0);
-        for (int jj = 0; jj < nb; ++jj) {
-            const int zj = nz;
-            const WT wxa = nwx, wyb = nwy;
-            WT wz[W];
+        for (int b = 0; b < WY; ++b) hr[b][c] = hp[int64_t(zr + c) * Ey + b];
+    for (int k = 0; k < sg.count; ++k) {
+        const int64_t gi = base + k;
+        const int zj = zq[gi];
+        while (zr < zj) {
 #pragma unroll
-            for (int c = 0; c < W; ++c) wz[c] = nw[c];
-            ++g;
-            if (g < gend) {
-                nz = zq[g];
+            for (int b = 0; b < WY; ++b) {
 #pragma unroll
-                for (int c = 0; c < W; ++c) nw[c] = wts[g * (3 * W) + 2 * W + c];
-                nwx = wts[g * (3 * W) + a];
-                nwy = wts[g * (3 * W) + W + b];
+                for (int c = 0; c < W - 1; ++c) hr[b][c] = hr[b][c + 1];
+                hr[b][W - 1] = hp[int64_t(zr + W) * Ey + b];
             }
-            while (zr < zj) {
-#pragma unroll
-                for (int c = 0; c < W - 1; ++c) ring[c] = ring[c + 1];
-                ring[W - 1] = nxt;
-                ++zr;
-                nxt = (active && zr + W < Ez) ? hcol[zr + W] : WT(0);
-            }
-            WT s = WT(0);
-#pragma unroll
-            for (int c = 0; c < W; ++c) s += wz[c] * ring[c];
-            red[jj][lane] = active ? double(s * wxa * wyb) : 0.0;
+            ++zr;
         }
-        __syncthreads();
-        if (lane < nb) {
-            double sum = 0.0;
-            for (int q = 0; q < lanes; ++q) sum += red[lane][q];
-            fs[base + j0 + lane] = sum;
+        const WT* w = wts + gi * (3 * W);
+        WT sy = WT(0);
+#pragma unroll
+        for (int b = 0; b < WY; ++b) {
+            WT t = WT(0);
+#pragma unroll
+            for (int c = 0; c < W; ++c) t += w[2 * W + c] * hr[b][c];
+            sy += w[W + b] * t;
         }
-        __syncthreads();
+        fs[gi] = double(sy);
     }
 }
 
@@ -238,25 +495,41 @@ template <int W, class WT>
 void run_matvec(Plan& pl, const double* x, double* y, WT* wts, WT* slab, WT* g, WT* h, WT* ca,
                 WT* cb, hipStream_t st) {
     const int64_t N = pl.N, NP = pl.N * pl.P;
-    const unsigned nseg = unsigned(pl.segs_h.size());
     const bool prof = pl.profiling;
     if (prof) pl.record_stage_event(st);
     hipLaunchKernelGGL(k_permute, dim3(nblocks(NP)), dim3(kThreads), 0, st, x, pl.perm.p, NP, N,
                        pl.vs.p);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL((k_spread<W, WT>), dim3(nseg), dim3(64), 0, st, pl.segs.p, pl.wins_d.p,
-                       pl.zq.p, wts, pl.vs.p, N, slab);
-    const dim3 gg(nblocks(pl.grid_max), unsigned(pl.P));
+    if (pl.nwave[3])
+        hipLaunchKernelGGL((k_spread_grp<W, WT>), dim3(pl.nwave[3]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, wts, pl.vs.p, N, slab);
+    if (pl.nwave[2])
+        hipLaunchKernelGGL((k_spread_lane<W, W, WT>), dim3(pl.nwave[2]), dim3(64), 0, st,
+                           pl.wave_items.p + pl.wave_off[2], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
+    if (pl.nwave[1])
+        hipLaunchKernelGGL((k_spread_lane<W, 1, WT>), dim3(pl.nwave[1]), dim3(64), 0, st,
+                           pl.wave_items.p + pl.wave_off[1], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_fold<WT>, dim3(unsigned((pl.grid_max + 3) / 4), unsigned(pl.P)), dim3(256), 0,
-                       st, pl.wins_d.p, pl.fold.p, pl.sbase.p, slab, g);
+    hipLaunchKernelGGL(k_fold_cols<WT>, dim3(unsigned((pl.fold_total + 3) / 4)), dim3(256), 0, st, pl.wins_d.p,
+                       pl.P, pl.fold_total, pl.fold.p, pl.sbase.p, slab, ca);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_conv_axis<WT>, gg, dim3(kThreads), 0, st, pl.wins_d.p, pl.tmat.p, 0, g, ca);
-    hipLaunchKernelGGL(k_conv_axis<WT>, gg, dim3(kThreads), 0, st, pl.wins_d.p, pl.tmat.p, 1, ca, cb);
-    hipLaunchKernelGGL(k_conv_axis<WT>, gg, dim3(kThreads), 0, st, pl.wins_d.p, pl.tmat.p, 2, cb, h);
+    hipLaunchKernelGGL(k_fold_conv_yz<WT>, dim3(unsigned(pl.emax[0]), unsigned(pl.P)), dim3(256),
+                       size_t(2 * pl.emax[1] * pl.emax[2] + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) *
+                           sizeof(double),
+                       st, pl.wins_d.p, pl.tmat.p, ca, g);
+    hipLaunchKernelGGL(k_conv_x<WT>, dim3(unsigned(pl.emax[1]), unsigned(pl.P)), dim3(256),
+                       size_t(pl.emax[0] * pl.emax[2] + pl.emax[0] * pl.emax[0]) * sizeof(double), st, pl.wins_d.p,
+                       pl.tmat.p, g, h);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL((k_gather<W, WT>), dim3(nseg), dim3(64), 0, st, pl.segs.p, pl.wins_d.p,
-                       pl.zq.p, wts, h, N, pl.fs.p);
+    if (pl.nwave[3])
+        hipLaunchKernelGGL((k_gather_grp<W, WT>), dim3(pl.nwave[3]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, wts, h, N, pl.fs.p);
+    if (pl.nwave[2])
+        hipLaunchKernelGGL((k_gather_lane<W, W, WT>), dim3(pl.nwave[2]), dim3(64), 0, st,
+                           pl.wave_items.p + pl.wave_off[2], pl.segs.p, pl.wins_d.p, pl.zq.p, wts, h, N, pl.fs.p);
+    if (pl.nwave[1])
+        hipLaunchKernelGGL((k_gather_lane<W, 1, WT>), dim3(pl.nwave[1]), dim3(64), 0, st,
+                           pl.wave_items.p + pl.wave_off[1], pl.segs.p, pl.wins_d.p, pl.zq.p, wts, h, N, pl.fs.p);
     if (prof) pl.record_stage_event(st);
     hipLaunchKernelGGL(k_window_sum, dim3(nblocks(N)), dim3(kThreads), 0, st, pl.fs.p, pl.pos.p,
                        pl.wins_d.p, pl.P, N, y);

@@ -176,7 +176,7 @@ inline unsigned nblocks(int64_t n, int t = kThreads) { return unsigned((n + t - 
 }  // namespace
 
 int64_t Plan::device_bytes() const {
-    return int64_t(wins_d.bytes() + sbase.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
+    return int64_t(wins_d.bytes() + sbase.bytes() + wave_items.bytes() + lstart.bytes() + lstart_off.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
                    wts32.bytes() + segs.bytes() + fold.bytes() + tmat.bytes() + xw.bytes() +
                    vs.bytes() + fs.bytes() + g64.bytes() + h64.bytes() + c64a.bytes() +
                    c64b.bytes() + g32.bytes() + h32.bytes() + c32a.bytes() + c32b.bytes() +
@@ -214,7 +214,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     pl->prm.reg_p = o.reg_p;
     pl->W = 2 * o.cutoff_m;
     pl->precision = o.precision;
-    pl->seg_points = o.seg_points > 0 ? o.seg_points : 256;
+    pl->seg_points = o.seg_points > 0 ? o.seg_points : 768;
     const int W = pl->W, m = pl->prm.m, n_os = pl->prm.n_os;
     pl->win.assign(windows, windows + 3 * P);
     pl->sigma.assign(sigma, sigma + P);
@@ -332,6 +332,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
             toff += int64_t(E) * E;
         }
         wd.lanes = wd.Wslot[0] * wd.Wslot[1];
+        for (int s2 = 0; s2 < 3; ++s2) pl->emax[s2] = std::max(pl->emax[s2], wd.E[s2]);
         wd.grid_off = goff;
         int64_t cells = int64_t(wd.E[0]) * wd.E[1] * wd.E[2];
         goff += cells;
@@ -341,6 +342,12 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     }
     pl->grid_total = goff;
     pl->tmat_total = toff;
+    {
+        const int64_t ey = pl->emax[1], ez = pl->emax[2], ex = pl->emax[0];
+        const int64_t lds_yz = (2 * ey * ez + ey * ey + ez * ez) * 8, lds_x = (ex * ez + ex * ex) * 8;
+        ANV_CHECK(lds_yz <= 65536 && lds_x <= 65536,
+                  "occupied grid box too large for the LDS-resident grid step (reduce n_bw or raise eps_b)");
+    }
     upload(pl->tmat, tm_h, st);
 
     // 4. sort points of each window by (column, layer); stable, so ties keep point order
@@ -403,6 +410,9 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
         wd.fold_off = int64_t(fold_h.size());
         fold_h.resize(fold_h.size() + size_t(ncol) * Ez, int2{0, 0});
         const uint32_t* kk = ks.data() + size_t(l) * N;
+        int dwl = 0;
+        for (int s2 = 0; s2 < 3; ++s2) dwl += pl->slot_feat[l][s2] >= 0;
+        const int sp = dwl == 3 ? pl->seg_points : pl->seg_points_lane;
         int64_t j = 0;
         while (j < N) {
             int64_t col = kk[j] / nbz;
@@ -414,7 +424,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
                 sg.start = int32_t(j);
                 sg.z0 = int32_t(kk[j] % nbz);
                 int32_t cnt = 0;
-                while (j < N && int64_t(kk[j] / nbz) == col && cnt < pl->seg_points) {
+                while (j < N && int64_t(kk[j] / nbz) == col && cnt < sp) {
                     ++j;
                     ++cnt;
                 }
@@ -434,6 +444,53 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
         }
     }
     ANV_CHECK(pl->segs_h.size() < (size_t(1) << 31), "too many work items");
+    {
+        // per window kind, work items sorted by length (longest first) so that the
+        // items sharing a wavefront have similar lengths; packed 64/W or 64 per wave
+        std::vector<int32_t> items;
+        for (int kind = 3; kind >= 1; --kind) {
+            std::vector<int32_t> ids;
+            for (size_t i = 0; i < pl->segs_h.size(); ++i) {
+                int l = pl->segs_h[i].win;
+                int dw = 0;
+                for (int s2 = 0; s2 < 3; ++s2) dw += pl->slot_feat[l][s2] >= 0;
+                if (dw == kind) ids.push_back(int32_t(i));
+            }
+            std::stable_sort(ids.begin(), ids.end(), [&](int32_t u, int32_t v) {
+                return pl->segs_h[u].count > pl->segs_h[v].count;
+            });
+            const int per = kind == 3 ? 1 : 64;
+            pl->wave_off[kind] = int64_t(items.size());
+            pl->nwave[kind] = int32_t((ids.size() + per - 1) / per);
+            for (int32_t w = 0; w < pl->nwave[kind]; ++w)
+                for (int q = 0; q < per; ++q) {
+                    size_t idx = size_t(w) * per + q;
+                    items.push_back(idx < ids.size() ? ids[idx] : -1);
+                }
+        }
+        if (items.empty()) items.push_back(-1);
+        upload(pl->wave_items, items, st);
+        // layer starts of 3-feature items
+        std::vector<int32_t> lso(pl->segs_h.size(), 0), lsv;
+        for (size_t i = 0; i < pl->segs_h.size(); ++i) {
+            const Segment& sgi = pl->segs_h[i];
+            int l = sgi.win;
+            int dw = 0;
+            for (int s2 = 0; s2 < 3; ++s2) dw += pl->slot_feat[l][s2] >= 0;
+            if (dw != 3) continue;
+            lso[i] = int32_t(lsv.size());
+            const uint32_t* kk = ks.data() + size_t(l) * N + sgi.start;
+            const int nbz = pl->wins_h[l].nb[2];
+            int j2 = 0;
+            for (int z = sgi.z0; z <= sgi.z1 + 1; ++z) {
+                while (j2 < sgi.count && int(kk[j2] % nbz) < z) ++j2;
+                lsv.push_back(j2);
+            }
+        }
+        if (lsv.empty()) lsv.push_back(0);
+        upload(pl->lstart, lsv, st);
+        upload(pl->lstart_off, lso, st);
+    }
     pl->slab_total = slab_off;
     pl->fold_total = int64_t(fold_h.size());
     upload(pl->segs, pl->segs_h, st);
@@ -447,16 +504,28 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     // 7. matvec scratch
     pl->vs.alloc(size_t(N) * P);
     pl->fs.alloc(size_t(N) * P);
+    int64_t tgt_total = pl->grid_total;  // fold target-major buffer: cells x footprint positions
+    {
+        int64_t off = 0;
+        for (int l = 0; l < P; ++l) {
+            WinDev& wd = pl->wins_h[l];
+            wd.tgt_off = off;
+            off += int64_t(wd.E[0]) * wd.E[1] * wd.E[2] * wd.lanes;
+        }
+        tgt_total = std::max(tgt_total, off);
+        ANV_HIP(hipMemcpyAsync(pl->wins_d.p, pl->wins_h.data(), pl->wins_h.size() * sizeof(WinDev),
+                               hipMemcpyHostToDevice, st));
+    }
     if (pl->precision == ANOVA_PREC_FP64) {
         pl->g64.alloc(pl->grid_total);
         pl->h64.alloc(pl->grid_total);
-        pl->c64a.alloc(pl->grid_total);
+        pl->c64a.alloc(tgt_total);
         pl->c64b.alloc(pl->grid_total);
         pl->slab64.alloc(pl->slab_total);
     } else {
         pl->g32.alloc(pl->grid_total);
         pl->h32.alloc(pl->grid_total);
-        pl->c32a.alloc(pl->grid_total);
+        pl->c32a.alloc(tgt_total);
         pl->c32b.alloc(pl->grid_total);
         pl->slab32.alloc(pl->slab_total);
     }

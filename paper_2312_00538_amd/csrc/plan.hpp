@@ -13,7 +13,8 @@ struct Plan {
     int32_t W = 8;              // taps per axis = 2m
     NfftParams prm;
     int32_t precision = ANOVA_PREC_FP64;
-    int32_t seg_points = 256;
+    int32_t seg_points = 768;   // work-item length for 3-feature windows
+    int32_t seg_points_lane = 128;  // work-item length for 1- and 2-feature windows
     std::vector<int32_t> win;   // P x 3 as given
     std::vector<double> sigma, eta;
     std::vector<std::array<int32_t, 3>> slot_feat;  // feature per slot, -1 = dummy
@@ -32,11 +33,20 @@ struct Plan {
     DevBuf<Segment> segs;
     DevBuf<int2> fold;          // per (window, column, layer): covering segment range
     DevBuf<int64_t> sbase;      // per segment: slab offset - z0 * lanes
+    // wavefront tables: for windows with 3, 2, 1 features, the work items each
+    // wavefront handles (64/W per wave for 3 features, 64 otherwise; -1 = none)
+    DevBuf<int32_t> wave_items;
+    // per 3-feature work item: start of each of its layers relative to its first point
+    // (z1 - z0 + 2 entries), at lstart[lstart_off[item]]
+    DevBuf<int32_t> lstart, lstart_off;
+    int64_t wave_off[4] = {0, 0, 0, 0};
+    int32_t nwave[4] = {0, 0, 0, 0};
     int64_t fold_total = 0;
     DevBuf<double> tmat;        // Toeplitz matrices, row-major E x E per (window, slot)
     int64_t tmat_total = 0;
     int64_t grid_total = 0;     // occupied cells summed over windows
     int64_t grid_max = 0;       // largest window grid
+    int32_t emax[3] = {1, 1, 1}; // largest occupied extent per slot over windows
     int64_t slab_total = 0;
 
     // original windowed coordinates [N][P][3] (exact kernel columns)
