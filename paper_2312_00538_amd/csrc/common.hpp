@@ -85,6 +85,12 @@ double kb_hat(int k, int n, int m, double b);
 // ---------------------------------------------------------------- plan
 constexpr int kMaxW = 8;  // 2m for the supported cutoffs m <= 4
 
+// elements per point record of Kaiser-Bessel weights (x, y, z taps), padded to
+// a multiple of 16 bytes so records can be moved in 16-byte pieces
+__host__ __device__ constexpr int rec_stride(int W, int elem_bytes) {
+    return ((3 * W * elem_bytes + 15) / 16) * 16 / elem_bytes;
+}
+
 struct WinDev {          // per-window geometry read by the kernels
     int32_t E[3];        // occupied grid extent per slot (x, y, z); 1 for a dummy slot
     int32_t nb[3];       // number of base cells per slot = E - Wslot + 1
@@ -94,6 +100,7 @@ struct WinDev {          // per-window geometry read by the kernels
     int64_t fold_off;    // offset of this window's fold index
     int64_t t_off[3];    // offsets of the Toeplitz matrices (E x E, row-major)
     int64_t tgt_off;     // offset of this window in the fold's target-major buffer
+    int64_t col_off;     // index of this window's first column in per-column tables
     double eta;
     int32_t pad;
 };

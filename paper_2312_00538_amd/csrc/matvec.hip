@@ -26,6 +26,44 @@ namespace {
 constexpr int kThreads = 256;
 inline unsigned nblocks(int64_t n, int t = kThreads) { return unsigned((n + t - 1) / t); }
 
+// Asynchronous staging of point records straight into LDS (gfx950 LDS DMA,
+// 16 bytes per lane per instruction). The chunk region holds CH records of RS
+// elements (REC data + padding); each 1 KB instruction slot maps to a record
+// element, padding slots and points past the item read a valid dummy record.
+template <class WT, int REC, int RS, int CH>
+__device__ inline void stage_records_async(WT* lds, const WT* __restrict__ wts, int64_t base, int cstart,
+                                           int count, int lane) {
+    constexpr int RB = RS * int(sizeof(WT));
+    constexpr int BYTES = CH * RB;
+    static_assert(BYTES % 1024 == 0, "chunk region must be whole 1 KB DMA slots");
+    static_assert(RB % 16 == 0 && (REC * int(sizeof(WT))) % 16 == 0, "records must be 16-byte pieces");
+#pragma unroll
+    for (int j = 0; j < BYTES / 1024; ++j) {
+        const int o = j * 1024 + lane * 16;
+        const int pnt = o / RB;
+        const int e = (o % RB) / int(sizeof(WT));
+        const int pt = cstart + pnt;
+        const bool valid = e < REC && pt < count;
+        const WT* src = valid ? wts + (base + pt) * REC + e : wts + base * REC;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(lds + j * (1024 / int(sizeof(WT)))),
+                                         16, 0, 0);
+    }
+}
+
+// 64 input values (doubles) of points cstart .. cstart+63 into a 1 KB LDS slot
+// (lanes 0..31 move two values each; the input array carries two padding entries)
+__device__ inline void stage_values_async(double* lds, const double* __restrict__ vs, int64_t base, int cstart,
+                                          int count, int lane) {
+    const int pt = cstart + 2 * lane;
+    const bool valid = lane < 32 && pt < count;
+    const double* src = valid ? vs + base + pt : vs + base;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+__device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
 __global__ void k_permute(const double* __restrict__ x, const int32_t* __restrict__ perm,
                           int64_t NP, int64_t N, double* __restrict__ vs) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -45,17 +83,23 @@ __global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ w
                                                    const Segment* __restrict__ segs,
                                                    const int32_t* __restrict__ lstart,
                                                    const int32_t* __restrict__ lstart_off,
+                                                   const WinDev* __restrict__ wins,
+                                                   const uint8_t* __restrict__ alone,
                                                    const WT* __restrict__ wts,
                                                    const double* __restrict__ vs, int64_t N,
-                                                   WT* __restrict__ slab) {
+                                                   WT* __restrict__ slab, WT* __restrict__ tgt) {
     constexpr int G = 64 / W;                 // lane groups
-    constexpr int REC = 3 * W;
+    constexpr int REC = rec_stride(W, int(sizeof(WT)));
     constexpr int CH = 64;                    // staged points
     constexpr int PADR = 16 / int(sizeof(WT)); // record padding, spreads groups over LDS banks
     constexpr int RS = REC + PADR;
-    __shared__ WT stw[CH * RS];
-    __shared__ WT stv[CH];
-    __shared__ WT red[G][W * W];
+    constexpr int STEP = CH - G;               // chunk c holds points [c*STEP, c*STEP + CH)
+    __shared__ WT stw[2][CH * RS];
+    __shared__ double stv[2][128];
+    // per-layer group sums: plane b holds [g][a] (consecutive lanes write consecutive
+    // elements); the plane stride 72 = 64 + 8 spreads the (a, b) readers over all banks
+    constexpr int RP = 64 + 8;
+    __shared__ WT red[W * RP];
     const int sid = wave_items[blockIdx.x];
     const Segment sg = segs[sid];
     const int lane = threadIdx.x;
@@ -68,41 +112,59 @@ __global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ w
     for (int b = 0; b < W; ++b)
 #pragma unroll
         for (int c = 0; c < W; ++c) acc[b][c] = WT(0);
+    // an item alone in its column has no overlapping neighbour: its layers go
+    // straight to the fold's target-major buffer (target line (cx+a, cy+b),
+    // footprint position (a, b)); otherwise to its slab
+    const bool direct = alone[sid] != 0;
     WT* out = slab + sg.off;
-    int cbase = -CH;
-    auto flush = [&](int layer, int c) {  // sum acc[.][c] over groups -> slab row `layer`
+    WT* tout = tgt;
+    int64_t tstride = 1;
+    {
+        const WinDev& wd = wins[sg.win];
+        const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+        const int ta = lane / W, tb = lane % W;  // footprint position written by this lane
+        tout = tgt + wd.tgt_off + ((int64_t(cx + ta) * wd.E[1] + (cy + tb)) * (W * W) + lane) * wd.E[2] + sg.z0;
+        tstride = 1;
+    }
+    int cc = -1;
+    stage_records_async<WT, REC, RS, CH>(stw[0], wts, base, 0, sg.count, lane);
+    stage_values_async(stv[0], vs, base, 0, sg.count, lane);
+    auto flush = [&](int layer, int c) {  // sum acc[.][c] over groups -> row `layer`
         if (lane_ok) {
 #pragma unroll
-            for (int b = 0; b < W; ++b) red[g][a * W + b] = acc[b][c];
+            for (int b = 0; b < W; ++b) red[b * RP + g * W + a] = acc[b][c];
         }
         __syncthreads();
         if (lane < W * W) {
+            const int ra = lane / W, rb = lane % W;
             WT t = WT(0);
 #pragma unroll
-            for (int q = 0; q < G; ++q) t += red[q][lane];
-            out[int64_t(layer) * (W * W) + lane] = t;
+            for (int q = 0; q < G; ++q) t += red[rb * RP + q * W + ra];
+            if (direct)
+                tout[int64_t(layer) * tstride] = t;
+            else
+                out[int64_t(layer) * (W * W) + lane] = t;
         }
         __syncthreads();
     };
     for (int z = sg.z0; z <= sg.z1; ++z) {
         const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
         for (int k = p; k < q; k += G) {
-            if (k + G > cbase + CH) {  // stage points k .. k+63
+            const int c = k / STEP;
+            if (c > cc) {  // chunk c has landed; start moving chunk c+1 into the other buffer
+                wait_vmem();
                 __syncthreads();
-                cbase = k;
-                if (cbase + lane < sg.count) {
-                    const int64_t gi = base + cbase + lane;
-                    const WT* r = wts + gi * REC;
-#pragma unroll
-                    for (int e = 0; e < REC; ++e) stw[lane * RS + e] = r[e];
-                    stv[lane] = WT(vs[gi]);
+                cc = c;
+                if ((c + 1) * STEP < sg.count) {
+                    stage_records_async<WT, REC, RS, CH>(stw[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                    stage_values_async(stv[(c + 1) & 1], vs, base, (c + 1) * STEP, sg.count, lane);
                 }
-                __syncthreads();
             }
+            const int cbase = c * STEP;
             const int pt = k + g;
             if (lane_ok && pt < q) {
-                const WT* w = &stw[(pt - cbase) * RS];
-                const WT vx = stv[pt - cbase] * w[a];
+                const WT* w = &stw[c & 1][(pt - cbase) * RS];
+                const WT vx = WT(stv[c & 1][pt - cbase]) * w[a];
                 WT wz[W];
 #pragma unroll
                 for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
@@ -160,7 +222,7 @@ __global__ __launch_bounds__(64) void k_spread_lane(const int32_t* __restrict__ 
             }
             ++zr;
         }
-        const WT* w = wts + gi * (3 * W);
+        const WT* w = wts + gi * rec_stride(W, int(sizeof(WT)));
         const WT v = WT(vs[gi]);
         WT wz[W];
 #pragma unroll
@@ -186,11 +248,13 @@ __global__ __launch_bounds__(64) void k_spread_lane(const int32_t* __restrict__ 
 // same element.
 template <class WT>
 __global__ __launch_bounds__(256) void k_fold_cols(const WinDev* __restrict__ wins, int32_t P,
-                                                   int64_t fold_total, const int2* __restrict__ fold,
+                                                   int64_t nlist, const int64_t* __restrict__ flist,
+                                                   const int2* __restrict__ fold,
                                                    const int64_t* __restrict__ sbase,
                                                    const WT* __restrict__ slab, WT* __restrict__ tgt) {
-    const int64_t f = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
-    if (f >= fold_total) return;
+    const int64_t fi = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+    if (fi >= nlist) return;
+    const int64_t f = flist[fi];
     int l = 0;
     while (l + 1 < P && wins[l + 1].fold_off <= f) ++l;
     const WinDev& wd = wins[l];
@@ -233,13 +297,15 @@ __global__ __launch_bounds__(256) void k_fold_cols(const WinDev* __restrict__ wi
 }
 
 // Fold step B fused with the y and z passes of the grid convolution. One block
-// per (x slice, window): the slice's cells are summed over the footprint
-// positions of their target line in (a, b) order, then T_y and T_z are applied
-// in LDS and the slice is written as g1[x][y][z].
-template <class WT>
-__global__ __launch_bounds__(256) void k_fold_conv_yz(const WinDev* __restrict__ wins,
-                                                      const double* __restrict__ tmat,
-                                                      const WT* __restrict__ tgt, WT* __restrict__ g1) {
+// per (x slice, window): each cell of the slice adds the footprint positions of
+// its target line in (a, b) order (only source columns that exist and whose
+// layer range covers the cell contribute), then T_y and T_z are applied in LDS
+// and the slice is written as g1[x][y][z].
+template <int W, class WT>
+__global__ __launch_bounds__(1024) void k_fold_conv_yz(const WinDev* __restrict__ wins,
+                                                       const double* __restrict__ tmat,
+                                                       const int2* __restrict__ crange,
+                                                       const WT* __restrict__ tgt, WT* __restrict__ g1) {
     extern __shared__ double sm[];
     const int l = blockIdx.y;
     const WinDev& wd = wins[l];
@@ -253,20 +319,35 @@ __global__ __launch_bounds__(256) void k_fold_conv_yz(const WinDev* __restrict__
     double* tz = ty + Ey * Ey; // T_z
     for (int e = threadIdx.x; e < Ey * Ey; e += blockDim.x) ty[e] = tmat[wd.t_off[1] + e];
     for (int e = threadIdx.x; e < Ez * Ez; e += blockDim.x) tz[e] = tmat[wd.t_off[2] + e];
-    const int cxmax = wd.nb[0];
+    const int wx = wd.Wslot[0], wy = wd.Wslot[1];
+    // layer ranges of the source columns this slice can see: cx in [x-W+1, x]
+    __shared__ int2 rng[W][64 + 1];
+    const int nby = wd.nb[1];
+    for (int e = threadIdx.x; e < W * nby; e += blockDim.x) {
+        const int a = e / nby, cy = e % nby, cx = x - a;
+        rng[a][cy] = (a < wx && cx >= 0 && cx < wd.nb[0]) ? crange[wd.col_off + int64_t(cx) * nby + cy]
+                                                          : make_int2(1, 0);
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < S; e += blockDim.x) {
         const int y = e / Ez, z = e % Ez;
         const WT* tl = tgt + wd.tgt_off + (int64_t(x) * Ey + y) * wd.lanes * Ez + z;
-        double acc = 0.0;
-        for (int a = 0; a < wd.Wslot[0]; ++a) {
-            const int cx = x - a;
-            if (cx < 0 || cx >= cxmax) continue;
-            for (int b = 0; b < wd.Wslot[1]; ++b) {
+        WT v[W][W];
+        bool ok[W][W];
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
                 const int cy = y - b;
-                if (cy < 0 || cy >= wd.nb[1]) continue;
-                acc += double(tl[int64_t(a * wd.Wslot[1] + b) * Ez]);
+                const int2 rr = (b < wy && cy >= 0 && cy < nby) ? rng[a][cy] : make_int2(1, 0);
+                ok[a][b] = z >= rr.x && z <= rr.y;
+                v[a][b] = tl[ok[a][b] ? int64_t(a * wy + b) * Ez : 0];
             }
-        }
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+            for (int b = 0; b < W; ++b) acc += ok[a][b] ? double(v[a][b]) : 0.0;
         s0[e] = acc;
     }
     __syncthreads();
@@ -356,11 +437,12 @@ __global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ w
                                                    const WT* __restrict__ h, int64_t N,
                                                    double* __restrict__ fs) {
     constexpr int G = 64 / W;
-    constexpr int REC = 3 * W;
+    constexpr int REC = rec_stride(W, int(sizeof(WT)));
     constexpr int CH = 64;
     constexpr int PADR = 16 / int(sizeof(WT));
     constexpr int RS = REC + PADR;
-    __shared__ WT stw[CH * RS];
+    constexpr int STEP = CH - G;
+    __shared__ WT stw[2][CH * RS];
     const int sid = wave_items[blockIdx.x];
     const Segment sg = segs[sid];
     const WinDev& wd = wins[sg.win];
@@ -378,25 +460,25 @@ __global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ w
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int b = 0; b < W; ++b) hr[b][c] = hp[int64_t(sg.z0 + c) * Ey + b];
-    int cbase = -CH;
+    int cc = -1;
+    stage_records_async<WT, REC, RS, CH>(stw[0], wts, base, 0, sg.count, lane);
     for (int z = sg.z0; z <= sg.z1; ++z) {
         const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
         for (int k = p; k < q; k += G) {
-            if (k + G > cbase + CH) {
+            const int c = k / STEP;
+            if (c > cc) {
+                wait_vmem();
                 __syncthreads();
-                cbase = k;
-                if (cbase + lane < sg.count) {
-                    const WT* r = wts + (base + cbase + lane) * REC;
-#pragma unroll
-                    for (int e = 0; e < REC; ++e) stw[lane * RS + e] = r[e];
-                }
-                __syncthreads();
+                cc = c;
+                if ((c + 1) * STEP < sg.count)
+                    stage_records_async<WT, REC, RS, CH>(stw[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
             }
+            const int cbase = c * STEP;
             const int pt = k + g;
             const bool act = lane_ok && pt < q;
             double part = 0.0;
             if (act) {
-                const WT* w = &stw[(pt - cbase) * RS];
+                const WT* w = &stw[c & 1][(pt - cbase) * RS];
                 WT wz[W];
 #pragma unroll
                 for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
@@ -468,7 +550,7 @@ __global__ __launch_bounds__(64) void k_gather_lane(const int32_t* __restrict__ 
             }
             ++zr;
         }
-        const WT* w = wts + gi * (3 * W);
+        const WT* w = wts + gi * rec_stride(W, int(sizeof(WT)));
         WT sy = WT(0);
 #pragma unroll
         for (int b = 0; b < WY; ++b) {
@@ -502,7 +584,8 @@ void run_matvec(Plan& pl, const double* x, double* y, WT* wts, WT* slab, WT* g, 
     if (prof) pl.record_stage_event(st);
     if (pl.nwave[3])
         hipLaunchKernelGGL((k_spread_grp<W, WT>), dim3(pl.nwave[3]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, wts, pl.vs.p, N, slab);
+                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, wts, pl.vs.p, N,
+                           slab, ca);
     if (pl.nwave[2])
         hipLaunchKernelGGL((k_spread_lane<W, W, WT>), dim3(pl.nwave[2]), dim3(64), 0, st,
                            pl.wave_items.p + pl.wave_off[2], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
@@ -510,13 +593,14 @@ void run_matvec(Plan& pl, const double* x, double* y, WT* wts, WT* slab, WT* g, 
         hipLaunchKernelGGL((k_spread_lane<W, 1, WT>), dim3(pl.nwave[1]), dim3(64), 0, st,
                            pl.wave_items.p + pl.wave_off[1], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_fold_cols<WT>, dim3(unsigned((pl.fold_total + 3) / 4)), dim3(256), 0, st, pl.wins_d.p,
-                       pl.P, pl.fold_total, pl.fold.p, pl.sbase.p, slab, ca);
+    if (pl.nflist)
+        hipLaunchKernelGGL(k_fold_cols<WT>, dim3(unsigned((pl.nflist + 3) / 4)), dim3(256), 0, st, pl.wins_d.p,
+                           pl.P, pl.nflist, pl.flist.p, pl.fold.p, pl.sbase.p, slab, ca);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_fold_conv_yz<WT>, dim3(unsigned(pl.emax[0]), unsigned(pl.P)), dim3(256),
+    hipLaunchKernelGGL((k_fold_conv_yz<W, WT>), dim3(unsigned(pl.emax[0]), unsigned(pl.P)), dim3(1024),
                        size_t(2 * pl.emax[1] * pl.emax[2] + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) *
                            sizeof(double),
-                       st, pl.wins_d.p, pl.tmat.p, ca, g);
+                       st, pl.wins_d.p, pl.tmat.p, pl.crange.p, ca, g);
     hipLaunchKernelGGL(k_conv_x<WT>, dim3(unsigned(pl.emax[1]), unsigned(pl.P)), dim3(256),
                        size_t(pl.emax[0] * pl.emax[2] + pl.emax[0] * pl.emax[0]) * sizeof(double), st, pl.wins_d.p,
                        pl.tmat.p, g, h);

@@ -153,8 +153,10 @@ __global__ void k_weights(const int32_t* __restrict__ perm, const int32_t* __res
     int64_t src = int64_t(l) * N + i;
     pos[src] = int32_t(t - int64_t(l) * N);
     zq[t] = q[src * 3 + 2] - qmin[l * 3 + 2];
+    const int RECG = rec_stride(W, int(sizeof(WT)));
+    for (int e = 3 * W; e < RECG; ++e) wts[t * RECG + e] = WT(0);
     for (int s = 0; s < 3; ++s) {
-        WT* w = wts + (t * 3 + s) * W;
+        WT* w = wts + t * RECG + s * W;
         if (wslot[l * 3 + s] == 1) {
             w[0] = WT(1);
             for (int a = 1; a < W; ++a) w[a] = WT(0);
@@ -176,7 +178,8 @@ inline unsigned nblocks(int64_t n, int t = kThreads) { return unsigned((n + t - 
 }  // namespace
 
 int64_t Plan::device_bytes() const {
-    return int64_t(wins_d.bytes() + sbase.bytes() + wave_items.bytes() + lstart.bytes() + lstart_off.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
+    return int64_t(wins_d.bytes() + sbase.bytes() + wave_items.bytes() + lstart.bytes() + lstart_off.bytes() +
+                   alone.bytes() + flist.bytes() + crange.bytes() + perm.bytes() + pos.bytes() + zq.bytes() + wts64.bytes() +
                    wts32.bytes() + segs.bytes() + fold.bytes() + tmat.bytes() + xw.bytes() +
                    vs.bytes() + fs.bytes() + g64.bytes() + h64.bytes() + c64a.bytes() +
                    c64b.bytes() + g32.bytes() + h32.bytes() + c32a.bytes() + c32b.bytes() +
@@ -345,6 +348,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     {
         const int64_t ey = pl->emax[1], ez = pl->emax[2], ex = pl->emax[0];
         const int64_t lds_yz = (2 * ey * ez + ey * ey + ez * ez) * 8, lds_x = (ex * ez + ex * ex) * 8;
+        for (int l = 0; l < P; ++l) ANV_CHECK(pl->wins_h[l].nb[1] <= 64, "occupied grid box too large");
         ANV_CHECK(lds_yz <= 65536 && lds_x <= 65536,
                   "occupied grid box too large for the LDS-resident grid step (reduce n_bw or raise eps_b)");
     }
@@ -386,12 +390,12 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     pl->zq.alloc(size_t(N) * P);
     const double bkb = M_PI * (2.0 - double(pl->prm.n_bw) / n_os);
     if (pl->precision == ANOVA_PREC_FP64) {
-        pl->wts64.alloc(size_t(N) * P * 3 * W);
+        pl->wts64.alloc(size_t(N) * P * rec_stride(W, 8));
         hipLaunchKernelGGL(k_weights<double>, dim3(nblocks(N * P)), dim3(kThreads), 0, st, pl->perm.p,
                            qbuf.p, tbuf.p, N, P, qmin_d.p, wsl_d.p, W, m, bkb, pl->pos.p, pl->zq.p,
                            pl->wts64.p);
     } else {
-        pl->wts32.alloc(size_t(N) * P * 3 * W);
+        pl->wts32.alloc(size_t(N) * P * rec_stride(W, 4));
         hipLaunchKernelGGL(k_weights<float>, dim3(nblocks(N * P)), dim3(kThreads), 0, st, pl->perm.p,
                            qbuf.p, tbuf.p, N, P, qmin_d.p, wsl_d.p, W, m, bkb, pl->pos.p, pl->zq.p,
                            pl->wts32.p);
@@ -402,11 +406,13 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     // 6. work items: runs of at most seg_points sorted points of one column, and
     //    for every (column, layer) the contiguous range of items that touch it
     std::vector<int2> fold_h;
-    int64_t slab_off = 0;
+    int64_t slab_off = 0, col_total = 0;
     for (int l = 0; l < P; ++l) {
         WinDev& wd = pl->wins_h[l];
         const int nbz = wd.nb[2], Ez = wd.E[2];
         const int64_t ncol = int64_t(wd.nb[0]) * wd.nb[1];
+        wd.col_off = col_total;
+        col_total += ncol;
         wd.fold_off = int64_t(fold_h.size());
         fold_h.resize(fold_h.size() + size_t(ncol) * Ez, int2{0, 0});
         const uint32_t* kk = ks.data() + size_t(l) * N;
@@ -490,6 +496,35 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
         if (lsv.empty()) lsv.push_back(0);
         upload(pl->lstart, lsv, st);
         upload(pl->lstart_off, lso, st);
+        // items alone in their column; fold entries of the other columns; column layer ranges
+        std::vector<uint8_t> al(pl->segs_h.size(), 0);
+        std::vector<int2> cr(size_t(col_total + 1), int2{1, 0});
+        std::vector<int64_t> fl;
+        size_t i0 = 0;
+        while (i0 < pl->segs_h.size()) {
+            size_t i1 = i0;
+            while (i1 < pl->segs_h.size() && pl->segs_h[i1].win == pl->segs_h[i0].win &&
+                   pl->segs_h[i1].col == pl->segs_h[i0].col)
+                ++i1;
+            const Segment& s0 = pl->segs_h[i0];
+            const WinDev& wd = pl->wins_h[s0.win];
+            int dw = 0;
+            for (int s2 = 0; s2 < 3; ++s2) dw += pl->slot_feat[s0.win][s2] >= 0;
+            const int64_t cidx = wd.col_off + s0.col;
+            if (dw == 3 && i1 - i0 == 1) {
+                al[i0] = 1;
+                cr[cidx] = int2{s0.z0, s0.z1 + W - 1};
+            } else {
+                cr[cidx] = int2{0, wd.E[2] - 1};
+                for (int L = 0; L < wd.E[2]; ++L) fl.push_back(wd.fold_off + int64_t(s0.col) * wd.E[2] + L);
+            }
+            i0 = i1;
+        }
+        upload(pl->alone, al, st);
+        pl->nflist = int64_t(fl.size());
+        if (fl.empty()) fl.push_back(0);
+        upload(pl->flist, fl, st);
+        upload(pl->crange, cr, st);
     }
     pl->slab_total = slab_off;
     pl->fold_total = int64_t(fold_h.size());
@@ -502,7 +537,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     upload(pl->wins_d, pl->wins_h, st);
 
     // 7. matvec scratch
-    pl->vs.alloc(size_t(N) * P);
+    pl->vs.alloc(size_t(N) * P + 2);  // two padding entries for the paired LDS staging
     pl->fs.alloc(size_t(N) * P);
     int64_t tgt_total = pl->grid_total;  // fold target-major buffer: cells x footprint positions
     {

@@ -39,6 +39,14 @@ struct Plan {
     // per 3-feature work item: start of each of its layers relative to its first point
     // (z1 - z0 + 2 entries), at lstart[lstart_off[item]]
     DevBuf<int32_t> lstart, lstart_off;
+    // per work item: 1 if it is the only item of its column (3-feature windows write
+    // such items straight into the fold's target-major buffer)
+    DevBuf<uint8_t> alone;
+    // fold entries (window, column, layer) that need the slab reduction, and per
+    // column the layers holding data in the target-major buffer (x > y = none)
+    DevBuf<int64_t> flist;
+    int64_t nflist = 0;
+    DevBuf<int2> crange;
     int64_t wave_off[4] = {0, 0, 0, 0};
     int32_t nwave[4] = {0, 0, 0, 0};
     int64_t fold_total = 0;
