@@ -61,11 +61,15 @@ typedef struct {
     int32_t reg_p;       /* smoothness of the regularisation; <= 0 picks per axis  */
     int32_t precision;   /* ANOVA_PREC_FP64 or ANOVA_PREC_MIXED                    */
     int32_t seg_points;  /* points per spreading work item; <= 0 = default         */
-    int32_t reserved;
+    int32_t batch_min_rhs; /* mixed precision with cutoff_m = 4 only: anova_matvec
+                            calls with R >= batch_min_rhs run the batched kernels
+                            (16 right-hand sides per pass, matrix-core spreading
+                            and gathering); 0 = default 2, < 0 = never        */
 } anova_opts;
 
 /* Fill `o` with the defaults: n_bw = 32, oversample = 2, cutoff_m = 4,
- * eps_b = 1/4, reg_p = 0 (automatic), precision = FP64. */
+ * eps_b = 1/4, reg_p = 0 (automatic), precision = FP64, seg_points = 0,
+ * batch_min_rhs = 0. */
 int anova_opts_default(anova_opts* o);
 
 /* Build a fast-summation plan for the ANOVA Gaussian kernel of Section 3:
@@ -92,7 +96,12 @@ int anova_plan_create(const double* X, int64_t N, int32_t d, int64_t ldx,
  * window is evaluated by NFFT fast summation (spread with the Kaiser-Bessel
  * window, grid convolution with the kernel's Fourier coefficients, gather)
  * and the windows are summed in FP64 in a fixed order, so results are
- * bitwise reproducible for a given plan and input.
+ * bitwise reproducible for a given plan, input and R. Mixed-precision plans
+ * with cutoff_m = 4 take R >= batch_min_rhs right-hand sides 16 at a time
+ * through the batched kernels (same algorithm and summation orders, FP32
+ * matrix-core contractions); their results agree with the one-at-a-time
+ * kernels to FP32 rounding, not bit for bit. The batched path allocates its
+ * scratch (about 16x the single-vector scratch) on first use.
  *   x   device, N x R FP64, column r at x + r*ldx_ (ldx_ >= N).
  *   y   device, N x R FP64 output, column r at y + r*ldy (ldy >= N); must not
  *       overlap x.
@@ -126,8 +135,9 @@ int anova_plan_info(anova_plan_t plan, anova_plan_info_t* info);
  *   0 permute input, 1 spread, 2 fold slabs, 3 grid convolution (3 axis
  *   passes), 4 gather, 5 window sum.
  * anova_profile_end synchronises on the last event and writes, for each
- * stage s < nstage, the mean duration per right-hand-side pass in ms
- * (stage_ms, host) and the number of passes measured (*passes, host).
+ * stage s < nstage, the mean duration per pass in ms (stage_ms, host) and
+ * the number of passes measured (*passes, host). A pass covers one
+ * right-hand side, or up to 16 in the batched path.
  * Errors: ANOVA_INVALID_ARG, ANOVA_HIP_ERROR. */
 #define ANOVA_NSTAGES 6
 int anova_profile_begin(anova_plan_t plan);

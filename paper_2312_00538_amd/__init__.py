@@ -37,7 +37,7 @@ class AnovaError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("version", ctypes.c_int32), ("n_bw", ctypes.c_int32), ("oversample", ctypes.c_int32),
                 ("cutoff_m", ctypes.c_int32), ("eps_b", ctypes.c_double), ("reg_p", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("seg_points", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("seg_points", ctypes.c_int32), ("batch_min_rhs", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):

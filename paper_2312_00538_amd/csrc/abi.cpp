@@ -48,6 +48,7 @@ int anova_opts_default(anova_opts* o) {
     o->reg_p = 0;
     o->precision = ANOVA_PREC_FP64;
     o->seg_points = 0;
+    o->batch_min_rhs = 0;
     return ANOVA_OK;
 }
 

@@ -670,6 +670,10 @@ int profile_end(Plan& pl, double* stage_ms, int nstage) {
 
 void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                     hipStream_t st) {
+    if (pl.batch_min_rhs > 0 && R >= pl.batch_min_rhs && batched_supported(pl)) {
+        enqueue_matvec_batched(pl, x, R, ldx, y, ldy, st);
+        return;
+    }
     for (int r = 0; r < R; ++r) {
         const double* xr = x + int64_t(r) * ldx;
         double* yr = y + int64_t(r) * ldy;

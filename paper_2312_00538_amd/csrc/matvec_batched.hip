@@ -1,0 +1,733 @@
+// Batched ANOVA-NFFT matvec: 16 right-hand sides per pass, FP32 grids and
+// weights, FP64 window sums (mixed precision). Same algorithm and the same
+// fixed summation orders as the single-vector path (matvec.hip); every array of
+// partial sums carries the 16 right-hand sides as its innermost index.
+//
+// For 3-feature windows (2m = 8 taps per axis) spreading and gathering are
+// dense contractions over the points of one grid layer and run on the matrix
+// cores (v_mfma_f32_16x16x4_f32):
+//   spread: T[(a, r)][(b, c)] += sum_p (v_{p,r} wx_p[a]) (wy_p[b] wz_p[c - z_p])
+//           M = 8 x-taps x 16 rhs, N = 8 y-taps x 8 z-cells, K = 4 points;
+//   gather: S[(a, r)][p] = sum_{(b,c)} h_r(a, b, c) (wy_p[b] wz_p[c - z_p]),
+//           f_{p,r} = sum_a wx_p[a] S[(a, r)][p]; M = 128, N = 16 points, K = 64.
+// The z-cells form a ring of 8 physical columns (cell z lives in column z & 7),
+// so advancing a layer is a flush (spread) or reload (gather) of one column.
+#include "plan.hpp"
+
+namespace anv {
+
+namespace {
+
+constexpr int RB = 16;  // right-hand sides per pass
+constexpr int kT = 256;
+inline unsigned nblk(int64_t n, int t = kT) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ inline void wait_vmem_b() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+__device__ inline void dma16(const void* src, void* lds) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                     (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+// xt[i][r] = x[i + r * ldx] in FP32 (zero for r >= R); 64 points per block,
+// transposed through LDS so that both the reads and the writes are coalesced.
+// Also resets the spread and gather work queues of the pass.
+__global__ __launch_bounds__(256) void k_transpose_in(const double* __restrict__ x, int R, int64_t ldx, int64_t N,
+                                                      float* __restrict__ xt, int32_t* __restrict__ queues) {
+    __shared__ float s[RB][65];
+    if (blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;  // work queues of this pass
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = j * 256 + threadIdx.x;
+        const int r = e / 64, i = e % 64;
+        s[r][i] = (r < R && i0 + i < N) ? float(x[i0 + i + int64_t(r) * ldx]) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = j * 256 + threadIdx.x;
+        const int i = e / RB, r = e % RB;
+        if (i0 + i < N) xt[(i0 + i) * RB + r] = s[r][i];
+    }
+}
+
+// vsb[g][.] = xt[perm[g]][.]: four lanes move one 64-byte row
+__global__ void k_permute_b(const float* __restrict__ xt, const int32_t* __restrict__ perm, int64_t NP,
+                            float* __restrict__ vsb) {
+    const int64_t t = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (t >= NP * 4) return;
+    const int64_t g = t / 4;
+    const int q = int(t % 4);
+    *reinterpret_cast<f4*>(vsb + g * RB + 4 * q) = *reinterpret_cast<const f4*>(xt + int64_t(perm[g]) * RB + 4 * q);
+}
+
+// LDS chunks of CHB = 32 consecutive points of a work item, moved by DMA (16
+// bytes per lane per instruction). A record occupies RPB = 32 floats: x taps,
+// y taps, z taps, and the z taps again, so that any 8 cyclically consecutive z
+// taps are 8 consecutive floats. A value row holds the point's 16 right-hand
+// sides. Slots past the item read its last point (finite data; callers mask).
+constexpr int CHB = 32;
+constexpr int RPB = 32;
+
+__device__ inline void stage_records(float* lrec, const float* __restrict__ wts, int64_t base, int cstart, int count,
+                                     int lane) {
+    const float* ub = wts + (base + cstart) * 24;  // uniform; lanes add small offsets
+    const int last = count - 1 - cstart;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {  // 8 records per 1 KB instruction
+        const int e = (lane % 8) * 4;
+        dma16(ub + min(j * 8 + lane / 8, last) * 24 + (e < 24 ? e : e - 8), lrec + j * 256);
+    }
+}
+
+__device__ inline void stage_values(float* lval, const float* __restrict__ vsb, int64_t base, int cstart, int count,
+                                    int lane) {
+    const float* ub = vsb + (base + cstart) * RB;
+    const int last = count - 1 - cstart;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)  // 16 rows per 1 KB instruction
+        dma16(ub + min(j * 16 + lane / 4, last) * RB + (lane % 4) * 4, lval + j * 256);
+}
+
+// LDS byte address of a pointer into shared memory (the low half of its flat address)
+__device__ inline uint32_t lds_addr(const void* p) { return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p)); }
+
+// Reads of staged chunk data. They are written as asm with the wait for their
+// own completion inside the block: the compiler would otherwise make every LDS
+// read wait for all DMA in flight, including the prefetch of the next chunk.
+// Chunk data are only read after the explicit wait at the chunk switch.
+__device__ inline void lds_spread_operands(uint32_t rec, uint32_t ywy, uint32_t ywz, uint32_t yv, f4& wx0, f4& wx1,
+                                           f4& wy, float& wz, float& v) {
+    asm volatile(
+        "ds_read_b128 %0, %5\n\t"
+        "ds_read_b128 %1, %5 offset:16\n\t"
+        "ds_read_b128 %2, %6\n\t"
+        "ds_read_b32 %3, %7\n\t"
+        "ds_read_b32 %4, %8\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx0), "=&v"(wx1), "=&v"(wy), "=&v"(wz), "=&v"(v)
+        : "v"(rec), "v"(ywy), "v"(ywz), "v"(yv)
+        : "memory");
+}
+
+__device__ inline void lds_gather_operands(uint32_t rec, uint32_t ywy, uint32_t ywz, f4& wx0, f4& wx1, float& wy0,
+                                           float& wy1, float (&wz)[8]) {
+    asm volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %12 offset:16\n\t"
+        "ds_read_b32 %2, %13\n\t"
+        "ds_read_b32 %3, %13 offset:16\n\t"
+        "ds_read_b32 %4, %14\n\t"
+        "ds_read_b32 %5, %14 offset:4\n\t"
+        "ds_read_b32 %6, %14 offset:8\n\t"
+        "ds_read_b32 %7, %14 offset:12\n\t"
+        "ds_read_b32 %8, %14 offset:16\n\t"
+        "ds_read_b32 %9, %14 offset:20\n\t"
+        "ds_read_b32 %10, %14 offset:24\n\t"
+        "ds_read_b32 %11, %14 offset:28\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx0), "=&v"(wx1), "=&v"(wy0), "=&v"(wy1), "=&v"(wz[0]), "=&v"(wz[1]), "=&v"(wz[2]), "=&v"(wz[3]),
+          "=&v"(wz[4]), "=&v"(wz[5]), "=&v"(wz[6]), "=&v"(wz[7])
+        : "v"(rec), "v"(ywy), "v"(ywz)
+        : "memory");
+}
+
+__device__ inline void lds_store_f4(uint32_t addr, f4 v) {
+    asm volatile("ds_write_b128 %0, %1" : : "v"(addr), "v"(v) : "memory");
+}
+
+__device__ inline void lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" : : : "memory"); }
+
+__device__ inline f4 lds_load_f4(uint32_t addr) {
+    f4 v;
+    asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr) : "memory");
+    return v;
+}
+
+// ---------------------------------------------------------------- spread (3 features, MFMA)
+// Lane = 16 lk + lr. Accumulator tile (mb, nb): rows (x tap a = mb, rhs r),
+// columns n = lr -> (y tap b = nb + 4 (lr / 8), physical z column lr % 8); the
+// lane holds rows r = 4 lk .. 4 lk + 3 of column lr. A step takes the points
+// k .. k+3 of one layer, point k + lk being k-index lk of the contraction.
+// Chunk c of the staged data serves the steps that start in [c STEP, (c+1) STEP).
+__global__ __launch_bounds__(64) void k_spread_mfma(const int32_t* __restrict__ wave_items, int32_t nitems,
+                                                    int32_t* __restrict__ queue,
+                                                    const Segment* __restrict__ segs,
+                                                    const int32_t* __restrict__ lstart,
+                                                    const int32_t* __restrict__ lstart_off,
+                                                    const WinDev* __restrict__ wins,
+                                                    const uint8_t* __restrict__ alone,
+                                                    const float* __restrict__ wts,
+                                                    const float* __restrict__ vsb, int64_t N,
+                                                    float* __restrict__ slab, float* __restrict__ tgt) {
+    constexpr int STEP = CHB - 4;
+    __shared__ __align__(16) float srec[2][CHB * RPB];
+    __shared__ __align__(16) float sval[2][CHB * RB];
+    __shared__ __align__(16) float stg[64 * RB];
+    const int lane = threadIdx.x;
+    // work items are taken in order (longest first) from a queue shared by the
+    // resident wavefronts, so that the matrix-core work evens out over the SIMDs
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(queue, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= nitems) break;
+        const int sid = wave_items[it];
+        const Segment sg = segs[sid];
+        const WinDev& wd = wins[sg.win];
+        const int lr = lane & 15, lk = lane >> 4;
+        const int64_t base = int64_t(sg.win) * N + sg.start;
+        const int32_t* ls = lstart + lstart_off[sid];
+        const bool direct = alone[sid] != 0;
+        const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+        const int E1 = wd.E[1], E2 = wd.E[2];
+        // Output element of footprint position (a, b) at layer L, as U(L) + a SA + b SB:
+        // fold target tgt[tgt_off + (((cx + a) E1 + cy + b) 64 + 8 a + b) E2 + L][r] for
+        // an item alone in its column, else its slab row [L - z0][8 a + b][r]
+        const int64_t SA = direct ? int64_t(64 * E1 + 8) * E2 : 8;
+        const int64_t SB = direct ? int64_t(65) * E2 : 1;
+        const int64_t U0 = direct ? wd.tgt_off + (int64_t(cx) * E1 + cy) * 64 * E2 : sg.off - int64_t(sg.z0) * 64;
+        const int64_t UL = direct ? 1 : 64;
+        float* const outp = direct ? tgt : slab;
+        f4 acc[32];
+#pragma unroll
+        for (int t = 0; t < 32; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+        // Write z cell `layer` and clear it. Its values sit in the lanes with
+        // lr % 8 == layer % 8; they go through LDS (rows [8 a + b][r]) so that
+        // the global stores are whole-wavefront: four lanes per 64-byte row.
+        const uint32_t stg0 = lds_addr(&stg[0]);
+        auto flush = [&](int layer) __attribute__((always_inline)) {
+            if ((lr & 7) == (layer & 7)) {
+#pragma unroll
+                for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb) {
+                        const int ab = mb * 8 + nb + 4 * (lr >> 3);
+                        lds_store_f4(stg0 + uint32_t(ab * RB + 4 * lk) * 4, acc[mb * 4 + nb]);
+                        acc[mb * 4 + nb] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+            }
+            lds_wait();
+            __syncthreads();
+            float* const row = outp + (U0 + int64_t(layer) * UL) * RB + 4 * (lane & 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ab = 16 * j + (lane >> 2);
+                const f4 v = lds_load_f4(stg0 + uint32_t(ab * RB + 4 * (lane & 3)) * 4);
+                *reinterpret_cast<f4*>(row + ((ab >> 3) * SA + (ab & 7) * SB) * RB) = v;
+            }
+        };
+        const uint32_t rec0 = lds_addr(&srec[0][0]), val0 = lds_addr(&sval[0][0]);
+        constexpr uint32_t RECB = CHB * RPB * 4, VALB = CHB * RB * 4;  // bytes per buffer
+        int cc = -1;
+        stage_records(srec[0], wts, base, 0, sg.count, lane);
+        stage_values(sval[0], vsb, base, 0, sg.count, lane);
+        for (int z = sg.z0; z <= sg.z1; ++z) {
+            const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+            for (int k = p; k < q; k += 4) {
+                const int c = k / STEP;
+                if (c > cc) {  // chunk c has landed (and earlier stores have drained); prefetch c + 1
+                    wait_vmem_b();
+                    __syncthreads();
+                    cc = c;
+                    if ((c + 1) * STEP < sg.count) {
+                        stage_records(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                        stage_values(sval[(c + 1) & 1], vsb, base, (c + 1) * STEP, sg.count, lane);
+                    }
+                }
+                const int pt = k + lk;
+                const uint32_t slot = uint32_t(pt - c * STEP);
+                const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + slot * (RPB * 4);
+                f4 wx0, wx1, wy;
+                float wz, v;
+                lds_spread_operands(rb, rb + 32 + 16 * uint32_t(lr >> 3), rb + 64 + 4 * uint32_t((lr - z) & 7),
+                                    val0 + uint32_t(c & 1) * VALB + (slot * RB + lr) * 4, wx0, wx1, wy, wz, v);
+                v = pt < q ? v : 0.0f;
+                const float bv[4] = {wy[0] * wz, wy[1] * wz, wy[2] * wz, wy[3] * wz};
+                const float av[8] = {v * wx0[0], v * wx0[1], v * wx0[2], v * wx0[3],
+                                     v * wx1[0], v * wx1[1], v * wx1[2], v * wx1[3]};
+    #pragma unroll
+                for (int mb = 0; mb < 8; ++mb)
+    #pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        acc[mb * 4 + nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[mb], bv[nb], acc[mb * 4 + nb], 0, 0, 0);
+            }
+            flush(z);
+        }
+        for (int j = 1; j < 8; ++j) flush(sg.z1 + j);
+    }
+}
+
+// ---------------------------------------------------------------- gather (3 features, MFMA)
+// S[(a, r)][p] = sum_K H[(a, r)][K] B[K][p] over K = 4 ks + lk <-> (z column
+// cp = ks / 2, y tap b = 4 (ks % 2) + lk); m-block mb is x tap a. A step takes
+// the 16 points k .. k+15 of one layer (column lr of B and of S). The ring
+// holds layer z0 + ((cp - z0) mod 8) in column cp; after layer z the column
+// z mod 8 is refilled with layer z + 8 from registers loaded a layer ahead.
+__global__ __launch_bounds__(64) void k_gather_mfma(const int32_t* __restrict__ wave_items, int32_t nitems,
+                                                    int32_t* __restrict__ queue,
+                                                    const Segment* __restrict__ segs,
+                                                    const int32_t* __restrict__ lstart,
+                                                    const int32_t* __restrict__ lstart_off,
+                                                    const WinDev* __restrict__ wins,
+                                                    const float* __restrict__ wts,
+                                                    const float* __restrict__ h, int64_t N,
+                                                    float* __restrict__ fs) {
+    constexpr int STEP = CHB - 16;
+    __shared__ __align__(16) float srec[2][CHB * RPB];
+    const int lane = threadIdx.x;
+    // work items are taken in order (longest first) from a queue shared by the
+    // resident wavefronts, so that the matrix-core work evens out over the SIMDs
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(queue, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= nitems) break;
+        const int sid = wave_items[it];
+        const Segment sg = segs[sid];
+        const WinDev& wd = wins[sg.win];
+        const int lr = lane & 15, lk = lane >> 4;
+        const int64_t base = int64_t(sg.win) * N + sg.start;
+        const int32_t* ls = lstart + lstart_off[sid];
+        const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+        const int Ey = wd.E[1], Ez = wd.E[2];
+        // h[x][z][y][r]: grid cell (cx + a, cy + b, layer), rhs lr
+        const float* hp = h + (wd.grid_off + int64_t(cx) * Ez * Ey + cy) * RB + lr;
+        float H[8][16];
+    #pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int cp = ks / 2, b = 4 * (ks % 2) + lk;
+            const int layer = sg.z0 + ((cp - sg.z0) & 7);
+    #pragma unroll
+            for (int mb = 0; mb < 8; ++mb) H[mb][ks] = hp[((int64_t(mb) * Ez + layer) * Ey + b) * RB];
+        }
+        float pre[8][2];
+        if (sg.z0 < sg.z1) {
+    #pragma unroll
+            for (int mb = 0; mb < 8; ++mb) {
+                pre[mb][0] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + lk) * RB];
+                pre[mb][1] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + 4 + lk) * RB];
+            }
+        }
+        const uint32_t rec0 = lds_addr(&srec[0][0]);
+        constexpr uint32_t RECB = CHB * RPB * 4;
+        int cc = -1;
+        stage_records(srec[0], wts, base, 0, sg.count, lane);
+        for (int z = sg.z0; z <= sg.z1; ++z) {
+            const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+            for (int k = p; k < q; k += 16) {
+                const int c = k / STEP;
+                if (c > cc) {
+                    wait_vmem_b();
+                    __syncthreads();
+                    cc = c;
+                    if ((c + 1) * STEP < sg.count) stage_records(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                }
+                const int pt = k + lr;
+                const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + uint32_t(pt - c * STEP) * (RPB * 4);
+                f4 wx0, wx1;
+                float wy0, wy1, wzr[8];  // wzr[cp]: z tap of the ring cell in column cp
+                lds_gather_operands(rb, rb + 32 + 4 * uint32_t(lk), rb + 64 + 4 * uint32_t((-z) & 7), wx0, wx1, wy0, wy1,
+                                    wzr);
+                f4 D[8];
+    #pragma unroll
+                for (int mb = 0; mb < 8; ++mb) D[mb] = f4{0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+                for (int ks = 0; ks < 16; ++ks) {
+                    const float bv = (ks % 2 ? wy1 : wy0) * wzr[ks / 2];
+    #pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) D[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(H[mb][ks], bv, D[mb], 0, 0, 0);
+                }
+                if (pt < q) {  // the lane holds S[(a, r = 4 lk + i)][point lr]
+                    f4 f = wx0[0] * D[0];
+                    f += wx0[1] * D[1];
+                    f += wx0[2] * D[2];
+                    f += wx0[3] * D[3];
+                    f += wx1[0] * D[4];
+                    f += wx1[1] * D[5];
+                    f += wx1[2] * D[6];
+                    f += wx1[3] * D[7];
+                    *reinterpret_cast<f4*>(fs + (base + pt) * RB + 4 * lk) = f;
+                }
+            }
+            if (z < sg.z1) {  // column z mod 8 takes layer z + 8; load layer z + 9 for the next column
+                const int cpz = z & 7;
+    #pragma unroll
+                for (int ks = 0; ks < 16; ++ks)
+                    if (ks / 2 == cpz) {
+    #pragma unroll
+                        for (int mb = 0; mb < 8; ++mb) H[mb][ks] = pre[mb][ks % 2];
+                    }
+                if (z + 1 < sg.z1) {
+    #pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) {
+                        pre[mb][0] = hp[((int64_t(mb) * Ez + z + 9) * Ey + lk) * RB];
+                        pre[mb][1] = hp[((int64_t(mb) * Ez + z + 9) * Ey + 4 + lk) * RB];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- 1 and 2 features: one lane per (item, rhs)
+template <int W, int WY>
+__global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict__ items, int nitems,
+                                                      const Segment* __restrict__ segs,
+                                                      const int32_t* __restrict__ zq,
+                                                      const float* __restrict__ wts,
+                                                      const float* __restrict__ vsb, int64_t N,
+                                                      float* __restrict__ slab) {
+    const int64_t t = blockIdx.x * int64_t(64) + threadIdx.x;
+    if (t >= int64_t(nitems) * RB) return;
+    const int sid = items[t / RB];
+    const int r = int(t % RB);
+    if (sid < 0) return;
+    const Segment sg = segs[sid];
+    const int64_t base = int64_t(sg.win) * N + sg.start;
+    constexpr int REC = rec_stride(W, 4);
+    float acc[WY][W];
+#pragma unroll
+    for (int b = 0; b < WY; ++b)
+#pragma unroll
+        for (int c = 0; c < W; ++c) acc[b][c] = 0.f;
+    int zr = sg.z0;
+    for (int k = 0; k < sg.count; ++k) {
+        const int64_t gi = base + k;
+        const int zj = zq[gi];
+        while (zr < zj) {
+#pragma unroll
+            for (int b = 0; b < WY; ++b) slab[(sg.off + int64_t(zr - sg.z0) * WY + b) * RB + r] = acc[b][0];
+#pragma unroll
+            for (int b = 0; b < WY; ++b) {
+#pragma unroll
+                for (int c = 0; c < W - 1; ++c) acc[b][c] = acc[b][c + 1];
+                acc[b][W - 1] = 0.f;
+            }
+            ++zr;
+        }
+        const float* w = wts + gi * REC;
+        const float v = vsb[gi * RB + r];
+#pragma unroll
+        for (int b = 0; b < WY; ++b) {
+            const float cb = v * w[W + b];
+#pragma unroll
+            for (int c = 0; c < W; ++c) acc[b][c] += cb * w[2 * W + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b) slab[(sg.off + int64_t(zr - sg.z0 + c) * WY + b) * RB + r] = acc[b][c];
+}
+
+template <int W, int WY>
+__global__ __launch_bounds__(64) void k_gather_lane_b(const int32_t* __restrict__ items, int nitems,
+                                                      const Segment* __restrict__ segs,
+                                                      const WinDev* __restrict__ wins,
+                                                      const int32_t* __restrict__ zq,
+                                                      const float* __restrict__ wts,
+                                                      const float* __restrict__ h, int64_t N,
+                                                      float* __restrict__ fs) {
+    const int64_t t = blockIdx.x * int64_t(64) + threadIdx.x;
+    if (t >= int64_t(nitems) * RB) return;
+    const int sid = items[t / RB];
+    const int r = int(t % RB);
+    if (sid < 0) return;
+    const Segment sg = segs[sid];
+    const WinDev& wd = wins[sg.win];
+    const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+    const int Ey = wd.E[1];
+    const float* hp = h + (wd.grid_off + int64_t(cx) * wd.E[2] * Ey + cy) * RB + r;
+    const int64_t base = int64_t(sg.win) * N + sg.start;
+    constexpr int REC = rec_stride(W, 4);
+    float hr[WY][W];
+    int zr = sg.z0;
+#pragma unroll
+    for (int c = 0; c < W; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b) hr[b][c] = hp[(int64_t(zr + c) * Ey + b) * RB];
+    for (int k = 0; k < sg.count; ++k) {
+        const int64_t gi = base + k;
+        const int zj = zq[gi];
+        while (zr < zj) {
+#pragma unroll
+            for (int b = 0; b < WY; ++b) {
+#pragma unroll
+                for (int c = 0; c < W - 1; ++c) hr[b][c] = hr[b][c + 1];
+                hr[b][W - 1] = hp[(int64_t(zr + W) * Ey + b) * RB];
+            }
+            ++zr;
+        }
+        const float* w = wts + gi * REC;
+        float sy = 0.f;
+#pragma unroll
+        for (int b = 0; b < WY; ++b) {
+            float s = 0.f;
+#pragma unroll
+            for (int c = 0; c < W; ++c) s += w[2 * W + c] * hr[b][c];
+            sy += w[W + b] * s;
+        }
+        fs[gi * RB + r] = sy;
+    }
+}
+
+// ---------------------------------------------------------------- fold and grid step, 16 rhs innermost
+__global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ wins, int32_t P, int64_t nlist,
+                                                     const int64_t* __restrict__ flist, const int2* __restrict__ fold,
+                                                     const int64_t* __restrict__ sbase, const float* __restrict__ slab,
+                                                     float* __restrict__ tgt) {
+    const int64_t fi = blockIdx.x;
+    if (fi >= nlist) return;
+    const int64_t f = flist[fi];
+    int l = 0;
+    while (l + 1 < P && wins[l + 1].fold_off <= f) ++l;
+    const WinDev& wd = wins[l];
+    const int lane = threadIdx.x / 4, q4 = threadIdx.x % 4;  // footprint position, rhs quad
+    if (lane >= wd.lanes) return;
+    const int64_t fl = f - wd.fold_off;
+    const int L = int(fl % wd.E[2]);
+    const int64_t col = fl / wd.E[2];
+    const int cx = int(col / wd.nb[1]), cy = int(col % wd.nb[1]);
+    const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
+    const int2 rr = fold[f];
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int s = rr.x; s < rr.y; ++s) {
+        const f4 v = *reinterpret_cast<const f4*>(slab + (sbase[s] + int64_t(L) * wd.lanes + lane) * RB + 4 * q4);
+        s0 += v[0];
+        s1 += v[1];
+        s2 += v[2];
+        s3 += v[3];
+    }
+    const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + lane) * wd.E[2] + L;
+    *reinterpret_cast<f4*>(tgt + (wd.tgt_off + t) * RB + 4 * q4) = f4{float(s0), float(s1), float(s2), float(s3)};
+}
+
+// fold step B + y and z passes; block per (x slice, window, half of the rhs)
+template <int W>
+__global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restrict__ wins,
+                                                         const double* __restrict__ tmat,
+                                                         const int2* __restrict__ crange,
+                                                         const float* __restrict__ tgt, float* __restrict__ g1,
+                                                         int RH) {
+    extern __shared__ float smf[];
+    const int l = blockIdx.y;
+    const WinDev& wd = wins[l];
+    const int x = blockIdx.x;
+    const int r0 = blockIdx.z * RH;
+    if (x >= wd.E[0]) return;
+    const int Ey = wd.E[1], Ez = wd.E[2];
+    const int S = Ey * Ez;
+    float* s0 = smf;            // [y][z][RH]
+    float* s1 = smf + S * RH;
+    float* ty = s1 + S * RH;
+    float* tz = ty + Ey * Ey;
+    for (int e = threadIdx.x; e < Ey * Ey; e += blockDim.x) ty[e] = float(tmat[wd.t_off[1] + e]);
+    for (int e = threadIdx.x; e < Ez * Ez; e += blockDim.x) tz[e] = float(tmat[wd.t_off[2] + e]);
+    __shared__ int2 rng[W][65];
+    const int wx = wd.Wslot[0], wy = wd.Wslot[1], nby = wd.nb[1];
+    for (int e = threadIdx.x; e < W * nby; e += blockDim.x) {
+        const int a = e / nby, cyy = e % nby, cxx = x - a;
+        rng[a][cyy] = (a < wx && cxx >= 0 && cxx < wd.nb[0]) ? crange[wd.col_off + int64_t(cxx) * nby + cyy]
+                                                            : make_int2(1, 0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
+        const int cell = e / RH, r = e % RH;
+        const int y = cell / Ez, zz = cell % Ez;
+        const float* tl = tgt + (wd.tgt_off + (int64_t(x) * Ey + y) * wd.lanes * Ez + zz) * RB + r0 + r;
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const int cyy = y - b;
+                const int2 rr = (b < wy && cyy >= 0 && cyy < nby) ? rng[a][cyy] : make_int2(1, 0);
+                const bool ok = zz >= rr.x && zz <= rr.y;
+                const float v = tl[ok ? int64_t(a * wy + b) * Ez * RB : 0];
+                acc += ok ? v : 0.f;
+            }
+        s0[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
+        const int cell = e / RH, r = e % RH;
+        const int y = cell / Ez, zz = cell % Ez;
+        float acc = 0.f;
+        for (int k = 0; k < Ey; ++k) acc += ty[y * Ey + k] * s0[(k * Ez + zz) * RH + r];
+        s1[e] = acc;
+    }
+    __syncthreads();
+    float* out = g1 + (wd.grid_off + int64_t(x) * S) * RB + r0;
+    for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
+        const int cell = e / RH, r = e % RH;
+        const int y = cell / Ez, zz = cell % Ez;
+        float acc = 0.f;
+        for (int k = 0; k < Ez; ++k) acc += tz[zz * Ez + k] * s1[(y * Ez + k) * RH + r];
+        out[int64_t(cell) * RB + r] = acc;
+    }
+}
+
+// x pass; block per (y slice, window, rhs half); output h[x][z][y][rhs]
+__global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
+                                                   const float* __restrict__ g1, float* __restrict__ h, int RH) {
+    extern __shared__ float smf[];
+    const int l = blockIdx.y;
+    const WinDev& wd = wins[l];
+    const int y = blockIdx.x;
+    const int r0 = blockIdx.z * RH;
+    if (y >= wd.E[1]) return;
+    const int Ex = wd.E[0], Ey = wd.E[1], Ez = wd.E[2];
+    float* sl = smf;                 // [x][z][RH]
+    float* tx = smf + Ex * Ez * RH;
+    for (int e = threadIdx.x; e < Ex * Ex; e += blockDim.x) tx[e] = float(tmat[wd.t_off[0] + e]);
+    for (int e = threadIdx.x; e < Ex * Ez * RH; e += blockDim.x) {
+        const int xz = e / RH, r = e % RH;
+        const int xx = xz / Ez, zz = xz % Ez;
+        sl[e] = g1[(wd.grid_off + (int64_t(xx) * Ey + y) * Ez + zz) * RB + r0 + r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < Ex * Ez * RH; e += blockDim.x) {
+        const int xz = e / RH, r = e % RH;
+        const int xx = xz / Ez, zz = xz % Ez;
+        float acc = 0.f;
+        for (int k = 0; k < Ex; ++k) acc += tx[xx * Ex + k] * sl[(k * Ez + zz) * RH + r];
+        h[(wd.grid_off + (int64_t(xx) * Ez + zz) * Ey + y) * RB + r0 + r] = acc;
+    }
+}
+
+// y[i + r ldy] = sum_l eta_l f_l(i, r), windows in order, FP64; 64 points per
+// block, transposed through LDS for column-major stores
+__global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ fs, const int32_t* __restrict__ pos,
+                                                      const WinDev* __restrict__ wins, int32_t P, int64_t N, int R,
+                                                      double* __restrict__ y, int64_t ldy) {
+    __shared__ double s[RB][65];
+    const int64_t i0 = int64_t(blockIdx.x) * 64;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = j * 256 + threadIdx.x;
+        const int i = e / RB, r = e % RB;
+        double acc = 0.0;
+        if (i0 + i < N)
+            for (int l = 0; l < P; ++l)
+                acc += wins[l].eta * double(fs[(int64_t(l) * N + pos[int64_t(l) * N + i0 + i]) * RB + r]);
+        s[r][i] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = j * 256 + threadIdx.x;
+        const int r = e / 64, i = e % 64;
+        if (r < R && i0 + i < N) y[i0 + i + int64_t(r) * ldy] = s[r][i];
+    }
+}
+
+}  // namespace
+
+bool batched_supported(const Plan& pl) { return pl.precision == ANOVA_PREC_MIXED && pl.W == 8; }
+
+void ensure_batched_buffers(Plan& pl) {
+    if (pl.b_ready) return;
+    pl.xtb.alloc(size_t(pl.N) * RB);
+    pl.vsb.alloc(size_t(pl.N) * pl.P * RB);
+    pl.fsb.alloc(size_t(pl.N) * pl.P * RB);
+    pl.slabb.alloc(size_t(pl.slab_total) * RB + RB);
+    pl.tgtb.alloc(size_t(pl.c32a.n) * RB);
+    pl.g1b.alloc(size_t(pl.grid_total) * RB);
+    pl.hb.alloc(size_t(pl.grid_total) * RB);
+    // items of 1- and 2-feature windows as flat lists (lane kernels take (item, rhs) per lane)
+    std::vector<int32_t> it2, it1;
+    for (size_t i = 0; i < pl.segs_h.size(); ++i) {
+        int l = pl.segs_h[i].win;
+        int dw = 0;
+        for (int s2 = 0; s2 < 3; ++s2) dw += pl.slot_feat[l][s2] >= 0;
+        if (dw == 2) it2.push_back(int32_t(i));
+        if (dw == 1) it1.push_back(int32_t(i));
+    }
+    pl.nb_items2 = int32_t(it2.size());
+    pl.nb_items1 = int32_t(it1.size());
+    it2.insert(it2.end(), it1.begin(), it1.end());
+    if (it2.empty()) it2.push_back(-1);
+    pl.b_items.alloc(it2.size());
+    ANV_HIP(hipMemcpy(pl.b_items.p, it2.data(), it2.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    // persistent grids of the matrix-core kernels: as many wavefronts as fit at once
+    pl.b_queue.alloc(2);
+    {
+        int dev = 0, ncu = 0, bs = 0, bg = 0;
+        ANV_HIP(hipGetDevice(&dev));
+        ANV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma, 64, 0));
+        ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma, 64, 0));
+        pl.b_grid[0] = std::max(1, std::min(pl.nwave[3], std::max(1, bs) * ncu));
+        pl.b_grid[1] = std::max(1, std::min(pl.nwave[3], std::max(1, bg) * ncu));
+    }
+    // right-hand sides per grid-step block: as many as the LDS budget allows
+    const int64_t ex = pl.emax[0], ey = pl.emax[1], ez = pl.emax[2];
+    pl.b_rsplit = 1;
+    while (pl.b_rsplit < RB && ((2 * ey * ez * (RB / pl.b_rsplit) + ey * ey + ez * ez) * 4 > 65536 ||
+                                (ex * ez * (RB / pl.b_rsplit) + ex * ex) * 4 > 65536))
+        pl.b_rsplit *= 2;
+    pl.b_ready = true;
+}
+
+void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
+    ensure_batched_buffers(pl);
+    const int64_t N = pl.N, NP = pl.N * pl.P;
+    for (int r0 = 0; r0 < R; r0 += RB) {
+        const int rn = std::min(RB, R - r0);
+        const double* xr = x + int64_t(r0) * ldx;
+        double* yr = y + int64_t(r0) * ldy;
+        const bool prof = pl.profiling;
+        if (prof) pl.record_stage_event(st);
+        hipLaunchKernelGGL(k_transpose_in, dim3(nblk(N, 64)), dim3(256), 0, st, xr, rn, ldx, N, pl.xtb.p,
+                           pl.b_queue.p);
+        hipLaunchKernelGGL(k_permute_b, dim3(nblk(NP * 4)), dim3(kT), 0, st, pl.xtb.p, pl.perm.p, NP, pl.vsb.p);
+        if (prof) pl.record_stage_event(st);
+        if (pl.nwave[3])
+            hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, pl.wts32.p, pl.vsb.p,
+                               N, pl.slabb.p, pl.tgtb.p);
+        if (pl.nb_items2)
+            hipLaunchKernelGGL((k_spread_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.vsb.p, N, pl.slabb.p);
+        if (pl.nb_items1)
+            hipLaunchKernelGGL((k_spread_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.vsb.p, N,
+                               pl.slabb.p);
+        if (prof) pl.record_stage_event(st);
+        if (pl.nflist)
+            hipLaunchKernelGGL(k_fold_cols_b, dim3(unsigned(pl.nflist)), dim3(256), 0, st, pl.wins_d.p, pl.P, pl.nflist,
+                               pl.flist.p, pl.fold.p, pl.sbase.p, pl.slabb.p, pl.tgtb.p);
+        if (prof) pl.record_stage_event(st);
+        const int RH = RB / pl.b_rsplit;
+        const size_t lds_yz =
+            size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) * sizeof(float);
+        hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(unsigned(pl.emax[0]), unsigned(pl.P), unsigned(pl.b_rsplit)),
+                           dim3(1024), lds_yz, st, pl.wins_d.p, pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH);
+        const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pl.emax[0]) * sizeof(float);
+        hipLaunchKernelGGL(k_conv_x_b, dim3(unsigned(pl.emax[1]), unsigned(pl.P), unsigned(pl.b_rsplit)), dim3(1024),
+                           lds_x, st, pl.wins_d.p, pl.tmat.p, pl.g1b.p, pl.hb.p, RH);
+        if (prof) pl.record_stage_event(st);
+        if (pl.nwave[3])
+            hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.wts32.p, pl.hb.p, N, pl.fsb.p);
+        if (pl.nb_items2)
+            hipLaunchKernelGGL((k_gather_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p, pl.hb.p, N,
+                               pl.fsb.p);
+        if (pl.nb_items1)
+            hipLaunchKernelGGL((k_gather_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p,
+                               pl.hb.p, N, pl.fsb.p);
+        if (prof) pl.record_stage_event(st);
+        hipLaunchKernelGGL(k_window_sum_b, dim3(nblk(N, 64)), dim3(256), 0, st, pl.fsb.p, pl.pos.p, pl.wins_d.p, pl.P,
+                           N, rn, yr, ldy);
+        if (prof) pl.record_stage_event(st);
+        ANV_HIP(hipGetLastError());
+    }
+}
+
+}  // namespace anv

@@ -183,7 +183,8 @@ int64_t Plan::device_bytes() const {
                    wts32.bytes() + segs.bytes() + fold.bytes() + tmat.bytes() + xw.bytes() +
                    vs.bytes() + fs.bytes() + g64.bytes() + h64.bytes() + c64a.bytes() +
                    c64b.bytes() + g32.bytes() + h32.bytes() + c32a.bytes() + c32b.bytes() +
-                   slab64.bytes() + slab32.bytes());
+                   slab64.bytes() + slab32.bytes() + xtb.bytes() + vsb.bytes() + fsb.bytes() + slabb.bytes() +
+                   tgtb.bytes() + g1b.bytes() + hb.bytes() + b_items.bytes() + b_queue.bytes());
 }
 
 Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows,
@@ -218,6 +219,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
     pl->W = 2 * o.cutoff_m;
     pl->precision = o.precision;
     pl->seg_points = o.seg_points > 0 ? o.seg_points : 768;
+    pl->batch_min_rhs = o.batch_min_rhs == 0 ? 2 : o.batch_min_rhs;
     const int W = pl->W, m = pl->prm.m, n_os = pl->prm.n_os;
     pl->win.assign(windows, windows + 3 * P);
     pl->sigma.assign(sigma, sigma + P);

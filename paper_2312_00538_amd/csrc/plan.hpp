@@ -67,6 +67,18 @@ struct Plan {
     DevBuf<double> slab64;
     DevBuf<float> slab32;
 
+    // batched path (16 right-hand sides per pass, mixed precision), allocated on
+    // first use: inputs [N][16] and [P*N][16], slabs, fold targets, grids and
+    // gathered values, each with the 16 right-hand sides innermost
+    int32_t batch_min_rhs = 2;
+    bool b_ready = false;
+    int32_t b_rsplit = 2;       // grid-step blocks per slice (right-hand sides split for LDS)
+    DevBuf<float> xtb, vsb, fsb, slabb, tgtb, g1b, hb;
+    DevBuf<int32_t> b_items;    // work items of 2-feature then 1-feature windows
+    DevBuf<int32_t> b_queue;    // work-queue counters of the matrix-core spread and gather
+    int32_t b_grid[2] = {1, 1}; // their persistent grid sizes
+    int32_t nb_items2 = 0, nb_items1 = 0;
+
     // stage timing (measurement hook)
     bool profiling = false;
     std::vector<hipEvent_t> events;
@@ -85,6 +97,12 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
 // y[:, r] = K x[:, r] for r < R (device pointers, column-major with leading dims).
 void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                     hipStream_t stream);
+
+// The 16-wide batched kernels (matvec_batched.hip): used by enqueue_matvec for
+// R >= batch_min_rhs when batched_supported(pl).
+bool batched_supported(const Plan& pl);
+void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
+                            hipStream_t stream);
 
 void profile_begin(Plan& pl);
 int profile_end(Plan& pl, double* stage_ms, int nstage);  // returns passes measured
