@@ -1,22 +1,30 @@
 #!/usr/bin/env python3
-"""Benchmark of the ANOVA-NFFT kernel matvec on one MI355X.
+"""Benchmark of the ANOVA-NFFT kernel matvec and the IPM solve on one MI355X.
 
-Workload: N = 100000 points, d = 30 standardized two-class Gaussian-mixture
-features (means +-0.5 e, unit covariance; a synthetic stand-in for the paper's
-HIGGS-sized problems), 10 windows of 3 consecutive features, sigma = 1,
-NFFT bandwidth 32 per axis, oversampling 2, Kaiser-Bessel cutoff m = 4.
-One step = one full matvec y = sum_l K_l x over all windows for the batch of
-right-hand sides. Metric: points * windows / s at relative l2 error <= 1e-4
-(checked each run on sampled rows against the FP64 direct-sum oracle).
+Workload (matvec): N = 100000 points, d = 30 standardized two-class
+Gaussian-mixture features (means +-0.5 e, unit covariance; a synthetic
+stand-in for the paper's HIGGS-sized problems), 10 windows of 3 consecutive
+features, sigma = 1, NFFT bandwidth 32 per axis, oversampling 2,
+Kaiser-Bessel cutoff m = 4, 16 right-hand sides. One step = one full matvec
+Y = sum_l K_l X over all windows for the 16 right-hand sides, inputs and
+outputs resident in HBM (column-major FP64). Headline: the batched
+mixed-precision path (FP32 weights, grids and matrix-core contractions, FP64
+window sums). The FP64 and mixed one-vector forms on the same GPU are reported
+beside it. Accuracy is checked every run on sampled rows against the FP64
+direct-sum oracle; a run above relative l2 error 1e-4 reports value 0.
 
-Prints ONE JSON line (rank 0). --gpus above 1 is refused: this build runs on a
-single GPU.
+Also reported: IPM solve latency p50/p99 for the small plain problem and the
+full N = 500000 problem, and the oracle's rate on the host cores.
+
+Prints ONE JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,8 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6     # FP64 vector and FP64 MFMA
+FP32_PEAK_TFLOPS = 157.3    # FP32 vector and FP32 MFMA (dense)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_matvec_scaling_r16_hbm_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2312_00538_amd", "csrc", "matvec_batched.hip")
 
 
 def parse():
@@ -35,16 +45,64 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rhs", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--rhs", type=int, default=16)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--N", type=int, default=100_000)
+    ap.add_argument("--reference-steps", type=int, default=30,
+                    help="timed steps of the one-vector FP64 and mixed forms (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--check-rows", type=int, default=128)
     ap.add_argument("--ipm-small-solves", type=int, default=20)
     ap.add_argument("--ipm-full-solves", type=int, default=5)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 256 MiB device-to-device three times (a known-size "
+                         "reference for hardware byte counters)")
     return ap.parse_args()
+
+
+def colmajor(torch, a, dev):
+    """(N, R) array -> device FP64 buffer holding column r at offset r * N."""
+    a = np.asarray(a, dtype=np.float64).reshape(a.shape[0], -1)
+    return torch.as_tensor(np.ascontiguousarray(a.T), device=dev)   # R x N contiguous
+
+
+def time_matvec(lib, torch, plan, xb, yb, N, R, steps, warmup):
+    """Mean wall time per matvec over `steps` calls (synchronised on both
+    sides) and the per-stage means from the library's stage events."""
+    for _ in range(warmup):
+        plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
+    torch.cuda.synchronize()
+    plan.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    stages, passes = plan.profile_end()
+    return el / steps, stages, passes
+
+
+def sampled_error(p, y_rows, rows, R):
+    import oracle
+    ref = oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, :R], rows=rows)
+    return max(float(np.linalg.norm(y_rows[:, r] - ref[:, r]) / np.linalg.norm(ref[:, r])) for r in range(R))
+
+
+def traffic_record():
+    """HBM bytes per launch of the batched kernels, from the committed rocprofv3
+    counter summary, if that summary was taken from the current kernel source."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic-data:\s*(\{.*\})", txt)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    return rec if rec.get("source_sha256") == sha else None
 
 
 def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
@@ -76,17 +134,17 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
             "ip_iters_p50": float(np.percentile([s["ip_iters"] for s in stats], 50)),
             "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
             "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
-            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom"}[precond]}
+            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom"}[precond], "precision": "fp64"}
 
 
 def cpu_baseline(p, seconds):
     """The oracle (FP64 direct sum, C + OpenMP) on a bounded sample of target
-    rows of the same workload; scaled to points*windows/s of a full matvec."""
+    rows of the same workload (one right-hand side), scaled to
+    points*windows/s of a full matvec."""
     import oracle
     P = p.windows.shape[0]
     N = p.X.shape[0]
-    rng = np.random.default_rng(7)
-    order = rng.permutation(N)
+    order = np.random.default_rng(7).permutation(N)
     done, t0, chunk = 0, time.perf_counter(), 512
     while True:
         rows = order[done:done + chunk]
@@ -97,8 +155,8 @@ def cpu_baseline(p, seconds):
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": done * P / el, "unit": "points*windows/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} of {N} target rows x all {N} sources x {P} windows (FP64 direct sum), "
-                      f"{el:.1f} s; full-matvec rate = rows * windows / time"}
+            "sample": f"{done} of {N} target rows x all {N} sources x {P} windows, one right-hand side "
+                      f"(FP64 direct sum), {el:.1f} s; full-matvec rate = rows * windows / time"}
 
 
 def main():
@@ -108,15 +166,14 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
-    import oracle
     import workloads
     import paper_2312_00538_amd as lib
 
     dev = torch.device("cuda:0")
-    p = workloads.matvec_scaling(seed=0, N=a.N, R=a.rhs)
+    R = a.rhs
+    p = workloads.matvec_scaling(seed=0, N=a.N, R=max(R, 1))
     N, d = p.X.shape
     P = p.windows.shape[0]
-    R = a.rhs
     prec = lib.PREC_FP64 if a.precision == "fp64" else lib.PREC_MIXED
     X = torch.as_tensor(p.X, device=dev)
     t0 = time.perf_counter()
@@ -124,54 +181,48 @@ def main():
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
-    x = torch.as_tensor(np.ascontiguousarray(p.v), device=dev)
-    y = plan.matvec(x)
-
-    # accuracy at this configuration: sampled rows against the FP64 oracle
+    xb = colmajor(torch, p.v[:, :R], dev)
+    yb = torch.empty((R, N), dtype=torch.float64, device=dev)
+    plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
+    torch.cuda.synchronize()
     rows = np.random.default_rng(123).choice(N, min(a.check_rows, N), replace=False)
-    ref = oracle.anova_matvec(p.X, p.windows, p.sigma, p.v, rows=rows)
-    yh = y.cpu().numpy()
-    errs = [float(np.linalg.norm(yh[rows, r] - ref[:, r]) / np.linalg.norm(ref[:, r])) for r in range(R)]
-    rel_err = max(errs)
+    rel_err = sampled_error(p, yb.cpu().numpy().T[rows], rows, R)
 
-    for _ in range(a.warmup):
-        plan.matvec(x, out=y)
-    torch.cuda.synchronize()
-    plan.profile_begin()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        plan.matvec(x, out=y)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    stages, passes = plan.profile_end()
-    ms = 1e3 * el / a.steps
-    value = N * P * R / (el / a.steps)
+    t_step, stages, passes = time_matvec(lib, torch, plan, xb, yb, N, R, a.steps, a.warmup)
+    value = N * P * R / t_step
+    batched = prec == lib.PREC_MIXED and R >= 2 and info["cutoff_m"] == 4
+    rb = 16 if batched else 1               # right-hand sides per pass
+    npass = -(-R // rb)
+    per_pass = {k: v for k, v in stages.items()}
 
-    # roofline of the dominant kernel. Spread and gather are bound by vector
-    # ALU work: 2 (2m)^3 flops of tap FMAs per point-window per right-hand side
-    # is the algorithmic count (weights are precomputed per plan).
+    # Roofline of the dominant kernel. Spread and gather each apply (2m)^3
+    # taps per point-window per right-hand side, 2 flops per tap (the
+    # algorithmic count; weights are evaluated once per plan). The batched
+    # path runs them as FP32 matrix-core contractions, the one-vector path on
+    # the vector ALUs. The grid step is bounded by its grid traffic.
     W = 2 * info["cutoff_m"]
-    dom = max(("spread", "gather", "fold", "convolve"), key=lambda s: stages[s])
-    t_dom = stages[dom] * 1e-3
     pw = N * P
-    wbytes = 8 if prec == lib.PREC_FP64 else 4
+    dom = max(("spread", "gather", "fold", "convolve"), key=lambda s: per_pass[s])
+    t_dom = per_pass[dom] * 1e-3
     if dom in ("spread", "gather"):
-        flops = 2.0 * W ** 3 * pw          # per right-hand-side pass
+        flops = 2.0 * W ** 3 * pw * rb
         achieved = flops / t_dom / 1e12
         peak = FP64_PEAK_TFLOPS if prec == lib.PREC_FP64 else FP32_PEAK_TFLOPS
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None}
+        roof = {"bound": "mfma" if batched else "alu", "kernel": ("k_%s_mfma" % dom) if batched else dom,
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "algorithmic_flops_per_launch": flops,
+                "launch_ms": per_pass[dom]}
+        rec = traffic_record() if batched else None
+        if rec is not None and rec.get("N") == N and rec.get("rhs") == rb and roof["kernel"] in rec:
+            roof["traffic"] = rec[roof["kernel"]]
+            roof["traffic_unit"] = "bytes per launch"
+            roof["traffic_note"] = rec["note"]
     else:
-        nbytes = 2.0 * info["grid_cells"] * wbytes
+        wb = 8 if prec == lib.PREC_FP64 else 4
+        nbytes = 2.0 * info["grid_cells"] * wb * rb
         achieved = nbytes / t_dom / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    # algorithmic HBM bytes of the spread: per point-window its 3 x 2m weights,
-    # its base layer (4 B) and its input value (8 B)
-    spread_bytes = pw * (3 * W * wbytes + 4 + 8)
-    hbm = {"spread_GBps": spread_bytes / (stages["spread"] * 1e-3) / 1e9,
-           "gather_GBps": (pw * (3 * W * wbytes + 4 + 8)) / (stages["gather"] * 1e-3) / 1e9,
-           "peak_GBps": HBM_PEAK_GBS}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launch_ms": per_pass[dom]}
 
     out = {
         "metric": "ANOVA-NFFT matvec points*windows/s at rel.err<=1e-4; IPM solve p50/p99 ms",
@@ -180,22 +231,45 @@ def main():
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": 1e3 * t_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == lib.PREC_FP64 else "f32 (window sums f64)",
+        "dtype": "f64" if prec == lib.PREC_FP64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "matvec-scaling: N=100000 d=30 Gaussian mixture, 10 windows x 3 features, "
-                               "sigma=1, bandwidth 32, oversampling 2, m=4",
-                   "N": N, "d": d, "windows": P, "rhs": R, "precision": a.precision},
+        "config": {"workload": f"matvec-scaling: N={N} d={d} two-class Gaussian mixture, {P} windows x 3 "
+                               f"features, sigma=1, bandwidth 32, oversampling 2, m=4, {R} right-hand sides",
+                   "N": N, "d": d, "windows": P, "rhs": R,
+                   "precision": "mixed (FP32 spread/grid/gather, FP64 window sums)" if prec else "fp64",
+                   "path": "batched 16-wide" if batched else "one vector per pass"},
         "rel_err_sampled": rel_err,
-        "stage_ms": stages,
+        "stage_ms_per_pass": per_pass,
+        "passes_per_step": npass,
         "plan_ms": 1e3 * t_plan,
         "plan": {k: info[k] for k in ("n_segments", "grid_cells", "device_bytes", "max_kernel_err")},
         "roofline": roof,
-        "hbm": hbm,
     }
+    if rel_err > 1e-4:
+        out["value"] = 0.0
+        out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4"
+    del plan, xb, yb
+
+    # the one-vector forms on the same GPU at the same accuracy bar
+    if a.reference_steps > 0:
+        refs = {}
+        for name, pr in (("fp64_1rhs", lib.PREC_FP64), ("mixed_1rhs", lib.PREC_MIXED)):
+            pl = lib.Plan(X, p.windows, p.sigma, precision=pr)
+            x1 = colmajor(torch, p.v[:, :1], dev)
+            y1 = torch.empty((1, N), dtype=torch.float64, device=dev)
+            pl.matvec_raw(x1.data_ptr(), 1, N, y1.data_ptr(), N)
+            torch.cuda.synchronize()
+            e1 = sampled_error(p, y1.cpu().numpy().T[rows], rows, 1)
+            t1, st1, _ = time_matvec(lib, torch, pl, x1, y1, N, 1, a.reference_steps, 3)
+            refs[name] = {"value": N * P / t1, "ms_per_step": 1e3 * t1, "rel_err_sampled": e1,
+                          "stage_ms": st1}
+            del pl
+        out["reference"] = refs
+
     ipm = []
     if a.ipm_small_solves > 0:
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.small_plain(seed=s, N=2000, d=9, R=0),
@@ -207,11 +281,14 @@ def main():
                                f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
                                "Nystrom rank 200"))
     out["ipm"] = ipm
-    if rel_err > 1e-4:
-        out["value"] = 0.0
-        out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4"
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
+    if a.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 
