@@ -229,6 +229,95 @@ int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol,
 int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg,
                   double* Zt, int64_t ldz, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * A request server that runs interior point solves (svm_ipm_solve semantics)
+ * of different sizes on one GPU with continuous batching. Requests are
+ * admitted, first fit in arrival order, while fewer than max_active solves are
+ * resident and the estimated device footprint of the resident solves
+ * (anova_request_footprint) stays within hbm_budget; a request that fits no
+ * budget still runs when nothing else is resident. An admitted solve keeps its
+ * plan, iterates and preconditioner on the device until it finishes and runs
+ * on its own stream and host thread, so the work of resident solves overlaps
+ * on the GPU, and admission continues as slots and memory free up. With
+ * share_launches, the one-vector matvecs of the resident solves are collected
+ * and run together: every matvec stage is one kernel launch for up to 8
+ * solves. Each solve's arithmetic is the same alone or in a mix, so results do
+ * not depend on what else is resident.
+ * Thread safety: submit and wait may be called from any threads. */
+#define ANOVA_SERVER_OPTS_VERSION 1
+typedef struct anova_server_s* anova_server_t;
+
+typedef struct {
+    int32_t version;         /* ANOVA_SERVER_OPTS_VERSION                           */
+    int32_t max_active;      /* resident solves at once, 1..64 (default 8)          */
+    int64_t hbm_budget;      /* device bytes for resident solves; <= 0: 80% of the
+                                free memory when the server is created (default)    */
+    int32_t share_launches;  /* 1 (default): resident solves share matvec launches  */
+    int32_t reserved;
+    double  gather_us;       /* longest wait for more matvecs before a shared launch
+                                (microseconds, default 200)                          */
+} anova_server_opts;
+
+typedef struct {
+    const double*  X;        /* host, N x d FP64 row-major; copied by submit        */
+    const double*  labels;   /* host, N FP64 in {-1, +1}; copied by submit          */
+    const int32_t* windows;  /* host, P x 3 as for anova_plan_create; copied         */
+    const double*  sigma;    /* host, P kernel widths; copied                        */
+    int64_t N;
+    int32_t d;
+    int32_t P;
+    double  C;
+    const anova_opts*     nfft;  /* host or NULL (defaults); copied                 */
+    const anova_ipm_opts* ipm;   /* host or NULL (defaults); copied                 */
+} anova_request;
+
+typedef struct {
+    int32_t status;          /* the solve's status                                  */
+    int32_t reserved;
+    int64_t footprint;       /* bytes charged against the budget                    */
+    double  queue_ms;        /* submit -> admission                                 */
+    double  run_ms;          /* admission -> result on the host                     */
+    double  latency_ms;      /* submit -> result on the host                        */
+    double  lambda;          /* as svm_ipm_solve's lambda                           */
+    anova_ipm_stats stats;
+} anova_result;
+
+/* Defaults: max_active = 8, hbm_budget = 0 (80% of free memory),
+ * share_launches = 1, gather_us = 200. */
+int anova_server_opts_default(anova_server_opts* o);
+
+/* Start a server on HIP device `device` (scheduler and, with shared launches,
+ * combiner threads). opts host or NULL. Errors: ANOVA_INVALID_ARG,
+ * ANOVA_HIP_ERROR. */
+int anova_server_create(const anova_server_opts* opts, int32_t device, anova_server_t* out);
+
+/* Queue a solve; returns at once with a ticket (host out). The inputs are
+ * copied, so the caller's buffers may be reused immediately. Errors:
+ * ANOVA_INVALID_ARG (NULL fields, N < 2, d < 1, P < 1, C <= 0, option
+ * version mismatch); problems found later (bad labels, windows) are reported
+ * by anova_server_wait. */
+int anova_server_submit(anova_server_t s, const anova_request* req, int64_t* ticket);
+
+/* Block until the ticket's solve has finished, then copy alpha (host, N FP64,
+ * may be NULL) and the result record (host, may be NULL); the ticket is
+ * consumed. Returns the solve's status (ANOVA_OK, ANOVA_NOT_CONVERGED, or the
+ * error it failed with, with the message in anova_last_error()). */
+int anova_server_wait(anova_server_t s, int64_t ticket, double* alpha, anova_result* result);
+
+/* Shared-launch counters since creation: launches made and matvecs served
+ * (host outs; both 0 without shared launches). */
+int anova_server_counters(anova_server_t s, int64_t* launches, int64_t* matvecs);
+
+/* Finish every queued and resident solve, then stop. NULL is accepted.
+ * Results not collected by anova_server_wait are dropped. */
+int anova_server_destroy(anova_server_t s);
+
+/* The device footprint the server charges for a request of this shape
+ * (host out, bytes): inputs, plan, grids, iterates and preconditioner, with
+ * a 25% margin. nfft and ipm host or NULL (defaults). */
+int anova_request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts* nfft,
+                            const anova_ipm_opts* ipm, int64_t* bytes);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* anova_last_error(void);
 

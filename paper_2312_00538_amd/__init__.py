@@ -24,6 +24,8 @@ EXPORTED = [
     "anova_opts_default", "anova_plan_create", "anova_matvec", "anova_plan_destroy",
     "anova_plan_info", "anova_ipm_opts_default", "svm_ipm_solve", "anova_pivoted_cholesky",
     "anova_nystrom", "anova_last_error", "anova_profile_begin", "anova_profile_end",
+    "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
+    "anova_server_counters", "anova_server_destroy", "anova_request_footprint",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -55,6 +57,17 @@ class IpmOpts(ctypes.Structure):
                 ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("max_active", ctypes.c_int32), ("hbm_budget", ctypes.c_int64),
+                ("share_launches", ctypes.c_int32), ("reserved", ctypes.c_int32), ("gather_us", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("windows", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("N", ctypes.c_int64), ("d", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("C", ctypes.c_double), ("nfft", ctypes.c_void_p), ("ipm", ctypes.c_void_p)]
+
+
 class IpmStats(ctypes.Structure):
     _fields_ = [("ip_iters", ctypes.c_int32), ("kry_iters_total", ctypes.c_int32),
                 ("kry_iters_max", ctypes.c_int32), ("rank_used", ctypes.c_int32), ("status", ctypes.c_int32),
@@ -65,6 +78,12 @@ class IpmStats(ctypes.Structure):
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("footprint", ctypes.c_int64),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("stats", IpmStats)]
 
 
 _lib = None
@@ -95,6 +114,14 @@ def load_library(path: str = LIB_PATH):
         "anova_last_error": ([], ctypes.c_char_p),
         "anova_profile_begin": ([P], ctypes.c_int),
         "anova_profile_end": ([P, P, i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "anova_server_opts_default": ([ctypes.POINTER(ServerOpts)], ctypes.c_int),
+        "anova_server_create": ([ctypes.POINTER(ServerOpts), i32, ctypes.POINTER(P)], ctypes.c_int),
+        "anova_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(i64)], ctypes.c_int),
+        "anova_server_wait": ([P, i64, P, ctypes.POINTER(ServerResult)], ctypes.c_int),
+        "anova_server_counters": ([P, ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+        "anova_server_destroy": ([P], ctypes.c_int),
+        "anova_request_footprint": ([i64, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(IpmOpts),
+                                     ctypes.POINTER(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -251,6 +278,75 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.anova_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: IpmOpts | None = None) -> int:
+    """Device bytes the server charges for a request of this shape."""
+    lib = load_library()
+    b = ctypes.c_int64(0)
+    _check(lib.anova_request_footprint(int(N), int(d), int(P), ctypes.byref(nfft) if nfft else None,
+                                       ctypes.byref(ipm) if ipm else None, ctypes.byref(b)))
+    return b.value
+
+
+class Server:
+    """Continuous-batching request server for IPM solves on one GPU (host
+    inputs are copied at submit; results come back on the host)."""
+
+    def __init__(self, max_active: int = 8, hbm_budget: int = 0, share_launches: bool = True,
+                 gather_us: float = 200.0, device: int = 0):
+        lib = load_library()
+        o = ServerOpts()
+        _check(lib.anova_server_opts_default(ctypes.byref(o)))
+        o.max_active, o.hbm_budget = int(max_active), int(hbm_budget)
+        o.share_launches, o.gather_us = int(bool(share_launches)), float(gather_us)
+        h = ctypes.c_void_p()
+        _check(lib.anova_server_create(ctypes.byref(o), int(device), ctypes.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def submit(self, X, labels, windows, sigma, C: float, nfft: Opts | None = None, ipm: IpmOpts | None = None,
+               **ipm_kw) -> int:
+        X = np.ascontiguousarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(labels, dtype=np.float64)
+        win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 3))
+        P = int(win.shape[0])
+        sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (P,)))
+        if ipm is None and ipm_kw:
+            ipm = default_ipm_opts(**ipm_kw)
+        q = Request(X.ctypes.data, y.ctypes.data, win.ctypes.data, sig.ctypes.data, X.shape[0], X.shape[1], P,
+                    float(C), ctypes.cast(ctypes.pointer(nfft), ctypes.c_void_p) if nfft else None,
+                    ctypes.cast(ctypes.pointer(ipm), ctypes.c_void_p) if ipm else None)
+        t = ctypes.c_int64(0)
+        _check(_lib.anova_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        self._n[t.value] = X.shape[0]
+        return t.value
+
+    def wait(self, ticket: int, allow_not_converged: bool = True):
+        """Blocks until the solve is done; returns (alpha, result dict)."""
+        alpha = np.empty(self._n.pop(ticket), dtype=np.float64)
+        r = ServerResult()
+        rc = _lib.anova_server_wait(self._h, int(ticket), alpha.ctypes.data_as(ctypes.c_void_p), ctypes.byref(r))
+        _check(rc, allow=(OK, NOT_CONVERGED) if allow_not_converged else (OK,))
+        res = {"status": r.status, "footprint": r.footprint, "queue_ms": r.queue_ms, "run_ms": r.run_ms,
+               "latency_ms": r.latency_ms, "lambda": r.lambda_, "stats": r.stats.as_dict()}
+        return alpha, res
+
+    def counters(self) -> tuple[int, int]:
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        _check(_lib.anova_server_counters(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.anova_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

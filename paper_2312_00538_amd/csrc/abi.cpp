@@ -5,6 +5,7 @@
 #include <memory>
 
 #include "plan.hpp"
+#include "server.hpp"
 #include "solver.hpp"
 
 namespace anv {
@@ -33,6 +34,10 @@ static int guarded(F&& f) {
 
 struct anova_plan_s {
     std::unique_ptr<anv::Plan> p;
+};
+
+struct anova_server_s {
+    std::unique_ptr<anv::Server> s;
 };
 
 extern "C" {
@@ -180,6 +185,85 @@ int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg, do
         ANV_CHECK(k >= 1 && k <= plan->p->N, "k must be in [1, N]");
         ANV_CHECK(ldg >= plan->p->N && ldz >= plan->p->N, "leading dimension < N");
         anv::nystrom_factor(*plan->p, G, k, ldg, Zt, ldz, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
+int anova_server_opts_default(anova_server_opts* o) {
+    if (!o) return ANOVA_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->version = ANOVA_SERVER_OPTS_VERSION;
+    o->max_active = 8;
+    o->hbm_budget = 0;
+    o->share_launches = 1;
+    o->gather_us = 200.0;
+    return ANOVA_OK;
+}
+
+int anova_server_create(const anova_server_opts* opts, int32_t device, anova_server_t* out) {
+    return guarded([&] {
+        ANV_CHECK(out != nullptr, "NULL output handle");
+        *out = nullptr;
+        anova_server_opts o;
+        anova_server_opts_default(&o);
+        if (opts) {
+            ANV_CHECK(opts->version == ANOVA_SERVER_OPTS_VERSION, "anova_server_opts.version mismatch");
+            o = *opts;
+        }
+        ANV_CHECK(o.max_active >= 1 && o.max_active <= 64, "max_active must be in [1, 64]");
+        ANV_CHECK(o.gather_us >= 0.0 && o.gather_us <= 1e6, "gather_us must be in [0, 1e6]");
+        int ndev = 0;
+        ANV_HIP(hipGetDeviceCount(&ndev));
+        ANV_CHECK(device >= 0 && device < ndev, "no such device");
+        auto h = std::make_unique<anova_server_s>();
+        h->s.reset(new anv::Server(o, device));
+        *out = h.release();
+        return ANOVA_OK;
+    });
+}
+
+int anova_server_submit(anova_server_t s, const anova_request* req, int64_t* ticket) {
+    return guarded([&] {
+        ANV_CHECK(s && req && ticket, "NULL argument");
+        *ticket = s->s->submit(*req);
+        return ANOVA_OK;
+    });
+}
+
+int anova_server_wait(anova_server_t s, int64_t ticket, double* alpha, anova_result* result) {
+    return guarded([&] {
+        ANV_CHECK(s != nullptr, "NULL server");
+        return s->s->wait(ticket, alpha, result);
+    });
+}
+
+int anova_server_counters(anova_server_t s, int64_t* launches, int64_t* matvecs) {
+    return guarded([&] {
+        ANV_CHECK(s && launches && matvecs, "NULL argument");
+        s->s->counters(launches, matvecs);
+        return ANOVA_OK;
+    });
+}
+
+int anova_server_destroy(anova_server_t s) {
+    return guarded([&] {
+        delete s;
+        return ANOVA_OK;
+    });
+}
+
+int anova_request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts* nfft, const anova_ipm_opts* ipm,
+                            int64_t* bytes) {
+    return guarded([&] {
+        ANV_CHECK(bytes != nullptr, "NULL output");
+        ANV_CHECK(N >= 1 && d >= 1 && P >= 1, "bad sizes");
+        anova_opts o;
+        anova_opts_default(&o);
+        if (nfft) o = *nfft;
+        anova_ipm_opts io;
+        anova_ipm_opts_default(&io);
+        if (ipm) io = *ipm;
+        *bytes = anv::request_footprint(N, d, P, o, io);
         return ANOVA_OK;
     });
 }

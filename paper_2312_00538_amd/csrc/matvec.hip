@@ -17,6 +17,8 @@
 // anywhere: each work item writes its own slab of partial sums and the fold
 // kernel adds the slabs that cover a cell in a fixed order, so results are
 // reproducible bit for bit.
+#include <cstring>
+
 #include "plan.hpp"
 
 namespace anv {
@@ -64,11 +66,21 @@ __device__ inline void stage_values_async(double* lds, const double* __restrict_
 
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
-__global__ void k_permute(const double* __restrict__ x, const int32_t* __restrict__ perm,
-                          int64_t NP, int64_t N, double* __restrict__ vs) {
-    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= NP) return;
-    vs[t] = x[perm[t]];
+// Block b of a launch belongs to job j with off[j] <= b < off[j + 1]; returns j
+// and turns b into the job's local block index.
+__device__ inline int job_of(const MvLaunch& L, int& b) {
+    int j = 0;
+    while (j + 1 < L.njobs && L.off[j + 1] <= b) ++j;
+    b -= L.off[j];
+    return j;
+}
+
+__global__ void k_permute(const MvLaunch ML) {
+    int b = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, b)];
+    const int64_t t = b * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= J.N * J.P) return;
+    J.vs[t] = J.x[J.perm[t]];
 }
 
 // 3-feature windows: one work item (a long run of one column) per wavefront.
@@ -79,15 +91,19 @@ __global__ void k_permute(const double* __restrict__ x, const int32_t* __restric
 // and the wave writes one slab row [a][b]. Point data are staged in LDS in
 // chunks of 64 consecutive points.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ wave_items,
-                                                   const Segment* __restrict__ segs,
-                                                   const int32_t* __restrict__ lstart,
-                                                   const int32_t* __restrict__ lstart_off,
-                                                   const WinDev* __restrict__ wins,
-                                                   const uint8_t* __restrict__ alone,
-                                                   const WT* __restrict__ wts,
-                                                   const double* __restrict__ vs, int64_t N,
-                                                   WT* __restrict__ slab, WT* __restrict__ tgt) {
+__global__ __launch_bounds__(64) void k_spread_grp(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const Segment* __restrict__ segs = J.segs;
+    const int32_t* __restrict__ lstart = J.lstart;
+    const int32_t* __restrict__ lstart_off = J.lstart_off;
+    const WinDev* __restrict__ wins = J.wins;
+    const uint8_t* __restrict__ alone = J.alone;
+    const WT* __restrict__ wts = static_cast<const WT*>(J.wts);
+    const double* __restrict__ vs = J.vs;
+    const int64_t N = J.N;
+    WT* __restrict__ slab = static_cast<WT*>(J.slab);
+    WT* __restrict__ tgt = static_cast<WT*>(J.ca);
     constexpr int G = 64 / W;                 // lane groups
     constexpr int REC = rec_stride(W, int(sizeof(WT)));
     constexpr int CH = 64;                    // staged points
@@ -100,7 +116,7 @@ __global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ w
     // elements); the plane stride 72 = 64 + 8 spreads the (a, b) readers over all banks
     constexpr int RP = 64 + 8;
     __shared__ WT red[W * RP];
-    const int sid = wave_items[blockIdx.x];
+    const int sid = J.wave_items[J.wave_off[3] + blk];
     const Segment sg = segs[sid];
     const int lane = threadIdx.x;
     const int g = lane / W, a = lane % W;
@@ -191,13 +207,16 @@ __global__ __launch_bounds__(64) void k_spread_grp(const int32_t* __restrict__ w
 // 1- and 2-feature windows: one lane per work item; WY = W for two features
 // (y taps in registers), 1 for one feature. Slab layout [layer][b].
 template <int W, int WY, class WT>
-__global__ __launch_bounds__(64) void k_spread_lane(const int32_t* __restrict__ wave_items,
-                                                    const Segment* __restrict__ segs,
-                                                    const int32_t* __restrict__ zq,
-                                                    const WT* __restrict__ wts,
-                                                    const double* __restrict__ vs, int64_t N,
-                                                    WT* __restrict__ slab) {
-    const int sid = wave_items[blockIdx.x * 64 + threadIdx.x];
+__global__ __launch_bounds__(64) void k_spread_lane(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const Segment* __restrict__ segs = J.segs;
+    const int32_t* __restrict__ zq = J.zq;
+    const WT* __restrict__ wts = static_cast<const WT*>(J.wts);
+    const double* __restrict__ vs = J.vs;
+    const int64_t N = J.N;
+    WT* __restrict__ slab = static_cast<WT*>(J.slab);
+    const int sid = J.wave_items[J.wave_off[WY == 1 ? 1 : 2] + blk * 64 + threadIdx.x];
     if (sid < 0) return;
     const Segment sg = segs[sid];
     const int64_t base = int64_t(sg.win) * N + sg.start;
@@ -247,12 +266,18 @@ __global__ __launch_bounds__(64) void k_spread_lane(const int32_t* __restrict__ 
 // (target, (a, b)) has exactly one source column, so no two lanes write the
 // same element.
 template <class WT>
-__global__ __launch_bounds__(256) void k_fold_cols(const WinDev* __restrict__ wins, int32_t P,
-                                                   int64_t nlist, const int64_t* __restrict__ flist,
-                                                   const int2* __restrict__ fold,
-                                                   const int64_t* __restrict__ sbase,
-                                                   const WT* __restrict__ slab, WT* __restrict__ tgt) {
-    const int64_t fi = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+__global__ __launch_bounds__(256) void k_fold_cols(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const WinDev* __restrict__ wins = J.wins;
+    const int32_t P = J.P;
+    const int64_t nlist = J.nflist;
+    const int64_t* __restrict__ flist = J.flist;
+    const int2* __restrict__ fold = J.fold;
+    const int64_t* __restrict__ sbase = J.sbase;
+    const WT* __restrict__ slab = static_cast<const WT*>(J.slab);
+    WT* __restrict__ tgt = static_cast<WT*>(J.ca);
+    const int64_t fi = int64_t(blk) * 4 + threadIdx.x / 64;
     if (fi >= nlist) return;
     const int64_t f = flist[fi];
     int l = 0;
@@ -302,14 +327,17 @@ __global__ __launch_bounds__(256) void k_fold_cols(const WinDev* __restrict__ wi
 // layer range covers the cell contribute), then T_y and T_z are applied in LDS
 // and the slice is written as g1[x][y][z].
 template <int W, class WT>
-__global__ __launch_bounds__(1024) void k_fold_conv_yz(const WinDev* __restrict__ wins,
-                                                       const double* __restrict__ tmat,
-                                                       const int2* __restrict__ crange,
-                                                       const WT* __restrict__ tgt, WT* __restrict__ g1) {
+__global__ __launch_bounds__(1024) void k_fold_conv_yz(const MvLaunch ML) {
     extern __shared__ double sm[];
-    const int l = blockIdx.y;
-    const WinDev& wd = wins[l];
-    const int x = blockIdx.x;
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const double* __restrict__ tmat = J.tmat;
+    const int2* __restrict__ crange = J.crange;
+    const WT* __restrict__ tgt = static_cast<const WT*>(J.ca);
+    WT* __restrict__ g1 = static_cast<WT*>(J.g);
+    const int l = blk / J.emax[0];
+    const WinDev& wd = J.wins[l];
+    const int x = blk % J.emax[0];
     if (x >= wd.E[0]) return;
     const int Ey = wd.E[1], Ez = wd.E[2];
     const int S = Ey * Ez;
@@ -370,12 +398,16 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz(const WinDev* __restrict_
 // x pass of the grid convolution, one block per (y slice, window); the result
 // is stored as h[x][z][y], the layout the gather reads.
 template <class WT>
-__global__ __launch_bounds__(256) void k_conv_x(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
-                                                const WT* __restrict__ g1, WT* __restrict__ h) {
+__global__ __launch_bounds__(256) void k_conv_x(const MvLaunch ML) {
     extern __shared__ double sm[];
-    const int l = blockIdx.y;
-    const WinDev& wd = wins[l];
-    const int y = blockIdx.x;
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const double* __restrict__ tmat = J.tmat;
+    const WT* __restrict__ g1 = static_cast<const WT*>(J.g);
+    WT* __restrict__ h = static_cast<WT*>(J.h);
+    const int l = blk / J.emax[1];
+    const WinDev& wd = J.wins[l];
+    const int y = blk % J.emax[1];
     if (y >= wd.E[1]) return;
     const int Ex = wd.E[0], Ey = wd.E[1], Ez = wd.E[2];
     double* sl = sm;            // [x][z] at this y
@@ -394,48 +426,23 @@ __global__ __launch_bounds__(256) void k_conv_x(const WinDev* __restrict__ wins,
     }
 }
 
-// out = T_axis applied along one axis of every window grid (layout [x][y][z]);
-// with zy_out the result is stored as [x][z][y], the layout the gather reads.
-template <class WT>
-__global__ void k_conv_axis(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
-                            int axis, const WT* __restrict__ in, WT* __restrict__ out, int zy_out) {
-    const int l = blockIdx.y;
-    const WinDev wd = wins[l];
-    const int64_t cells = int64_t(wd.E[0]) * wd.E[1] * wd.E[2];
-    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= cells) return;
-    const int E = wd.E[axis];
-    int64_t stride = 1;
-    for (int s = 2; s > axis; --s) stride *= wd.E[s];
-    const int i = int((c / stride) % E);
-    const int64_t base = wd.grid_off + c - int64_t(i) * stride;
-    const double* T = tmat + wd.t_off[axis] + int64_t(i) * E;
-    double acc = 0.0;
-    for (int k = 0; k < E; ++k) acc += T[k] * double(in[base + int64_t(k) * stride]);
-    int64_t o = c;
-    if (zy_out) {
-        const int gz = int(c % wd.E[2]);
-        const int gy = int((c / wd.E[2]) % wd.E[1]);
-        const int64_t gx = c / (int64_t(wd.E[2]) * wd.E[1]);
-        o = (gx * wd.E[2] + gz) * wd.E[1] + gy;
-    }
-    out[wd.grid_off + o] = WT(acc);
-}
-
 // 3-feature windows, one work item per wavefront as in the spread. Every lane
 // group keeps the same W x W block h(cx + a, cy + b, z .. z + W - 1) (h stored
 // as [x][z][y]) for the current layer; per step each group takes one point of
 // the layer, lane a forms the share of x-tap a and the W lanes add their shares
 // with a fixed xor butterfly.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ wave_items,
-                                                   const Segment* __restrict__ segs,
-                                                   const int32_t* __restrict__ lstart,
-                                                   const int32_t* __restrict__ lstart_off,
-                                                   const WinDev* __restrict__ wins,
-                                                   const WT* __restrict__ wts,
-                                                   const WT* __restrict__ h, int64_t N,
-                                                   double* __restrict__ fs) {
+__global__ __launch_bounds__(64) void k_gather_grp(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const Segment* __restrict__ segs = J.segs;
+    const int32_t* __restrict__ lstart = J.lstart;
+    const int32_t* __restrict__ lstart_off = J.lstart_off;
+    const WinDev* __restrict__ wins = J.wins;
+    const WT* __restrict__ wts = static_cast<const WT*>(J.wts);
+    const WT* __restrict__ h = static_cast<const WT*>(J.h);
+    const int64_t N = J.N;
+    double* __restrict__ fs = J.fs;
     constexpr int G = 64 / W;
     constexpr int REC = rec_stride(W, int(sizeof(WT)));
     constexpr int CH = 64;
@@ -443,7 +450,7 @@ __global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ w
     constexpr int RS = REC + PADR;
     constexpr int STEP = CH - G;
     __shared__ WT stw[2][CH * RS];
-    const int sid = wave_items[blockIdx.x];
+    const int sid = J.wave_items[J.wave_off[3] + blk];
     const Segment sg = segs[sid];
     const WinDev& wd = wins[sg.win];
     const int lane = threadIdx.x;
@@ -516,14 +523,17 @@ __global__ __launch_bounds__(64) void k_gather_grp(const int32_t* __restrict__ w
 
 // 1- and 2-feature windows: one lane per work item.
 template <int W, int WY, class WT>
-__global__ __launch_bounds__(64) void k_gather_lane(const int32_t* __restrict__ wave_items,
-                                                    const Segment* __restrict__ segs,
-                                                    const WinDev* __restrict__ wins,
-                                                    const int32_t* __restrict__ zq,
-                                                    const WT* __restrict__ wts,
-                                                    const WT* __restrict__ h, int64_t N,
-                                                    double* __restrict__ fs) {
-    const int sid = wave_items[blockIdx.x * 64 + threadIdx.x];
+__global__ __launch_bounds__(64) void k_gather_lane(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const Segment* __restrict__ segs = J.segs;
+    const WinDev* __restrict__ wins = J.wins;
+    const int32_t* __restrict__ zq = J.zq;
+    const WT* __restrict__ wts = static_cast<const WT*>(J.wts);
+    const WT* __restrict__ h = static_cast<const WT*>(J.h);
+    const int64_t N = J.N;
+    double* __restrict__ fs = J.fs;
+    const int sid = J.wave_items[J.wave_off[WY == 1 ? 1 : 2] + blk * 64 + threadIdx.x];
     if (sid < 0) return;
     const Segment sg = segs[sid];
     const WinDev& wd = wins[sg.win];
@@ -563,72 +573,113 @@ __global__ __launch_bounds__(64) void k_gather_lane(const int32_t* __restrict__ 
     }
 }
 
-__global__ void k_window_sum(const double* __restrict__ fs, const int32_t* __restrict__ pos,
-                             const WinDev* __restrict__ wins, int32_t P, int64_t N,
-                             double* __restrict__ y) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ void k_window_sum(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const int64_t i = blk * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t N = J.N;
     if (i >= N) return;
     double acc = 0.0;
-    for (int l = 0; l < P; ++l) acc += wins[l].eta * fs[int64_t(l) * N + pos[int64_t(l) * N + i]];
-    y[i] = acc;
+    for (int l = 0; l < J.P; ++l) acc += J.wins[l].eta * J.fs[int64_t(l) * N + J.pos[int64_t(l) * N + i]];
+    J.y[i] = acc;
+}
+
+MvJob make_job(Plan& pl, const double* x, double* y) {
+    MvJob J;
+    std::memset(&J, 0, sizeof(J));
+    const bool f64 = pl.precision == ANOVA_PREC_FP64;
+    J.x = x;
+    J.y = y;
+    J.perm = pl.perm.p;
+    J.pos = pl.pos.p;
+    J.zq = pl.zq.p;
+    J.wts = f64 ? static_cast<const void*>(pl.wts64.p) : static_cast<const void*>(pl.wts32.p);
+    J.segs = pl.segs.p;
+    J.lstart = pl.lstart.p;
+    J.lstart_off = pl.lstart_off.p;
+    J.wins = pl.wins_d.p;
+    J.alone = pl.alone.p;
+    J.wave_items = pl.wave_items.p;
+    J.flist = pl.flist.p;
+    J.fold = pl.fold.p;
+    J.sbase = pl.sbase.p;
+    J.crange = pl.crange.p;
+    J.tmat = pl.tmat.p;
+    J.vs = pl.vs.p;
+    J.fs = pl.fs.p;
+    J.slab = f64 ? static_cast<void*>(pl.slab64.p) : static_cast<void*>(pl.slab32.p);
+    J.g = f64 ? static_cast<void*>(pl.g64.p) : static_cast<void*>(pl.g32.p);
+    J.h = f64 ? static_cast<void*>(pl.h64.p) : static_cast<void*>(pl.h32.p);
+    J.ca = f64 ? static_cast<void*>(pl.c64a.p) : static_cast<void*>(pl.c32a.p);
+    J.N = pl.N;
+    J.nflist = pl.nflist;
+    for (int k = 0; k < 4; ++k) {
+        J.wave_off[k] = pl.wave_off[k];
+        J.nwave[k] = pl.nwave[k];
+    }
+    J.P = pl.P;
+    for (int a = 0; a < 3; ++a) J.emax[a] = pl.emax[a];
+    return J;
+}
+
+// Launches kernel `kern` over the jobs of L with blocks(job) blocks each (jobs
+// with none are skipped by the offsets); returns false if no job has work.
+template <class F, class K>
+bool launch_jobs(MvLaunch& L, F blocks, K kern, unsigned threads, size_t lds, hipStream_t st) {
+    int64_t tot = 0;
+    for (int j = 0; j < L.njobs; ++j) {
+        L.off[j] = int32_t(tot);
+        tot += blocks(L.job[j]);
+    }
+    L.off[L.njobs] = int32_t(tot);
+    if (tot == 0) return false;
+    ANV_CHECK(tot < (int64_t(1) << 31), "launch too large");
+    hipLaunchKernelGGL(kern, dim3(unsigned(tot)), dim3(threads), lds, st, L);
+    return true;
 }
 
 template <int W, class WT>
-void run_matvec(Plan& pl, const double* x, double* y, WT* wts, WT* slab, WT* g, WT* h, WT* ca,
-                WT* cb, hipStream_t st) {
-    const int64_t N = pl.N, NP = pl.N * pl.P;
-    const bool prof = pl.profiling;
-    if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_permute, dim3(nblocks(NP)), dim3(kThreads), 0, st, x, pl.perm.p, NP, N,
-                       pl.vs.p);
-    if (prof) pl.record_stage_event(st);
-    if (pl.nwave[3])
-        hipLaunchKernelGGL((k_spread_grp<W, WT>), dim3(pl.nwave[3]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, wts, pl.vs.p, N,
-                           slab, ca);
-    if (pl.nwave[2])
-        hipLaunchKernelGGL((k_spread_lane<W, W, WT>), dim3(pl.nwave[2]), dim3(64), 0, st,
-                           pl.wave_items.p + pl.wave_off[2], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
-    if (pl.nwave[1])
-        hipLaunchKernelGGL((k_spread_lane<W, 1, WT>), dim3(pl.nwave[1]), dim3(64), 0, st,
-                           pl.wave_items.p + pl.wave_off[1], pl.segs.p, pl.zq.p, wts, pl.vs.p, N, slab);
-    if (prof) pl.record_stage_event(st);
-    if (pl.nflist)
-        hipLaunchKernelGGL(k_fold_cols<WT>, dim3(unsigned((pl.nflist + 3) / 4)), dim3(256), 0, st, pl.wins_d.p,
-                           pl.P, pl.nflist, pl.flist.p, pl.fold.p, pl.sbase.p, slab, ca);
-    if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL((k_fold_conv_yz<W, WT>), dim3(unsigned(pl.emax[0]), unsigned(pl.P)), dim3(1024),
-                       size_t(2 * pl.emax[1] * pl.emax[2] + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) *
-                           sizeof(double),
-                       st, pl.wins_d.p, pl.tmat.p, pl.crange.p, ca, g);
-    hipLaunchKernelGGL(k_conv_x<WT>, dim3(unsigned(pl.emax[1]), unsigned(pl.P)), dim3(256),
-                       size_t(pl.emax[0] * pl.emax[2] + pl.emax[0] * pl.emax[0]) * sizeof(double), st, pl.wins_d.p,
-                       pl.tmat.p, g, h);
-    if (prof) pl.record_stage_event(st);
-    if (pl.nwave[3])
-        hipLaunchKernelGGL((k_gather_grp<W, WT>), dim3(pl.nwave[3]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                           pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, wts, h, N, pl.fs.p);
-    if (pl.nwave[2])
-        hipLaunchKernelGGL((k_gather_lane<W, W, WT>), dim3(pl.nwave[2]), dim3(64), 0, st,
-                           pl.wave_items.p + pl.wave_off[2], pl.segs.p, pl.wins_d.p, pl.zq.p, wts, h, N, pl.fs.p);
-    if (pl.nwave[1])
-        hipLaunchKernelGGL((k_gather_lane<W, 1, WT>), dim3(pl.nwave[1]), dim3(64), 0, st,
-                           pl.wave_items.p + pl.wave_off[1], pl.segs.p, pl.wins_d.p, pl.zq.p, wts, h, N, pl.fs.p);
-    if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_window_sum, dim3(nblocks(N)), dim3(kThreads), 0, st, pl.fs.p, pl.pos.p,
-                       pl.wins_d.p, pl.P, N, y);
-    if (prof) pl.record_stage_event(st);
+void run_jobs(MvLaunch& L, Plan* prof, hipStream_t st) {
+    auto ev = [&]() {
+        if (prof && prof->profiling) prof->record_stage_event(st);
+    };
+    int e0 = 1, e1 = 1, e2 = 1;
+    for (int j = 0; j < L.njobs; ++j) {
+        e0 = std::max(e0, L.job[j].emax[0]);
+        e1 = std::max(e1, L.job[j].emax[1]);
+        e2 = std::max(e2, L.job[j].emax[2]);
+    }
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return int64_t(nblocks(J.N * J.P)); }, k_permute, kThreads, 0, st);
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]); }, k_spread_grp<W, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[2]); }, k_spread_lane<W, W, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[1]); }, k_spread_lane<W, 1, WT>, 64, 0, st);
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return (J.nflist + 3) / 4; }, k_fold_cols<WT>, 256, 0, st);
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[0]) * J.P; }, k_fold_conv_yz<W, WT>, 1024,
+                size_t(2 * e1 * e2 + e1 * e1 + e2 * e2) * sizeof(double), st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[1]) * J.P; }, k_conv_x<WT>, 256,
+                size_t(e0 * e2 + e0 * e0) * sizeof(double), st);
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]); }, k_gather_grp<W, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[2]); }, k_gather_lane<W, W, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[1]); }, k_gather_lane<W, 1, WT>, 64, 0, st);
+    ev();
+    launch_jobs(L, [](const MvJob& J) { return int64_t(nblocks(J.N)); }, k_window_sum, kThreads, 0, st);
+    ev();
     ANV_HIP(hipGetLastError());
 }
 
-template <int W>
-void run_prec(Plan& pl, const double* x, double* y, hipStream_t st) {
-    if (pl.precision == ANOVA_PREC_FP64)
-        run_matvec<W, double>(pl, x, y, pl.wts64.p, pl.slab64.p, pl.g64.p, pl.h64.p, pl.c64a.p,
-                              pl.c64b.p, st);
-    else
-        run_matvec<W, float>(pl, x, y, pl.wts32.p, pl.slab32.p, pl.g32.p, pl.h32.p, pl.c32a.p,
-                             pl.c32b.p, st);
+void run_launch(MvLaunch& L, int W, int precision, Plan* prof, hipStream_t st) {
+    const bool f64 = precision == ANOVA_PREC_FP64;
+    switch (W) {
+        case 4: f64 ? run_jobs<4, double>(L, prof, st) : run_jobs<4, float>(L, prof, st); break;
+        case 6: f64 ? run_jobs<6, double>(L, prof, st) : run_jobs<6, float>(L, prof, st); break;
+        case 8: f64 ? run_jobs<8, double>(L, prof, st) : run_jobs<8, float>(L, prof, st); break;
+        default: throw Error(ANOVA_INVALID_ARG, "unsupported cutoff");
+    }
 }
 
 }  // namespace
@@ -674,15 +725,30 @@ void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, in
         enqueue_matvec_batched(pl, x, R, ldx, y, ldy, st);
         return;
     }
+    MvLaunch L;
+    L.njobs = 1;
     for (int r = 0; r < R; ++r) {
-        const double* xr = x + int64_t(r) * ldx;
-        double* yr = y + int64_t(r) * ldy;
-        switch (pl.W) {
-            case 4: run_prec<4>(pl, xr, yr, st); break;
-            case 6: run_prec<6>(pl, xr, yr, st); break;
-            case 8: run_prec<8>(pl, xr, yr, st); break;
-            default: throw Error(ANOVA_INVALID_ARG, "unsupported cutoff");
+        L.job[0] = make_job(pl, x + int64_t(r) * ldx, y + int64_t(r) * ldy);
+        run_launch(L, pl.W, pl.precision, &pl, st);
+    }
+}
+
+void enqueue_matvec_multi(Plan* const* plans, const double* const* x, double* const* y, int n, hipStream_t st) {
+    // one launch per stage for up to kMaxJobs plans of equal cutoff and precision
+    std::vector<int> done(n, 0);
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        MvLaunch L;
+        L.njobs = 0;
+        for (int k = i; k < n && L.njobs < kMaxJobs; ++k) {
+            if (done[k] || plans[k]->W != plans[i]->W || plans[k]->precision != plans[i]->precision) continue;
+            bool dup = false;
+            for (int q = 0; q < L.njobs; ++q) dup |= (plans[k]->pos.p == L.job[q].pos);
+            if (dup) continue;  // a plan's scratch serves one vector per launch
+            L.job[L.njobs++] = make_job(*plans[k], x[k], y[k]);
+            done[k] = 1;
         }
+        run_launch(L, plans[i]->W, plans[i]->precision, nullptr, st);
     }
 }
 

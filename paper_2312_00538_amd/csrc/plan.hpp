@@ -1,6 +1,7 @@
 // The fast-summation plan: everything that depends only on (X, windows, sigma).
 #pragma once
 #include <array>
+#include <functional>
 #include <memory>
 
 #include "common.hpp"
@@ -86,9 +87,56 @@ struct Plan {
     void record_stage_event(hipStream_t st);
 
     double max_kerr = 0.0;
+    // When set, the solver's one-vector matvecs go through this hook (a request
+    // server uses it to put the matvecs of several resident solves in shared
+    // launches) instead of enqueue_matvec.
+    std::function<void(Plan&, const double*, double*, hipStream_t)> mv_hook;
     ~Plan();
     int64_t device_bytes() const;
 };
+
+// One plan's share of a matvec launch that may serve several plans at once
+// (pointers to the plan's arrays and scratch, the caller's vectors, sizes).
+constexpr int kMaxJobs = 8;
+struct MvJob {
+    const double* x;
+    double* y;
+    const int32_t* perm;
+    const int32_t* pos;
+    const int32_t* zq;
+    const void* wts;
+    const Segment* segs;
+    const int32_t* lstart;
+    const int32_t* lstart_off;
+    const WinDev* wins;
+    const uint8_t* alone;
+    const int32_t* wave_items;
+    const int64_t* flist;
+    const int2* fold;
+    const int64_t* sbase;
+    const int2* crange;
+    const double* tmat;
+    double* vs;
+    double* fs;
+    void* slab;
+    void* g;
+    void* h;
+    void* ca;
+    int64_t N;
+    int64_t nflist;
+    int64_t wave_off[4];
+    int32_t nwave[4];
+    int32_t P;
+    int32_t emax[3];
+};
+// Passed to every kernel by value: the jobs and, per kernel, the first block
+// of each job.
+struct MvLaunch {
+    MvJob job[kMaxJobs];
+    int32_t njobs;
+    int32_t off[kMaxJobs + 1];
+};
+static_assert(sizeof(MvLaunch) < 4000, "kernel argument block");
 
 Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows,
                   int32_t P, const double* sigma, const double* eta, const anova_opts* opts,
@@ -103,6 +151,11 @@ void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, in
 bool batched_supported(const Plan& pl);
 void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                             hipStream_t stream);
+
+// y_i = K_i x_i for n (plan, vector) pairs, one vector per plan: the plans'
+// stages share launches (grouped by cutoff and precision, up to kMaxJobs plans).
+void enqueue_matvec_multi(Plan* const* plans, const double* const* x, double* const* y, int n,
+                          hipStream_t stream);
 
 void profile_begin(Plan& pl);
 int profile_end(Plan& pl, double* stage_ms, int nstage);  // returns passes measured

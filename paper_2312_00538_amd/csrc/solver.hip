@@ -516,7 +516,12 @@ struct Workspace {
 };
 
 // kernel matvec of one vector (device pointers, length N)
-void kmv(Plan& pl, const double* x, double* y, hipStream_t st) { enqueue_matvec(pl, x, 1, pl.N, y, pl.N, st); }
+void kmv(Plan& pl, const double* x, double* y, hipStream_t st) {
+    if (pl.mv_hook)
+        pl.mv_hook(pl, x, y, st);
+    else
+        enqueue_matvec(pl, x, 1, pl.N, y, pl.N, st);
+}
 
 // A_hat^{-1} applied to r (first N entries); out[N] = r[N]/s when has_last
 void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, const double* r,

@@ -76,3 +76,21 @@ def test_invalid_arguments_are_rejected_before_device_work(L):
     assert L.anova_plan_create(*args(10, 3, 3, win, 1, sig)) == lib.INVALID_ARG
     assert L.anova_matvec(None, fake, 1, 10, fake, 10, None) == lib.INVALID_ARG
     assert L.anova_plan_destroy(None) == lib.OK
+
+
+def test_server_options_and_footprint(L):
+    # defaults of the request server, and the footprint it charges: grows with
+    # the problem and with the Nystrom build's extra N x k buffers
+    o = lib.ServerOpts()
+    assert L.anova_server_opts_default(ctypes.byref(o)) == lib.OK
+    assert (o.max_active, o.hbm_budget, o.share_launches, o.gather_us) == (8, 0, 1, 200.0)
+    f = lib.request_footprint
+    assert f(10_000, 9, 3) < f(100_000, 9, 3) < f(100_000, 30, 10)
+    assert f(100_000, 9, 3) > 100_000 * 9 * 8          # at least the data itself
+    ny = lib.default_ipm_opts(precond=lib.PRECOND_NYSTROM)
+    assert f(100_000, 9, 3, ipm=ny) > f(100_000, 9, 3)
+    b = ctypes.c_int64(0)
+    assert L.anova_request_footprint(0, 9, 3, None, None, ctypes.byref(b)) == lib.INVALID_ARG
+    assert L.anova_server_destroy(None) == lib.OK
+    t = ctypes.c_int64(0)
+    assert L.anova_server_submit(None, None, ctypes.byref(t)) == lib.INVALID_ARG
