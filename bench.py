@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--ipm-small-solves", type=int, default=20)
     ap.add_argument("--ipm-full-solves", type=int, default=5)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
+    ap.add_argument("--serving-requests", type=int, default=12,
+                    help="requests of the Poisson serving stream (0 = skip)")
+    ap.add_argument("--serving-rate", type=float, default=2.0)
+    ap.add_argument("--serving-max-active", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 256 MiB device-to-device three times (a known-size "
                          "reference for hardware byte counters)")
@@ -135,6 +139,46 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
             "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
             "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
             "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom"}[precond], "precision": "fp64"}
+
+
+def serving(lib, workloads, n, rate, max_active, share):
+    """Replays a Poisson stream of training requests (arrival times from the
+    stream, inputs generated beforehand) against a request server; latency is
+    submit -> result on the host, as the server measures it."""
+    import threading
+    stream = workloads.serving_stream(seed=0, n_requests=n, rate=rate)
+    probs = [workloads.gaussian_mixture(seed=r["data_seed"], N=r["N"], d=r["d"], R=0, sigma=r["sigma"], C=r["C"])
+             for r in stream]
+    srv = lib.Server(max_active=max_active, share_launches=share)
+    tickets = [None] * n
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, (r, p) in enumerate(zip(stream, probs)):
+            delay = r["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(p.X, p.labels, p.windows, p.sigma, p.C, mu0=0.0, max_ip=200)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = []
+    for i in range(n):
+        while tickets[i] is None:
+            time.sleep(0.001)
+        res.append(srv.wait(tickets[i])[1])
+    t_end = time.perf_counter()
+    th.join()
+    launches, matvecs = srv.counters()
+    srv.close()
+    lat = np.array([r["latency_ms"] for r in res])
+    span = t_end - t0 - stream[0]["arrival"]
+    return {"requests": n, "rate_per_s": rate, "max_active": max_active, "shared_launches": bool(share),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile([r["queue_ms"] for r in res], 50)),
+            "solves_per_s": n / span, "converged": int(sum(r["status"] == 0 for r in res)),
+            "matvecs_in_shared_launches": matvecs, "shared_launch_count": launches,
+            "N_max": int(max(r["N"] for r in stream)), "N_median": int(np.median([r["N"] for r in stream]))}
 
 
 def cpu_baseline(p, seconds):
@@ -281,6 +325,13 @@ def main():
                                f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
                                "Nystrom rank 200"))
     out["ipm"] = ipm
+    if a.serving_requests > 0:
+        label = (f"serving: Poisson stream, rate {a.serving_rate}/s, N log-uniform 5e3..1e6, d uniform 6..60 "
+                 "(3-feature windows), sigma log-uniform 0.5..2, C log-uniform 0.1..100; FP64 IPM, "
+                 "pivoted-Cholesky rank 200, automatic initial barrier parameter, at most 200 iterations")
+        cont = serving(lib, workloads, a.serving_requests, a.serving_rate, a.serving_max_active, True)
+        one = serving(lib, workloads, a.serving_requests, a.serving_rate, 1, False)
+        out["serving"] = {"workload": label, "continuous_batching": cont, "one_at_a_time": one}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     if a.copy_calibration:

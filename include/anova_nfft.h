@@ -162,7 +162,9 @@ typedef struct {
     double  tol_kry;     /* upper bound of the MINRES relative tolerance (1e-3)  */
     double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */
     double  gamma0;      /* step-to-boundary factor (Algorithm 1: 0.99995)       */
-    double  mu0;         /* initial barrier parameter (Algorithm 1: 1.0)         */
+    double  mu0;         /* initial barrier parameter (Algorithm 1: 1.0); <= 0:
+                            the mean complementarity |1 - y_i (KYa)_i| min(a_i, C - a_i)
+                            at the starting point, at least 1                    */
     int32_t rank;        /* low-rank factor rank k                               */
     int32_t mu_rule;     /* 0: sigma_it = 1 - (1 - sigma_bar) * (previous step);
                             1: constant sigma_bar (Section 2 allows either)      */

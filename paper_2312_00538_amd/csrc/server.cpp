@@ -75,22 +75,26 @@ class Combiner {
         thread_.join();
         (void)hipStreamDestroy(stream_);
     }
-    void solver_enter() {
-        std::lock_guard<std::mutex> g(m_);
-        ++active_;
-    }
-    void solver_leave() {
+    void solver_leave(bool& joined) {
         {
             std::lock_guard<std::mutex> g(m_);
-            --active_;
+            if (joined) --active_;
+            joined = false;
         }
         cv_.notify_all();
     }
-    // Called from a solver thread: y = K x on `st`, in a shared launch.
-    void matvec(Plan& pl, const double* x, double* y, hipStream_t st, hipEvent_t ready, hipEvent_t done) {
+    // Called from a solver thread: y = K x on `st`, in a shared launch. A solve
+    // counts as taking part (the combiner waits for its matvecs) from its
+    // first matvec until solver_leave.
+    void matvec(Plan& pl, const double* x, double* y, hipStream_t st, hipEvent_t ready, hipEvent_t done,
+                bool& joined) {
         Item it{&pl, x, y, ready, done, false, nullptr};
         ANV_HIP(hipEventRecord(ready, st));
         std::unique_lock<std::mutex> lk(m_);
+        if (!joined) {
+            ++active_;
+            joined = true;
+        }
         pending_.push_back(&it);
         if (pending_.size() == 1) first_ = clk::now();
         cv_.notify_all();
@@ -213,7 +217,7 @@ struct Server::Impl {
         std::string err;
         hipStream_t stream = nullptr;
         hipEvent_t ev_ready = nullptr, ev_done = nullptr;
-        bool entered = false;
+        bool joined = false;
         try {
             ANV_HIP(hipSetDevice(device));
             ANV_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
@@ -228,18 +232,12 @@ struct Server::Impl {
                                    hipMemcpyHostToDevice, stream));
             std::unique_ptr<Plan> pl(create_plan(Xd.p, r->N, r->d, r->d, r->windows.data(), r->P, r->sigma.data(),
                                                  nullptr, &r->nfft, stream));
-            if (comb) {
-                pl->mv_hook = [this, ev_ready, ev_done](Plan& p, const double* x, double* y, hipStream_t s) {
-                    comb->matvec(p, x, y, s, ev_ready, ev_done);
+            if (comb)
+                pl->mv_hook = [this, ev_ready, ev_done, &joined](Plan& p, const double* x, double* y, hipStream_t s) {
+                    comb->matvec(p, x, y, s, ev_ready, ev_done, joined);
                 };
-                comb->solver_enter();
-                entered = true;
-            }
             status = ipm_solve(*pl, yd.p, r->C, r->ipm, ad.p, &lambda, &st, stream);
-            if (entered) {
-                comb->solver_leave();
-                entered = false;
-            }
+            if (comb) comb->solver_leave(joined);
             ANV_HIP(hipMemcpyAsync(alpha_h.data(), ad.p, alpha_h.size() * sizeof(double), hipMemcpyDeviceToHost,
                                    stream));
             ANV_HIP(hipStreamSynchronize(stream));
@@ -250,7 +248,7 @@ struct Server::Impl {
             status = ANOVA_HIP_ERROR;
             err = e.what();
         }
-        if (entered) comb->solver_leave();
+        if (comb) comb->solver_leave(joined);
         if (stream) {
             (void)hipStreamSynchronize(stream);
             (void)hipStreamDestroy(stream);

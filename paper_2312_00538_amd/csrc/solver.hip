@@ -285,6 +285,15 @@ __global__ void k_theta(const double* __restrict__ a, int64_t N, double C, doubl
 }
 
 // u = y * a (the vector the kernel is applied to: K Y a)
+// w_i = |1 - y_i (K Y a)_i| * min(a_i, C - a_i): the complementarity that the
+// reduced gradient at lambda = 0 would give at the starting point
+__global__ void k_compl_scale(const double* __restrict__ y, const double* __restrict__ a,
+                              const double* __restrict__ kya, int64_t N, double C, double* __restrict__ w) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    w[i] = fabs(1.0 - y[i] * kya[i]) * fmin(a[i], C - a[i]);
+}
+
 __global__ void k_mul(const double* __restrict__ y, const double* __restrict__ a, int64_t N,
                       double* __restrict__ u) {
     int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
@@ -811,7 +820,8 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     ANV_CHECK(o.max_ip >= 1 && o.max_kry >= 1, "iteration caps must be >= 1");
     ANV_CHECK(o.sigma_bar > 0.0 && o.sigma_bar < 1.0, "sigma_bar must be in (0, 1)");
     ANV_CHECK(o.gamma0 > 0.0 && o.gamma0 < 1.0, "gamma0 must be in (0, 1)");
-    ANV_CHECK(o.mu0 > 0.0 && o.tol > 0.0 && o.tol_inf > 0.0 && o.tol_kry > 0.0, "tolerances must be > 0");
+    ANV_CHECK(std::isfinite(o.mu0) && o.tol > 0.0 && o.tol_inf > 0.0 && o.tol_kry > 0.0,
+              "tolerances must be > 0 and mu0 finite");
     ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
                   o.precond == ANOVA_PRECOND_NYSTROM,
@@ -898,6 +908,16 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         xa = std::fabs(sh[4]);
     };
 
+    if (!(o.mu0 > 0.0)) {
+        // automatic start: the mean complementarity implied by the reduced
+        // gradient at the starting point, never below the value 1 of Algorithm 1
+        hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, N, ya.p);
+        kmv(pl, ya.p, kya.p, st);
+        ++matvecs;
+        hipLaunchKernelGGL(k_compl_scale, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, kya.p, N, C, ytmp.p);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(N)), dim3(kT), 0, st, th.p, N, 1.0);
+        mu = std::max(1.0, red.dot(ytmp.p, th.p, N, st) / double(N));
+    }
     double xa0, xl0, D, Pr, G;
     eval_stats(xa0, xl0, D, Pr, G);
     double xa = xa0, xl = xl0;

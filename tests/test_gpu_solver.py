@@ -157,3 +157,23 @@ def test_ipm_nystrom_preconditioner(dev):
     p = workloads.gaussian_mixture(seed=1, N=600, d=20, noise=0.1, sigma=0.8, C=10.0)
     a, lam, st = _check_solve(p, 10.0, dev, rank=100, precond=lib.PRECOND_NYSTROM, seed=3)
     assert st["kry_iters_max"] <= 20
+
+
+def test_ipm_automatic_initial_barrier_reaches_the_optimum(dev):
+    # a large box bound, where Algorithm 1 started at mu0 = 1 stalls: the
+    # automatic start (mu0 <= 0) converges to the dual optimum, pinned by
+    # scikit-learn's SMO solver on the exact dense kernel
+    from sklearn.svm import SVC
+    import paper_2312_00538_amd as lib
+    p = workloads.gaussian_mixture(seed=21, N=900, d=9, sigma=0.6, C=30.0, R=0)
+    pl = _plan(p, dev)
+    alpha, lam, st = pl.solve(to_dev(p.labels, dev), p.C, mu0=0.0, max_ip=200)
+    print(st)
+    assert st["status"] == 0 and st["rel_gap"] <= 1e-6
+    K = oracle.anova_dense(p.X, p.windows, p.sigma)
+    svc = SVC(C=p.C, kernel="precomputed", tol=1e-10, max_iter=-1).fit(K, p.labels)
+    a = np.zeros(p.X.shape[0])
+    a[svc.support_] = np.abs(svc.dual_coef_[0])
+    d_svc = oracle.dual_objective(K, p.labels, a)
+    d_gpu = oracle.dual_objective(K, p.labels, alpha.cpu().numpy())
+    assert d_gpu == pytest.approx(d_svc, rel=1e-6)
