@@ -54,16 +54,6 @@ __global__ __launch_bounds__(256) void k_transpose_in(const double* __restrict__
     }
 }
 
-// vsb[g][.] = xt[perm[g]][.]: four lanes move one 64-byte row
-__global__ void k_permute_b(const float* __restrict__ xt, const int32_t* __restrict__ perm, int64_t NP,
-                            float* __restrict__ vsb) {
-    const int64_t t = blockIdx.x * int64_t(kT) + threadIdx.x;
-    if (t >= NP * 4) return;
-    const int64_t g = t / 4;
-    const int q = int(t % 4);
-    *reinterpret_cast<f4*>(vsb + g * RB + 4 * q) = *reinterpret_cast<const f4*>(xt + int64_t(perm[g]) * RB + 4 * q);
-}
-
 // LDS chunks of CHB = 32 consecutive points of a work item, moved by DMA (16
 // bytes per lane per instruction). A record occupies RPB = 32 floats: x taps,
 // y taps, z taps, and the z taps again, so that any 8 cyclically consecutive z
@@ -83,13 +73,20 @@ __device__ inline void stage_records(float* lrec, const float* __restrict__ wts,
     }
 }
 
-__device__ inline void stage_values(float* lval, const float* __restrict__ vsb, int64_t base, int cstart, int count,
-                                    int lane) {
-    const float* ub = vsb + (base + cstart) * RB;
+// Point indices of the two value rows a lane moves for the chunk starting at
+// cstart (rows past the item repeat its last point).
+__device__ inline void value_rows(const int32_t* __restrict__ perm, int64_t base, int cstart, int count, int lane,
+                                  int32_t (&pr)[2]) {
     const int last = count - 1 - cstart;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)  // 16 rows per 1 KB instruction
-        dma16(ub + min(j * 16 + lane / 4, last) * RB + (lane % 4) * 4, lval + j * 256);
+    for (int j = 0; j < 2; ++j) pr[j] = perm[base + cstart + min(j * 16 + lane / 4, last)];
+}
+
+// The 16 right-hand sides of those points, gathered from the point-major input
+// straight into LDS (16 rows per 1 KB instruction).
+__device__ inline void stage_values(float* lval, const float* __restrict__ xt, const int32_t (&pr)[2], int lane) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) dma16(xt + int64_t(pr[j]) * RB + (lane % 4) * 4, lval + j * 256);
 }
 
 // LDS byte address of a pointer into shared memory (the low half of its flat address)
@@ -161,7 +158,8 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const int32_t* __restrict__ 
                                                     const WinDev* __restrict__ wins,
                                                     const uint8_t* __restrict__ alone,
                                                     const float* __restrict__ wts,
-                                                    const float* __restrict__ vsb, int64_t N,
+                                                    const int32_t* __restrict__ perm,
+                                                    const float* __restrict__ xt, int64_t N,
                                                     float* __restrict__ slab, float* __restrict__ tgt) {
     constexpr int STEP = CHB - 4;
     __shared__ __align__(16) float srec[2][CHB * RPB];
@@ -223,8 +221,11 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const int32_t* __restrict__ 
         const uint32_t rec0 = lds_addr(&srec[0][0]), val0 = lds_addr(&sval[0][0]);
         constexpr uint32_t RECB = CHB * RPB * 4, VALB = CHB * RB * 4;  // bytes per buffer
         int cc = -1;
+        int32_t prow[2];  // value rows of the next chunk to stage, loaded a chunk ahead
         stage_records(srec[0], wts, base, 0, sg.count, lane);
-        stage_values(sval[0], vsb, base, 0, sg.count, lane);
+        value_rows(perm, base, 0, sg.count, lane, prow);
+        stage_values(sval[0], xt, prow, lane);
+        if (STEP < sg.count) value_rows(perm, base, STEP, sg.count, lane, prow);
         for (int z = sg.z0; z <= sg.z1; ++z) {
             const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
             for (int k = p; k < q; k += 4) {
@@ -235,7 +236,8 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const int32_t* __restrict__ 
                     cc = c;
                     if ((c + 1) * STEP < sg.count) {
                         stage_records(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
-                        stage_values(sval[(c + 1) & 1], vsb, base, (c + 1) * STEP, sg.count, lane);
+                        stage_values(sval[(c + 1) & 1], xt, prow, lane);
+                        if ((c + 2) * STEP < sg.count) value_rows(perm, base, (c + 2) * STEP, sg.count, lane, prow);
                     }
                 }
                 const int pt = k + lk;
@@ -262,12 +264,24 @@ __global__ __launch_bounds__(64) void k_spread_mfma(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------- gather (3 features, MFMA)
-// S[(a, r)][p] = sum_K H[(a, r)][K] B[K][p] over K = 4 ks + lk <-> (z column
-// cp = ks / 2, y tap b = 4 (ks % 2) + lk); m-block mb is x tap a. A step takes
-// the 16 points k .. k+15 of one layer (column lr of B and of S). The ring
-// holds layer z0 + ((cp - z0) mod 8) in column cp; after layer z the column
-// z mod 8 is refilled with layer z + 8 from registers loaded a layer ahead.
-__global__ __launch_bounds__(64) void k_gather_mfma(const int32_t* __restrict__ wave_items, int32_t nitems,
+// S[(a, r)][p] = sum_K H[(a, r)][K] B[K][p] over the 64 taps K <-> (y tap b, z
+// column c); m-block mb is x tap a; a step takes the 16 points k .. k+15 of one
+// layer (column lr of B and of S). The contraction runs on
+// v_mfma_f32_16x16x32_bf16 with every FP32 operand split into bf16 hi + lo
+// parts: H B ~ Hhi Bhi + Hhi Blo + Hlo Bhi (the dropped lo*lo term is below
+// 2^-16 of each product; sums stay in FP32). In k-step ks2 lane (lr, lk) holds
+// the 8 taps (b = 4 ks2 + lk, c = j), j = 0..7, i.e. one tap of every z column,
+// so refilling a column after a layer touches one element in every lane. The
+// ring holds layer z0 + ((c - z0) mod 8) in column c; after layer z the column
+// z mod 8 takes layer z + 8 from registers loaded a layer ahead.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ inline void split_bf16(float x, __bf16& hi, __bf16& lo) {
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+__global__ __launch_bounds__(64, 2) void k_gather_mfma(const int32_t* __restrict__ wave_items, int32_t nitems,
                                                     int32_t* __restrict__ queue,
                                                     const Segment* __restrict__ segs,
                                                     const int32_t* __restrict__ lstart,
@@ -296,21 +310,26 @@ __global__ __launch_bounds__(64) void k_gather_mfma(const int32_t* __restrict__ 
         const int Ey = wd.E[1], Ez = wd.E[2];
         // h[x][z][y][r]: grid cell (cx + a, cy + b, layer), rhs lr
         const float* hp = h + (wd.grid_off + int64_t(cx) * Ez * Ey + cy) * RB + lr;
-        float H[8][16];
-    #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int cp = ks / 2, b = 4 * (ks % 2) + lk;
-            const int layer = sg.z0 + ((cp - sg.z0) & 7);
-    #pragma unroll
-            for (int mb = 0; mb < 8; ++mb) H[mb][ks] = hp[((int64_t(mb) * Ez + layer) * Ey + b) * RB];
-        }
+        bf8 Hh[8][2], Hl[8][2];
+#pragma unroll
+        for (int ks2 = 0; ks2 < 2; ++ks2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int layer = sg.z0 + ((j - sg.z0) & 7);
+#pragma unroll
+                for (int mb = 0; mb < 8; ++mb) {
+                    __bf16 hi, lo;
+                    split_bf16(hp[((int64_t(mb) * Ez + layer) * Ey + 4 * ks2 + lk) * RB], hi, lo);
+                    Hh[mb][ks2][j] = hi;
+                    Hl[mb][ks2][j] = lo;
+                }
+            }
         float pre[8][2];
         if (sg.z0 < sg.z1) {
-    #pragma unroll
-            for (int mb = 0; mb < 8; ++mb) {
-                pre[mb][0] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + lk) * RB];
-                pre[mb][1] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + 4 + lk) * RB];
-            }
+#pragma unroll
+            for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+                for (int ks2 = 0; ks2 < 2; ++ks2) pre[mb][ks2] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + 4 * ks2 + lk) * RB];
         }
         const uint32_t rec0 = lds_addr(&srec[0][0]);
         constexpr uint32_t RECB = CHB * RPB * 4;
@@ -329,18 +348,35 @@ __global__ __launch_bounds__(64) void k_gather_mfma(const int32_t* __restrict__ 
                 const int pt = k + lr;
                 const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + uint32_t(pt - c * STEP) * (RPB * 4);
                 f4 wx0, wx1;
-                float wy0, wy1, wzr[8];  // wzr[cp]: z tap of the ring cell in column cp
+                float wy0, wy1, wzr[8];  // wzr[c]: z tap of the ring cell in column c
                 lds_gather_operands(rb, rb + 32 + 4 * uint32_t(lk), rb + 64 + 4 * uint32_t((-z) & 7), wx0, wx1, wy0, wy1,
                                     wzr);
-                f4 D[8];
-    #pragma unroll
-                for (int mb = 0; mb < 8; ++mb) D[mb] = f4{0.f, 0.f, 0.f, 0.f};
-    #pragma unroll
-                for (int ks = 0; ks < 16; ++ks) {
-                    const float bv = (ks % 2 ? wy1 : wy0) * wzr[ks / 2];
-    #pragma unroll
-                    for (int mb = 0; mb < 8; ++mb) D[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(H[mb][ks], bv, D[mb], 0, 0, 0);
+                bf8 Bh[2], Bl[2];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    __bf16 hi, lo;
+                    split_bf16(wy0 * wzr[j], hi, lo);
+                    Bh[0][j] = hi;
+                    Bl[0][j] = lo;
+                    split_bf16(wy1 * wzr[j], hi, lo);
+                    Bh[1][j] = hi;
+                    Bl[1][j] = lo;
                 }
+                f4 D[8];
+#pragma unroll
+                for (int mb = 0; mb < 8; ++mb) D[mb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks2 = 0; ks2 < 2; ++ks2)
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) D[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Hh[mb][ks2], Bh[ks2], D[mb], 0, 0, 0);
+#pragma unroll
+                for (int ks2 = 0; ks2 < 2; ++ks2)
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) D[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Hh[mb][ks2], Bl[ks2], D[mb], 0, 0, 0);
+#pragma unroll
+                for (int ks2 = 0; ks2 < 2; ++ks2)
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb) D[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Hl[mb][ks2], Bh[ks2], D[mb], 0, 0, 0);
                 if (pt < q) {  // the lane holds S[(a, r = 4 lk + i)][point lr]
                     f4 f = wx0[0] * D[0];
                     f += wx0[1] * D[1];
@@ -354,19 +390,27 @@ __global__ __launch_bounds__(64) void k_gather_mfma(const int32_t* __restrict__ 
                 }
             }
             if (z < sg.z1) {  // column z mod 8 takes layer z + 8; load layer z + 9 for the next column
-                const int cpz = z & 7;
-    #pragma unroll
-                for (int ks = 0; ks < 16; ++ks)
-                    if (ks / 2 == cpz) {
-    #pragma unroll
-                        for (int mb = 0; mb < 8; ++mb) H[mb][ks] = pre[mb][ks % 2];
-                    }
+                switch (z & 7) {
+#define ANV_REFILL(J)                                          \
+    case J:                                                    \
+        _Pragma("unroll") for (int mb = 0; mb < 8; ++mb)       \
+            _Pragma("unroll") for (int ks2 = 0; ks2 < 2; ++ks2) { \
+                __bf16 hi, lo;                                 \
+                split_bf16(pre[mb][ks2], hi, lo);              \
+                Hh[mb][ks2][J] = hi;                           \
+                Hl[mb][ks2][J] = lo;                           \
+            }                                                  \
+        break;
+                    ANV_REFILL(0) ANV_REFILL(1) ANV_REFILL(2) ANV_REFILL(3)
+                    ANV_REFILL(4) ANV_REFILL(5) ANV_REFILL(6) ANV_REFILL(7)
+#undef ANV_REFILL
+                }
                 if (z + 1 < sg.z1) {
-    #pragma unroll
-                    for (int mb = 0; mb < 8; ++mb) {
-                        pre[mb][0] = hp[((int64_t(mb) * Ez + z + 9) * Ey + lk) * RB];
-                        pre[mb][1] = hp[((int64_t(mb) * Ez + z + 9) * Ey + 4 + lk) * RB];
-                    }
+#pragma unroll
+                    for (int mb = 0; mb < 8; ++mb)
+#pragma unroll
+                        for (int ks2 = 0; ks2 < 2; ++ks2)
+                            pre[mb][ks2] = hp[((int64_t(mb) * Ez + z + 9) * Ey + 4 * ks2 + lk) * RB];
                 }
             }
         }
@@ -379,7 +423,8 @@ __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict_
                                                       const Segment* __restrict__ segs,
                                                       const int32_t* __restrict__ zq,
                                                       const float* __restrict__ wts,
-                                                      const float* __restrict__ vsb, int64_t N,
+                                                      const int32_t* __restrict__ perm,
+                                                      const float* __restrict__ xt, int64_t N,
                                                       float* __restrict__ slab) {
     const int64_t t = blockIdx.x * int64_t(64) + threadIdx.x;
     if (t >= int64_t(nitems) * RB) return;
@@ -410,7 +455,7 @@ __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict_
             ++zr;
         }
         const float* w = wts + gi * REC;
-        const float v = vsb[gi * RB + r];
+        const float v = xt[int64_t(perm[gi]) * RB + r];
 #pragma unroll
         for (int b = 0; b < WY; ++b) {
             const float cb = v * w[W + b];
@@ -632,7 +677,6 @@ bool batched_supported(const Plan& pl) { return pl.precision == ANOVA_PREC_MIXED
 void ensure_batched_buffers(Plan& pl) {
     if (pl.b_ready) return;
     pl.xtb.alloc(size_t(pl.N) * RB);
-    pl.vsb.alloc(size_t(pl.N) * pl.P * RB);
     pl.fsb.alloc(size_t(pl.N) * pl.P * RB);
     pl.slabb.alloc(size_t(pl.slab_total) * RB + RB);
     pl.tgtb.alloc(size_t(pl.c32a.n) * RB);
@@ -675,7 +719,7 @@ void ensure_batched_buffers(Plan& pl) {
 
 void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
     ensure_batched_buffers(pl);
-    const int64_t N = pl.N, NP = pl.N * pl.P;
+    const int64_t N = pl.N;
     for (int r0 = 0; r0 < R; r0 += RB) {
         const int rn = std::min(RB, R - r0);
         const double* xr = x + int64_t(r0) * ldx;
@@ -684,18 +728,18 @@ void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, doubl
         if (prof) pl.record_stage_event(st);
         hipLaunchKernelGGL(k_transpose_in, dim3(nblk(N, 64)), dim3(256), 0, st, xr, rn, ldx, N, pl.xtb.p,
                            pl.b_queue.p);
-        hipLaunchKernelGGL(k_permute_b, dim3(nblk(NP * 4)), dim3(kT), 0, st, pl.xtb.p, pl.perm.p, NP, pl.vsb.p);
         if (prof) pl.record_stage_event(st);
         if (pl.nwave[3])
             hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, pl.wts32.p, pl.vsb.p,
+                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, pl.wts32.p, pl.perm.p, pl.xtb.p,
                                N, pl.slabb.p, pl.tgtb.p);
         if (pl.nb_items2)
             hipLaunchKernelGGL((k_spread_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.vsb.p, N, pl.slabb.p);
+                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
+                               pl.slabb.p);
         if (pl.nb_items1)
             hipLaunchKernelGGL((k_spread_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.vsb.p, N,
+                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
                                pl.slabb.p);
         if (prof) pl.record_stage_event(st);
         if (pl.nflist)

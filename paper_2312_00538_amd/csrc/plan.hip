@@ -183,7 +183,7 @@ int64_t Plan::device_bytes() const {
                    wts32.bytes() + segs.bytes() + fold.bytes() + tmat.bytes() + xw.bytes() +
                    vs.bytes() + fs.bytes() + g64.bytes() + h64.bytes() + c64a.bytes() +
                    c64b.bytes() + g32.bytes() + h32.bytes() + c32a.bytes() + c32b.bytes() +
-                   slab64.bytes() + slab32.bytes() + xtb.bytes() + vsb.bytes() + fsb.bytes() + slabb.bytes() +
+                   slab64.bytes() + slab32.bytes() + xtb.bytes() + fsb.bytes() + slabb.bytes() +
                    tgtb.bytes() + g1b.bytes() + hb.bytes() + b_items.bytes() + b_queue.bytes());
 }
 

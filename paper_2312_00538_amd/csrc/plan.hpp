@@ -69,12 +69,12 @@ struct Plan {
     DevBuf<float> slab32;
 
     // batched path (16 right-hand sides per pass, mixed precision), allocated on
-    // first use: inputs [N][16] and [P*N][16], slabs, fold targets, grids and
+    // first use: inputs [N][16] (point order), slabs, fold targets, grids and
     // gathered values, each with the 16 right-hand sides innermost
     int32_t batch_min_rhs = 2;
     bool b_ready = false;
     int32_t b_rsplit = 2;       // grid-step blocks per slice (right-hand sides split for LDS)
-    DevBuf<float> xtb, vsb, fsb, slabb, tgtb, g1b, hb;
+    DevBuf<float> xtb, fsb, slabb, tgtb, g1b, hb;
     DevBuf<int32_t> b_items;    // work items of 2-feature then 1-feature windows
     DevBuf<int32_t> b_queue;    // work-queue counters of the matrix-core spread and gather
     int32_t b_grid[2] = {1, 1}; // their persistent grid sizes
