@@ -288,36 +288,32 @@ __global__ __launch_bounds__(256) void k_fold_cols(const MvLaunch ML) {
     const int L = int(fl % wd.E[2]);
     const int64_t col = fl / wd.E[2];
     const int cx = int(col / wd.nb[1]), cy = int(col % wd.nb[1]);
-    const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
+    // lane = (part, footprint position): the items covering the cell are dealt
+    // to the parts in turn (windows with fewer than 64 positions use the spare
+    // lanes), and the parts' sums are added in part order
+    const int lanes = wd.lanes, parts = 64 / lanes;
+    const int pos = lane % lanes, part = lane / lanes;
+    const int a = pos / wd.Wslot[1], b = pos % wd.Wslot[1];
     const int2 r = fold[f];
     double acc = 0.0;
-    // the items' slab offsets are fetched 64 at a time by one vector load and
-    // broadcast, so the slab reads of a batch are all in flight together
-    for (int s0 = r.x; s0 < r.y; s0 += 64) {
-        const int n = min(64, r.y - s0);
-        const int64_t myoff = lane < n ? sbase[s0 + lane] : 0;
-        const int64_t row = int64_t(L) * wd.lanes + lane;
-        const bool act = lane < wd.lanes;  // lanes beyond the footprint only relay offsets
-        int q = 0;
-        for (; q + 4 <= n; q += 4) {
-            const int64_t o0 = __shfl(myoff, q, 64), o1 = __shfl(myoff, q + 1, 64);
-            const int64_t o2 = __shfl(myoff, q + 2, 64), o3 = __shfl(myoff, q + 3, 64);
-            const WT v0 = act ? slab[o0 + row] : WT(0);
-            const WT v1 = act ? slab[o1 + row] : WT(0);
-            const WT v2 = act ? slab[o2 + row] : WT(0);
-            const WT v3 = act ? slab[o3 + row] : WT(0);
+    if (part < parts) {
+        const int64_t row = int64_t(L) * lanes + pos;
+        int s = r.x + part;
+        for (; s + 3 * parts < r.y; s += 4 * parts) {
+            const int64_t o0 = sbase[s], o1 = sbase[s + parts], o2 = sbase[s + 2 * parts], o3 = sbase[s + 3 * parts];
+            const WT v0 = slab[o0 + row], v1 = slab[o1 + row], v2 = slab[o2 + row], v3 = slab[o3 + row];
             acc += double(v0);
             acc += double(v1);
             acc += double(v2);
             acc += double(v3);
         }
-        for (; q < n; ++q) {
-            const int64_t o = __shfl(myoff, q, 64);
-            acc += act ? double(slab[o + row]) : 0.0;
-        }
+        for (; s < r.y; s += parts) acc += double(slab[sbase[s] + row]);
     }
+    double tot = 0.0;
+    for (int q = 0; q < parts; ++q) tot += __shfl(acc, q * lanes + pos, 64);
+    acc = tot;
     if (lane >= wd.lanes) return;
-    const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + lane) * wd.E[2] + L;
+    const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + pos) * wd.E[2] + L;
     tgt[wd.tgt_off + t] = WT(acc);
 }
 

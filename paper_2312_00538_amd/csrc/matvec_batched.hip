@@ -525,30 +525,47 @@ __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ 
                                                      const int64_t* __restrict__ flist, const int2* __restrict__ fold,
                                                      const int64_t* __restrict__ sbase, const float* __restrict__ slab,
                                                      float* __restrict__ tgt) {
+    __shared__ double red[256][4];
     const int64_t fi = blockIdx.x;
     if (fi >= nlist) return;
     const int64_t f = flist[fi];
     int l = 0;
     while (l + 1 < P && wins[l + 1].fold_off <= f) ++l;
     const WinDev& wd = wins[l];
-    const int lane = threadIdx.x / 4, q4 = threadIdx.x % 4;  // footprint position, rhs quad
-    if (lane >= wd.lanes) return;
+    // thread = (part, footprint position, rhs quad): the items covering the cell
+    // are dealt to the parts in turn, and the parts' sums are added in part order
+    const int lanes = wd.lanes, parts = 64 / lanes;
+    const int t = threadIdx.x, q4 = t % 4, rest = t / 4;
+    const int pos = rest % lanes, part = rest / lanes;
     const int64_t fl = f - wd.fold_off;
     const int L = int(fl % wd.E[2]);
     const int64_t col = fl / wd.E[2];
     const int cx = int(col / wd.nb[1]), cy = int(col % wd.nb[1]);
-    const int a = lane / wd.Wslot[1], b = lane % wd.Wslot[1];
+    const int a = pos / wd.Wslot[1], b = pos % wd.Wslot[1];
     const int2 rr = fold[f];
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-    for (int s = rr.x; s < rr.y; ++s) {
-        const f4 v = *reinterpret_cast<const f4*>(slab + (sbase[s] + int64_t(L) * wd.lanes + lane) * RB + 4 * q4);
-        s0 += v[0];
-        s1 += v[1];
-        s2 += v[2];
-        s3 += v[3];
+    if (part < parts) {
+        for (int s = rr.x + part; s < rr.y; s += parts) {
+            const f4 v = *reinterpret_cast<const f4*>(slab + (sbase[s] + int64_t(L) * lanes + pos) * RB + 4 * q4);
+            s0 += v[0];
+            s1 += v[1];
+            s2 += v[2];
+            s3 += v[3];
+        }
     }
-    const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + lane) * wd.E[2] + L;
-    *reinterpret_cast<f4*>(tgt + (wd.tgt_off + t) * RB + 4 * q4) = f4{float(s0), float(s1), float(s2), float(s3)};
+    red[t][0] = s0;
+    red[t][1] = s1;
+    red[t][2] = s2;
+    red[t][3] = s3;
+    __syncthreads();
+    if (part != 0 || rest >= lanes) return;
+    double o[4] = {0, 0, 0, 0};
+    for (int q = 0; q < parts; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[i] += red[(q * lanes + pos) * 4 + q4][i];
+    const int64_t tt = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * lanes + pos) * wd.E[2] + L;
+    *reinterpret_cast<f4*>(tgt + (wd.tgt_off + tt) * RB + 4 * q4) =
+        f4{float(o[0]), float(o[1]), float(o[2]), float(o[3])};
 }
 
 // fold step B + y and z passes; block per (x slice, window, half of the rhs)
@@ -674,12 +691,41 @@ __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ 
 
 bool batched_supported(const Plan& pl) { return pl.precision == ANOVA_PREC_MIXED && pl.W == 8; }
 
+namespace {
+__global__ void k_to_f32(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) b[i] = float(a[i]);
+}
+}  // namespace
+
+void enqueue_matvec_sketch(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
+    if (pl.W != 8 || R < 2) {
+        enqueue_matvec(pl, x, R, ldx, y, ldy, st);
+        return;
+    }
+    if (pl.precision == ANOVA_PREC_FP64 && pl.wts32.n == 0) {
+        static_assert(rec_stride(8, 8) == rec_stride(8, 4), "FP64 and FP32 records hold the same elements");
+        pl.wts32.alloc(pl.wts64.n);
+        hipLaunchKernelGGL(k_to_f32, dim3(nblk(int64_t(pl.wts64.n))), dim3(kT), 0, st, pl.wts64.p,
+                           int64_t(pl.wts64.n), pl.wts32.p);
+    }
+    enqueue_matvec_batched(pl, x, R, ldx, y, ldy, st);
+}
+
+void release_batched_buffers(Plan& pl) {
+    for (DevBuf<float>* b : {&pl.xtb, &pl.fsb, &pl.slabb, &pl.tgtb, &pl.g1b, &pl.hb}) b->release();
+    pl.b_items.release();
+    pl.b_queue.release();
+    if (pl.precision == ANOVA_PREC_FP64) pl.wts32.release();
+    pl.b_ready = false;
+}
+
 void ensure_batched_buffers(Plan& pl) {
     if (pl.b_ready) return;
     pl.xtb.alloc(size_t(pl.N) * RB);
     pl.fsb.alloc(size_t(pl.N) * pl.P * RB);
     pl.slabb.alloc(size_t(pl.slab_total) * RB + RB);
-    pl.tgtb.alloc(size_t(pl.c32a.n) * RB);
+    pl.tgtb.alloc(size_t(pl.tgt_total) * RB);
     pl.g1b.alloc(size_t(pl.grid_total) * RB);
     pl.hb.alloc(size_t(pl.grid_total) * RB);
     // items of 1- and 2-feature windows as flat lists (lane kernels take (item, rhs) per lane)

@@ -407,6 +407,17 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
 
     // 6. work items: runs of at most seg_points sorted points of one column, and
     //    for every (column, layer) the contiguous range of items that touch it
+    //    1- and 2-feature windows run one lane per item: their items are sized so
+    //    that about 32K lanes (512 wavefronts) share the points, 8..128 points each
+    {
+        int64_t lane_points = 0;
+        for (int l = 0; l < P; ++l) {
+            int dw = 0;
+            for (int s2 = 0; s2 < 3; ++s2) dw += pl->slot_feat[l][s2] >= 0;
+            if (dw < 3) lane_points += N;
+        }
+        pl->seg_points_lane = int32_t(std::min<int64_t>(128, std::max<int64_t>(8, lane_points / 32768)));
+    }
     std::vector<int2> fold_h;
     int64_t slab_off = 0, col_total = 0;
     for (int l = 0; l < P; ++l) {
@@ -550,6 +561,7 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
             off += int64_t(wd.E[0]) * wd.E[1] * wd.E[2] * wd.lanes;
         }
         tgt_total = std::max(tgt_total, off);
+        pl->tgt_total = tgt_total;
         ANV_HIP(hipMemcpyAsync(pl->wins_d.p, pl->wins_h.data(), pl->wins_h.size() * sizeof(WinDev),
                                hipMemcpyHostToDevice, st));
     }

@@ -15,7 +15,7 @@ struct Plan {
     NfftParams prm;
     int32_t precision = ANOVA_PREC_FP64;
     int32_t seg_points = 768;   // work-item length for 3-feature windows
-    int32_t seg_points_lane = 128;  // work-item length for 1- and 2-feature windows
+    int32_t seg_points_lane = 128;  // work-item length for 1- and 2-feature windows (set by the plan)
     std::vector<int32_t> win;   // P x 3 as given
     std::vector<double> sigma, eta;
     std::vector<std::array<int32_t, 3>> slot_feat;  // feature per slot, -1 = dummy
@@ -57,6 +57,7 @@ struct Plan {
     int64_t grid_max = 0;       // largest window grid
     int32_t emax[3] = {1, 1, 1}; // largest occupied extent per slot over windows
     int64_t slab_total = 0;
+    int64_t tgt_total = 0;      // fold target-major buffer: cells x footprint positions
 
     // original windowed coordinates [N][P][3] (exact kernel columns)
     DevBuf<double> xw;
@@ -151,6 +152,13 @@ void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, in
 bool batched_supported(const Plan& pl);
 void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                             hipStream_t stream);
+// A matvec of R right-hand sides at FP32 accuracy, for random sketches that only
+// need an approximation of K: the batched kernels (an FP64 plan converts its
+// weights to FP32 on first use) when the cutoff allows, else enqueue_matvec.
+void enqueue_matvec_sketch(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
+                           hipStream_t stream);
+// frees the batched path's buffers (and the FP32 weights of an FP64 plan)
+void release_batched_buffers(Plan& pl);
 
 // y_i = K_i x_i for n (plan, vector) pairs, one vector per plan: the plans'
 // stages share launches (grouped by cutoff and precision, up to kMaxJobs plans).

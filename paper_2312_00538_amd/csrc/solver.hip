@@ -42,13 +42,15 @@ __device__ void block_sums(double (&v)[NS], double* __restrict__ out) {
     }
 }
 
-// fold block partials [nb][ns] in block order: out[q] = sum_b part[b][q]
+// fold block partials [nb][ns]: out[q] = sum_b part[b][q], one wavefront per q;
+// lane j adds blocks j, j + 64, ... in order, then a fixed xor tree adds the lanes
 __global__ void k_fold_partials(const double* __restrict__ part, int nb, int ns, double* __restrict__ out) {
-    int q = threadIdx.x;
-    if (q >= ns) return;
+    const int q = blockIdx.x, j = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b * ns + q];
-    out[q] = s;
+    for (int b = j; b < nb; b += 64) s += part[b * ns + q];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (j == 0) out[q] = s;
 }
 
 // up to 4 dot products sum_i a_q[i] * b_q[i] over [0, n)
@@ -165,23 +167,6 @@ __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
 }
 
 // ------------------------------------------------------------------ low-rank products
-// w[j] = sum_i Z[j*N + i] * u[i] (block j, fixed-order block reduction)
-__global__ void k_gemv_t(const double* __restrict__ Z, int64_t N, const double* __restrict__ u,
-                         double* __restrict__ w) {
-    const int j = blockIdx.x;
-    const double* zc = Z + int64_t(j) * N;
-    double v[1] = {0.0};
-    for (int64_t i = threadIdx.x; i < N; i += kT) v[0] += zc[i] * u[i];
-    __shared__ double sh[kT];
-    sh[threadIdx.x] = v[0];
-    __syncthreads();
-    for (int s = kT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) w[j] = sh[0];
-}
-
 // part[c] = sum_{i in chunk c} A_i B_i^T / theta_i (k x k; theta NULL = 1): one block per
 // 16 x 16 output tile and row chunk; the chunk partials are folded in order.
 constexpr int kSy = 16;
@@ -214,6 +199,142 @@ __global__ void k_gram_partial(const double* __restrict__ Z, const double* __res
     if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc;
 }
 
+// Weighted Gram matrix on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// part[c][a][b] = sum_{i in chunk c} Z_a(i) Z_b(i) / theta_i for a >= b (the
+// upper triangle is filled only inside diagonal super-tiles). Block = 4 waves on
+// one pair (sa >= sb) of 128-column super-tiles and one row chunk; wave w owns
+// tile rows 2w, 2w+1 x all 8 tile columns (16 accumulators of 16 x 16). Rows go
+// through LDS in panels of 16 (four k-steps of 4 rows). FP64 16x16x4 operand
+// layout: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; element e of
+// the result is D[l / 16 + 4 e][l % 16].
+constexpr int kST = 128;   // super-tile columns
+constexpr int kSP = 16;    // panel rows
+__global__ __launch_bounds__(256) void k_syrk_mfma(const double* __restrict__ Z, int64_t N, int k,
+                                                   const double* __restrict__ theta, int64_t chunk,
+                                                   double* __restrict__ part) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double pa[kST][kSP + 1], pb[kST][kSP + 1], wt[kSP];
+    int sa = 0;
+    while ((sa + 1) * (sa + 2) / 2 <= int(blockIdx.x)) ++sa;
+    const int sb = int(blockIdx.x) - sa * (sa + 1) / 2;
+    const int c = blockIdx.y;
+    const int64_t i0 = int64_t(c) * chunk, i1 = std::min<int64_t>(N, i0 + chunk);
+    const int t = threadIdx.x, w = t / 64, l = t % 64, lm = l % 16, lg = l / 16;
+    d4 acc[2][8];
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < 8; ++tc) acc[tr][tc] = d4{0.0, 0.0, 0.0, 0.0};
+    // the next panel is loaded into registers while the current one is multiplied
+    constexpr int PE = kST * kSP / 256;  // panel elements per thread and operand
+    double ra[PE], rb[PE], rw = 0.0;
+    auto load_panel = [&](int64_t ib0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int e = t + 256 * q, col = e / kSP, r = e % kSP;
+            const int64_t i = ib0 + r;
+            const int ga = sa * kST + col, gb = sb * kST + col;
+            ra[q] = (ga < k && i < i1) ? Z[int64_t(ga) * N + i] : 0.0;
+            rb[q] = (gb < k && i < i1) ? Z[int64_t(gb) * N + i] : 0.0;
+        }
+        if (t < kSP) {
+            const int64_t i = ib0 + t;
+            rw = (i < i1) ? (theta ? 1.0 / theta[i] : 1.0) : 0.0;
+        }
+    };
+    if (i0 < i1) load_panel(i0);
+    for (int64_t ib0 = i0; ib0 < i1; ib0 += kSP) {
+#pragma unroll
+        for (int q = 0; q < PE; ++q) {
+            const int e = t + 256 * q;
+            pa[e / kSP][e % kSP] = ra[q];
+            pb[e / kSP][e % kSP] = rb[q];
+        }
+        if (t < kSP) wt[t] = rw;
+        __syncthreads();
+        if (ib0 + kSP < i1) load_panel(ib0 + kSP);
+#pragma unroll
+        for (int s4 = 0; s4 < kSP / 4; ++s4) {
+            const int r = 4 * s4 + lg;
+            double av[2];
+#pragma unroll
+            for (int tr = 0; tr < 2; ++tr) av[tr] = pa[(2 * w + tr) * 16 + lm][r] * wt[r];
+#pragma unroll
+            for (int tc = 0; tc < 8; ++tc) {
+                const double bv = pb[tc * 16 + lm][r];
+#pragma unroll
+                for (int tr = 0; tr < 2; ++tr) acc[tr][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tr], bv, acc[tr][tc], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int tr = 0; tr < 2; ++tr)
+#pragma unroll
+        for (int tc = 0; tc < 8; ++tc)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int ia = sa * kST + (2 * w + tr) * 16 + lg + 4 * e, ib = sb * kST + tc * 16 + lm;
+                if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc[tr][tc][e];
+            }
+}
+
+// M[a][b] = diag [a == b] + sum_c part[c][max(a,b)][min(a,b)] (chunks in order)
+__global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, double diag,
+                            double* __restrict__ M) {
+    const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (e >= int64_t(k) * k) return;
+    const int a = int(e / k), b = int(e % k);
+    const int64_t src = int64_t(a >= b ? a : b) * k + (a >= b ? b : a);
+    double s = (a == b) ? diag : 0.0;
+    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * k * k + src];
+    M[e] = s;
+}
+
+// row chunks of k_syrk_mfma: enough blocks to fill the GPU, partials within 256 MB,
+// chunks a whole number of panels
+void syrk_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
+    const int ns = (k + kST - 1) / kST, pairs = ns * (ns + 1) / 2;
+    int64_t want = std::max<int64_t>(1, (1024 + pairs - 1) / pairs);
+    want = std::min<int64_t>(want, std::max<int64_t>(1, (int64_t(256) << 20) / (int64_t(k) * k * 8)));
+    want = std::min<int64_t>(want, std::max<int64_t>(1, N / kSP));
+    chunk = (N + want - 1) / want;
+    chunk = (chunk + kSP - 1) / kSP * kSP;
+    nchunk = int((N + chunk - 1) / chunk);
+}
+
+// w_part[s][j] = sum over rows of segment s of Z[j N + i] u[i]: one block per
+// (column j, segment s), so that the product of a long column keeps the GPU busy
+__global__ void k_gemv_t_seg(const double* __restrict__ Z, int64_t N, const double* __restrict__ u,
+                             int64_t seg, double* __restrict__ wpart) {
+    const int j = blockIdx.x, sgi = blockIdx.y;
+    const int64_t r0 = int64_t(sgi) * seg, r1 = std::min<int64_t>(N, r0 + seg);
+    const double* zc = Z + int64_t(j) * N;
+    double a0 = 0.0, a1 = 0.0;
+    int64_t i = r0 + threadIdx.x;
+    for (; i + kT < r1; i += 2 * kT) {
+        a0 += zc[i] * u[i];
+        a1 += zc[i + kT] * u[i + kT];
+    }
+    if (i < r1) a0 += zc[i] * u[i];
+    __shared__ double sh[kT];
+    sh[threadIdx.x] = a0 + a1;
+    __syncthreads();
+    for (int s = kT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) wpart[int64_t(sgi) * gridDim.x + j] = sh[0];
+}
+
+__global__ void k_gemv_t_fold(const double* __restrict__ wpart, int nseg, int k, double* __restrict__ w) {
+    const int j = blockIdx.x * kT + threadIdx.x;
+    if (j >= k) return;
+    double s = 0.0;
+    for (int q = 0; q < nseg; ++q) s += wpart[int64_t(q) * k + j];
+    w[j] = s;
+}
+
 __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, double diag,
                             double* __restrict__ M) {
     int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
@@ -223,55 +344,150 @@ __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, 
     M[e] = s;
 }
 
-// in-place Cholesky of the k x k SPD matrix M (row-major, lower triangle used),
-// one block; status[0] = 0 ok, 1 = non-positive pivot
-__global__ void k_chol(double* __restrict__ M, int k, int* __restrict__ status) {
-    __shared__ double piv;
+// In-place Cholesky of the k x k SPD matrix M (row-major, lower triangle used),
+// one block, right-looking in panels of 16 columns: the first wavefront factors
+// the diagonal block in registers (lane r holds row r, shuffles broadcast the
+// pivots), all threads solve the panel below it (one row each) and update the
+// trailing lower triangle. status[0] = 0 ok, 1 = non-positive pivot.
+constexpr int kCB = 16;
+__global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int k, int* __restrict__ status) {
+    __shared__ double D[kCB][kCB + 1];
     __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    for (int j = 0; j < k; ++j) {
-        if (threadIdx.x == 0) {
-            double v = M[j * k + j];
-            if (!(v > 0.0)) {
-                bad = 1;
-                v = 1e-300;
+    const int t = threadIdx.x;
+    if (t == 0) bad = 0;
+    for (int j0 = 0; j0 < k; j0 += kCB) {
+        const int nb = min(kCB, k - j0);
+        __syncthreads();  // the previous trailing update is complete
+        if (t < 64) {
+            double d[kCB];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) d[c] = (t < nb && c <= t) ? M[int64_t(j0 + t) * k + j0 + c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) {
+                if (c < nb) {
+                    double dcc = __shfl(d[c], c, 64);
+                    if (!(dcc > 0.0)) {
+                        if (t == 0) bad = 1;
+                        dcc = 1e-300;
+                    }
+                    dcc = sqrt(dcc);
+                    if (t == c) d[c] = dcc;
+                    else if (t > c) d[c] /= dcc;
+#pragma unroll
+                    for (int cc = c + 1; cc < kCB; ++cc) {
+                        const double lcc = __shfl(d[c], cc, 64);  // L[cc][c], from lane cc
+                        if (cc <= t && t < nb) d[cc] -= d[c] * lcc;
+                    }
+                }
             }
-            piv = sqrt(v);
-            M[j * k + j] = piv;
+            if (t < nb) {
+#pragma unroll
+                for (int c = 0; c < kCB; ++c)
+                    if (c <= t) {
+                        M[int64_t(j0 + t) * k + j0 + c] = d[c];
+                        D[t][c] = d[c];
+                    }
+            }
         }
         __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) M[i * k + j] /= piv;
-        __syncthreads();
-        // trailing update of the lower triangle, row by row
-        for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
-            int i = j + 1 + e / (k - j - 1), c = j + 1 + e % (k - j - 1);
-            if (c <= i) M[i * k + c] -= M[i * k + j] * M[c * k + j];
+        // panel: rows below the block, x L_D^T = m
+        for (int i = j0 + nb + t; i < k; i += blockDim.x) {
+            double x[kCB];
+            double* mi = M + int64_t(i) * k + j0;
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) x[c] = c < nb ? mi[c] : 0.0;  // all loads before any store
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) {
+                if (c < nb) {
+                    double v = x[c];
+#pragma unroll
+                    for (int q = 0; q < c; ++q) v -= x[q] * D[c][q];
+                    x[c] = v / D[c][c];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kCB; ++c)
+                if (c < nb) mi[c] = x[c];
         }
         __syncthreads();
+        // trailing lower triangle
+        const int m = k - j0 - nb;
+        for (int e = t; e < m * m; e += blockDim.x) {
+            const int r = e / m, cc = e % m;
+            if (cc > r) continue;
+            const double* li = M + int64_t(j0 + nb + r) * k + j0;
+            const double* lc = M + int64_t(j0 + nb + cc) * k + j0;
+            double sacc = 0.0;
+            for (int q = 0; q < nb; ++q) sacc += li[q] * lc[q];
+            M[int64_t(j0 + nb + r) * k + j0 + nb + cc] -= sacc;
+        }
     }
-    if (threadIdx.x == 0) status[0] = bad;
+    __syncthreads();
+    if (t == 0) status[0] = bad;
 }
 
-// t = (L L^T)^{-1} w with L the Cholesky factor in M (one block, in place on t)
+// t = (L L^T)^{-1} w with L the Cholesky factor in M (one block, panels of 16).
+// The first wavefront solves each diagonal block in registers (forward: lane j
+// holds row j of the block; backward: lane j holds column j), all threads then
+// update the remaining entries.
 __global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double* __restrict__ w,
                              double* __restrict__ t) {
     extern __shared__ double sx[];
-    for (int i = threadIdx.x; i < k; i += blockDim.x) sx[i] = w[i];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < k; i += blockDim.x) sx[i] = w[i];
     __syncthreads();
-    for (int j = 0; j < k; ++j) {  // forward: L z = w
-        if (threadIdx.x == 0) sx[j] /= Lm[j * k + j];
+    for (int j0 = 0; j0 < k; j0 += kCB) {  // forward: L z = w
+        const int nb = min(kCB, k - j0);
+        if (tid < 64) {
+            double d[kCB];
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) d[c] = (tid < nb && c <= tid) ? Lm[int64_t(j0 + tid) * k + j0 + c] : 0.0;
+            double b = tid < nb ? sx[j0 + tid] : 0.0;
+#pragma unroll
+            for (int c = 0; c < kCB; ++c) {
+                if (c < nb) {
+                    const double xc = __shfl(b, c, 64) / __shfl(d[c], c, 64);
+                    if (tid == c) b = xc;
+                    else if (tid > c) b -= d[c] * xc;
+                }
+            }
+            if (tid < nb) sx[j0 + tid] = b;
+        }
         __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) sx[i] -= Lm[i * k + j] * sx[j];
+        for (int i = j0 + nb + tid; i < k; i += blockDim.x) {
+            const double* lr = Lm + int64_t(i) * k + j0;
+            double v = 0.0;
+            for (int q = 0; q < nb; ++q) v += lr[q] * sx[j0 + q];
+            sx[i] -= v;
+        }
         __syncthreads();
     }
-    for (int j = k - 1; j >= 0; --j) {  // backward: L^T t = z
-        if (threadIdx.x == 0) sx[j] /= Lm[j * k + j];
+    for (int j1 = k; j1 > 0; j1 -= kCB) {  // backward: L^T t = z
+        const int j0 = max(0, j1 - kCB), nb = j1 - j0;
+        if (tid < 64) {
+            double d[kCB];  // column tid of the block: d[q] = L[j0 + q][j0 + tid]
+#pragma unroll
+            for (int q = 0; q < kCB; ++q) d[q] = (tid < nb && q < nb && q >= tid) ? Lm[int64_t(j0 + q) * k + j0 + tid] : 0.0;
+            double b = tid < nb ? sx[j0 + tid] : 0.0;
+#pragma unroll
+            for (int c = kCB - 1; c >= 0; --c) {
+                if (c < nb) {
+                    const double xc = __shfl(b, c, 64) / __shfl(d[c], c, 64);
+                    if (tid == c) b = xc;
+                    else if (tid < c) b -= d[c] * xc;
+                }
+            }
+            if (tid < nb) sx[j0 + tid] = b;
+        }
         __syncthreads();
-        for (int i = threadIdx.x; i < j; i += blockDim.x) sx[i] -= Lm[j * k + i] * sx[j];
+        for (int i = tid; i < j0; i += blockDim.x) {
+            double v = 0.0;
+            for (int q = 0; q < nb; ++q) v += Lm[int64_t(j0 + q) * k + i] * sx[j0 + q];
+            sx[i] -= v;
+        }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < k; i += blockDim.x) t[i] = sx[i];
+    for (int i = tid; i < k; i += blockDim.x) t[i] = sx[i];
 }
 
 // ------------------------------------------------------------------ IPM vector kernels
@@ -500,7 +716,7 @@ struct Reducer {
     const double* dots(const DotArgs& d, int64_t n, hipStream_t st) {
         unsigned nb = blocks(n);
         hipLaunchKernelGGL(k_dots<NS>, dim3(nb), dim3(kT), 0, st, d, n, part.p);
-        hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(64), 0, st, part.p, int(nb), NS, out.p);
+        hipLaunchKernelGGL(k_fold_partials, dim3(NS), dim3(64), 0, st, part.p, int(nb), NS, out.p);
         ANV_HIP(hipMemcpyAsync(host, out.p, NS * sizeof(double), hipMemcpyDeviceToHost, st));
         ANV_HIP(hipStreamSynchronize(st));
         return host;
@@ -520,8 +736,11 @@ struct Workspace {
     DevBuf<double> M, Mpart, w, t;        // capacitance and its factor
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
+    DevBuf<double> wpart;                 // per-segment partials of Z^T u
     int nchunk = 0;
     int64_t chunk = 0;
+    int nseg = 1;
+    int64_t seg = 1;
 };
 
 // kernel matvec of one vector (device pointers, length N)
@@ -538,7 +757,9 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
     const int64_t N = pl.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
-        hipLaunchKernelGGL(k_gemv_t, dim3(ws.k), dim3(kT), 0, st, ws.Z.p, N, ws.tmp.p, ws.w.p);
+        hipLaunchKernelGGL(k_gemv_t_seg, dim3(ws.k, ws.nseg), dim3(kT), 0, st, ws.Z.p, N, ws.tmp.p, ws.seg,
+                           ws.wpart.p);
+        hipLaunchKernelGGL(k_gemv_t_fold, dim3(nblk(ws.k)), dim3(kT), 0, st, ws.wpart.p, ws.nseg, ws.k, ws.w.p);
         hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.w.p,
                            ws.t.p);
     }
@@ -549,10 +770,10 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
 void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t st) {
     if (ws.k == 0) return;
     const int k = ws.k;
-    const int tiles = (k + kSy - 1) / kSy;
-    hipLaunchKernelGGL(k_gram_partial, dim3(tiles, tiles, ws.nchunk), dim3(kT), 0, st, ws.Z.p, ws.Z.p, pl.N, k,
-                       th, ws.chunk, ws.Mpart.p);
-    hipLaunchKernelGGL(k_gram_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
+    const int ns = (k + kST - 1) / kST;
+    hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st, ws.Z.p,
+                       pl.N, k, th, ws.chunk, ws.Mpart.p);
+    hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, ws.M.p, k, ws.status.p);
     int bad = 0;
@@ -569,11 +790,12 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
         ws.w.alloc(k);
         ws.t.alloc(k);
         ws.status.alloc(1);
-        ws.chunk = 8192;
-        ws.nchunk = int((N + ws.chunk - 1) / ws.chunk);
-        ws.nchunk = std::min(ws.nchunk, 256);
-        ws.chunk = (N + ws.nchunk - 1) / ws.nchunk;
+        syrk_chunks(N, k, ws.nchunk, ws.chunk);
         ws.Mpart.alloc(size_t(ws.nchunk) * k * k);
+        // segments of Z^T u: about 2048 blocks in all
+        ws.nseg = int(std::max<int64_t>(1, std::min<int64_t>((2048 + k - 1) / k, (N + 4095) / 4096)));
+        ws.seg = (N + ws.nseg - 1) / ws.nseg;
+        ws.wpart.alloc(size_t(ws.nseg) * k);
     }
     ws.tmp.alloc(N + 1);
     ws.kyz.alloc(N + 1);
@@ -674,21 +896,31 @@ std::vector<double> inv_lower_transposed(const std::vector<double>& L, int k) {
 
 struct Gram {
     DevBuf<double> part, M;
-    int nchunk = 1;
-    int64_t chunk = 1;
+    int nchunk = 1, nchunk_s = 1;
+    int64_t chunk = 1, chunk_s = 1;
     void setup(int64_t N, int k) {
         chunk = 8192;
         nchunk = int(std::min<int64_t>(256, (N + chunk - 1) / chunk));
         chunk = (N + nchunk - 1) / nchunk;
-        part.alloc(size_t(nchunk) * k * k);
+        syrk_chunks(N, k, nchunk_s, chunk_s);
+        part.alloc(size_t(std::max(nchunk, nchunk_s)) * k * k);
         M.alloc(size_t(k) * k);
     }
-    // host copy of A^T B (k x k, row-major)
+    // host copy of A^T B (k x k, row-major); A == B goes to the matrix cores
     std::vector<double> run(const double* A, const double* B, int64_t N, int k, hipStream_t st) {
-        const int tiles = (k + kSy - 1) / kSy;
-        hipLaunchKernelGGL(k_gram_partial, dim3(tiles, tiles, nchunk), dim3(kT), 0, st, A, B, N, k,
-                           (const double*)nullptr, chunk, part.p);
-        hipLaunchKernelGGL(k_gram_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, part.p, nchunk, k, 0.0, M.p);
+        if (A == B) {
+            const int ns = (k + kST - 1) / kST;
+            hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(nchunk_s)), dim3(256), 0, st, A,
+                               N, k, (const double*)nullptr, chunk_s, part.p);
+            hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, part.p, nchunk_s, k, 0.0,
+                               M.p);
+        } else {
+            const int tiles = (k + kSy - 1) / kSy;
+            hipLaunchKernelGGL(k_gram_partial, dim3(tiles, tiles, nchunk), dim3(kT), 0, st, A, B, N, k,
+                               (const double*)nullptr, chunk, part.p);
+            hipLaunchKernelGGL(k_gram_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, part.p, nchunk, k, 0.0,
+                               M.p);
+        }
         std::vector<double> h(size_t(k) * k);
         ANV_HIP(hipMemcpyAsync(h.data(), M.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         ANV_HIP(hipStreamSynchronize(st));
@@ -897,7 +1129,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         kmv(pl, ya.p, kya.p, st);
         ++matvecs;
         hipLaunchKernelGGL(k_ipm_stats, dim3(rb), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, spart.p);
-        hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(64), 0, st, spart.p, int(rb), 5, sout.p);
+        hipLaunchKernelGGL(k_fold_partials, dim3(5), dim3(64), 0, st, spart.p, int(rb), 5, sout.p);
         ANV_HIP(hipMemcpyAsync(sh, sout.p, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
         ANV_HIP(hipStreamSynchronize(st));
         const double quad = sh[1];
