@@ -320,6 +320,43 @@ int anova_server_destroy(anova_server_t s);
 int anova_request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts* nfft,
                             const anova_ipm_opts* ipm, int64_t* bytes);
 
+/* ---- Hyperparameter grid -------------------------------------------------
+ * Parameter search (Section 6.3 selects sigma and C by a search over
+ * parameter combinations): many IPM solves that differ in the data (folds),
+ * the kernel widths and C. One problem is one plan (a fold's training points
+ * and one set of widths) with its labels and a list of C values. The low-rank
+ * preconditioner depends on the kernel matrix only, so the solves of a
+ * problem share one factor (built by the first of them). Up to max_active
+ * solves run at once, each on its own stream and host thread; their matvecs
+ * are collected and run together: the vectors of one plan in one 16-wide
+ * batched pass when the plan is mixed precision with cutoff_m = 4 (any
+ * number of them, one included, so each solve's arithmetic does not depend
+ * on the other solves), other plans in shared one-vector launches. */
+typedef struct {
+    anova_plan_t plan;       /* each plan in at most one problem                     */
+    const double* labels;    /* device, N of the plan, {-1, +1}                      */
+    int32_t n_c;             /* number of C values, >= 1                             */
+    int32_t reserved;
+    const double* C;         /* host, n_c values > 0                                 */
+    double* alpha;           /* device out, N x n_c column-major: column j for C[j]  */
+    double* lambda;          /* host out, n_c                                        */
+    anova_ipm_stats* stats;  /* host out, n_c; stats[j].status is that solve's
+                                status (ANOVA_OK, ANOVA_NOT_CONVERGED or an error)  */
+} anova_grid_problem;
+
+/* Run every (problem, C) solve of the grid and return when all have
+ * finished. Runs on the current HIP device, on streams of its own: the inputs
+ * must be ready on the device before the call and the outputs are ready when
+ * it returns. The plans must not be used by other calls meanwhile. opts as
+ * for svm_ipm_solve (host or NULL). max_active in [1, 256]; gather_us: the
+ * longest wait for more matvecs before a shared launch (microseconds, >= 0).
+ * launches / matvecs (host, may be NULL): shared launches made and matvecs
+ * served. Returns ANOVA_INVALID_ARG (NULL fields, n_c < 1, C <= 0, a plan in
+ * two problems, bad options) before any solve starts, ANOVA_HIP_ERROR, or
+ * ANOVA_OK with the per-solve outcome in stats[j].status. */
+int anova_grid_solve(const anova_grid_problem* problems, int32_t n_problems, const anova_ipm_opts* opts,
+                     int32_t max_active, double gather_us, int64_t* launches, int64_t* matvecs);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* anova_last_error(void);
 

@@ -25,7 +25,7 @@ EXPORTED = [
     "anova_plan_info", "anova_ipm_opts_default", "svm_ipm_solve", "anova_pivoted_cholesky",
     "anova_nystrom", "anova_last_error", "anova_profile_begin", "anova_profile_end",
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
-    "anova_server_counters", "anova_server_destroy", "anova_request_footprint",
+    "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -80,6 +80,12 @@ class IpmStats(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class GridProblem(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("n_c", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("C", ctypes.c_void_p), ("alpha", ctypes.c_void_p),
+                ("lambda_", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
 class ServerResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("footprint", ctypes.c_int64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
@@ -122,6 +128,8 @@ def load_library(path: str = LIB_PATH):
         "anova_server_destroy": ([P], ctypes.c_int),
         "anova_request_footprint": ([i64, i32, i32, ctypes.POINTER(Opts), ctypes.POINTER(IpmOpts),
                                      ctypes.POINTER(i64)], ctypes.c_int),
+        "anova_grid_solve": ([ctypes.POINTER(GridProblem), i32, ctypes.POINTER(IpmOpts), i32, dbl,
+                              ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -294,6 +302,42 @@ def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: Ipm
     _check(lib.anova_request_footprint(int(N), int(d), int(P), ctypes.byref(nfft) if nfft else None,
                                        ctypes.byref(ipm) if ipm else None, ctypes.byref(b)))
     return b.value
+
+
+def grid_solve(problems, opts: IpmOpts | None = None, max_active: int = 64, gather_us: float = 200.0,
+               **kw):
+    """Hyperparameter grid of IPM solves (anova_grid_solve).
+
+    problems: list of (plan, labels, Cs) with labels a device tensor of the
+    plan's N and Cs a sequence of C values; each plan in one problem only.
+    Returns (results, launches, matvecs) with results[i] = (alpha (N x nC
+    device tensor, column j for Cs[j]), lambdas (nC,), stats (list of dicts,
+    'status' per solve)). Runs on the current device; waits for torch's
+    current stream before it starts."""
+    import torch
+    lib = load_library()
+    if opts is None:
+        opts = default_ipm_opts(**kw)
+    arr = (GridProblem * len(problems))()
+    keep = []
+    for i, (plan, labels, Cs) in enumerate(problems):
+        labels = _dev_f64(labels, "labels").contiguous()
+        c = np.ascontiguousarray(np.asarray(Cs, dtype=np.float64).reshape(-1))
+        nc = int(c.shape[0])
+        alpha = torch.empty((nc, plan.N), dtype=torch.float64, device=labels.device)
+        lam = np.zeros(nc, dtype=np.float64)
+        st = (IpmStats * max(nc, 1))()
+        keep.append((labels, c, alpha, lam, st))
+        arr[i] = GridProblem(plan.handle.value, labels.data_ptr(), nc, 0, c.ctypes.data, alpha.data_ptr(),
+                             lam.ctypes.data, ctypes.addressof(st))
+    torch.cuda.current_stream().synchronize()
+    la, mv = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib.anova_grid_solve(arr, len(problems), ctypes.byref(opts), int(max_active), float(gather_us),
+                                ctypes.byref(la), ctypes.byref(mv)))
+    out = []
+    for (labels, c, alpha, lam, st) in keep:
+        out.append((alpha.t(), lam.copy(), [st[j].as_dict() for j in range(len(c))]))
+    return out, la.value, mv.value
 
 
 class Server:

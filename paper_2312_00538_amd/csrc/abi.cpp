@@ -3,6 +3,7 @@
 #include <chrono>
 #include <cstring>
 #include <memory>
+#include <vector>
 
 #include "plan.hpp"
 #include "server.hpp"
@@ -264,6 +265,29 @@ int anova_request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts* n
         anova_ipm_opts_default(&io);
         if (ipm) io = *ipm;
         *bytes = anv::request_footprint(N, d, P, o, io);
+        return ANOVA_OK;
+    });
+}
+
+int anova_grid_solve(const anova_grid_problem* problems, int32_t n_problems, const anova_ipm_opts* opts,
+                     int32_t max_active, double gather_us, int64_t* launches, int64_t* matvecs) {
+    return guarded([&] {
+        ANV_CHECK(problems && n_problems >= 1, "no problems");
+        anova_ipm_opts o;
+        anova_ipm_opts_default(&o);
+        if (opts) {
+            ANV_CHECK(opts->version == ANOVA_IPM_OPTS_VERSION, "anova_ipm_opts.version mismatch");
+            o = *opts;
+        }
+        std::vector<anv::GridProblem> g(static_cast<size_t>(n_problems));
+        for (int32_t i = 0; i < n_problems; ++i) {
+            const anova_grid_problem& q = problems[i];
+            ANV_CHECK(q.plan && q.plan->p, "NULL plan");
+            g[i] = anv::GridProblem{q.plan->p.get(), q.labels, q.n_c, q.C, q.alpha, q.lambda, q.stats};
+        }
+        int device = 0;
+        ANV_HIP(hipGetDevice(&device));
+        anv::grid_solve(g.data(), n_problems, o, max_active, gather_us, device, launches, matvecs);
         return ANOVA_OK;
     });
 }

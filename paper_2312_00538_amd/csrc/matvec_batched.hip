@@ -31,19 +31,26 @@ __device__ inline void dma16(const void* src, void* lds) {
                                      (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-// xt[i][r] = x[i + r * ldx] in FP32 (zero for r >= R); 64 points per block,
-// transposed through LDS so that both the reads and the writes are coalesced.
-// Also resets the spread and gather work queues of the pass.
-__global__ __launch_bounds__(256) void k_transpose_in(const double* __restrict__ x, int R, int64_t ldx, int64_t N,
-                                                      float* __restrict__ xt, int32_t* __restrict__ queues) {
+// Column pointers of one pass: right-hand side r is read from x[r] and its
+// result written to y[r] (N doubles each); columns r >= R are absent.
+struct ColPtrs {
+    const double* x[RB];
+    double* y[RB];
+};
+
+// xt[i][r] = x_r[i] in FP32 (zero for r >= R); 64 points per block, transposed
+// through LDS so that both the reads and the writes are coalesced. Also resets
+// the spread and gather work queues of the pass.
+__global__ __launch_bounds__(256) void k_transpose_in(const ColPtrs cols, int R, int64_t N, float* __restrict__ xt,
+                                                      int32_t* __restrict__ queues) {
     __shared__ float s[RB][65];
     if (blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;  // work queues of this pass
     const int64_t i0 = int64_t(blockIdx.x) * 64;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int e = j * 256 + threadIdx.x;
-        const int r = e / 64, i = e % 64;
-        s[r][i] = (r < R && i0 + i < N) ? float(x[i0 + i + int64_t(r) * ldx]) : 0.0f;
+        const int r = e / 64, i = e % 64;  // r is uniform across a wavefront
+        s[r][i] = (r < R && i0 + i < N) ? float(cols.x[r][i0 + i]) : 0.0f;
     }
     __syncthreads();
 #pragma unroll
@@ -661,11 +668,11 @@ __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wi
     }
 }
 
-// y[i + r ldy] = sum_l eta_l f_l(i, r), windows in order, FP64; 64 points per
-// block, transposed through LDS for column-major stores
+// y_r[i] = sum_l eta_l f_l(i, r), windows in order, FP64; 64 points per
+// block, transposed through LDS for coalesced stores
 __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ fs, const int32_t* __restrict__ pos,
                                                       const WinDev* __restrict__ wins, int32_t P, int64_t N, int R,
-                                                      double* __restrict__ y, int64_t ldy) {
+                                                      const ColPtrs cols) {
     __shared__ double s[RB][65];
     const int64_t i0 = int64_t(blockIdx.x) * 64;
 #pragma unroll
@@ -682,8 +689,8 @@ __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int e = j * 256 + threadIdx.x;
-        const int r = e / 64, i = e % 64;
-        if (r < R && i0 + i < N) y[i0 + i + int64_t(r) * ldy] = s[r][i];
+        const int r = e / 64, i = e % 64;  // r is uniform across a wavefront
+        if (r < R && i0 + i < N) cols.y[r][i0 + i] = s[r][i];
     }
 }
 
@@ -763,61 +770,115 @@ void ensure_batched_buffers(Plan& pl) {
     pl.b_ready = true;
 }
 
+namespace {
+
+// one pass of up to RB right-hand sides
+void batched_pass(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
+    const int64_t N = pl.N;
+    const bool prof = pl.profiling;
+    if (prof) pl.record_stage_event(st);
+    hipLaunchKernelGGL(k_transpose_in, dim3(nblk(N, 64)), dim3(256), 0, st, cols, rn, N, pl.xtb.p, pl.b_queue.p);
+    if (prof) pl.record_stage_event(st);
+    if (pl.nwave[3])
+        hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                           pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p,
+                           pl.wts32.p, pl.perm.p, pl.xtb.p, N, pl.slabb.p, pl.tgtb.p);
+    if (pl.nb_items2)
+        hipLaunchKernelGGL((k_spread_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
+                           pl.slabb.p);
+    if (pl.nb_items1)
+        hipLaunchKernelGGL((k_spread_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p,
+                           pl.xtb.p, N, pl.slabb.p);
+    if (prof) pl.record_stage_event(st);
+    if (pl.nflist)
+        hipLaunchKernelGGL(k_fold_cols_b, dim3(unsigned(pl.nflist)), dim3(256), 0, st, pl.wins_d.p, pl.P, pl.nflist,
+                           pl.flist.p, pl.fold.p, pl.sbase.p, pl.slabb.p, pl.tgtb.p);
+    if (prof) pl.record_stage_event(st);
+    const int RH = RB / pl.b_rsplit;
+    const size_t lds_yz =
+        size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) * sizeof(float);
+    hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(unsigned(pl.emax[0]), unsigned(pl.P), unsigned(pl.b_rsplit)),
+                       dim3(1024), lds_yz, st, pl.wins_d.p, pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH);
+    const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pl.emax[0]) * sizeof(float);
+    hipLaunchKernelGGL(k_conv_x_b, dim3(unsigned(pl.emax[1]), unsigned(pl.P), unsigned(pl.b_rsplit)), dim3(1024), lds_x,
+                       st, pl.wins_d.p, pl.tmat.p, pl.g1b.p, pl.hb.p, RH);
+    if (prof) pl.record_stage_event(st);
+    if (pl.nwave[3])
+        hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                           pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
+                           pl.wts32.p, pl.hb.p, N, pl.fsb.p);
+    if (pl.nb_items2)
+        hipLaunchKernelGGL((k_gather_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p, pl.hb.p, N,
+                           pl.fsb.p);
+    if (pl.nb_items1)
+        hipLaunchKernelGGL((k_gather_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p,
+                           pl.hb.p, N, pl.fsb.p);
+    if (prof) pl.record_stage_event(st);
+    hipLaunchKernelGGL(k_window_sum_b, dim3(nblk(N, 64)), dim3(256), 0, st, pl.fsb.p, pl.pos.p, pl.wins_d.p, pl.P, N,
+                       rn, cols);
+    if (prof) pl.record_stage_event(st);
+    ANV_HIP(hipGetLastError());
+}
+
+}  // namespace
+
 void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
     ensure_batched_buffers(pl);
-    const int64_t N = pl.N;
     for (int r0 = 0; r0 < R; r0 += RB) {
         const int rn = std::min(RB, R - r0);
-        const double* xr = x + int64_t(r0) * ldx;
-        double* yr = y + int64_t(r0) * ldy;
-        const bool prof = pl.profiling;
-        if (prof) pl.record_stage_event(st);
-        hipLaunchKernelGGL(k_transpose_in, dim3(nblk(N, 64)), dim3(256), 0, st, xr, rn, ldx, N, pl.xtb.p,
-                           pl.b_queue.p);
-        if (prof) pl.record_stage_event(st);
-        if (pl.nwave[3])
-            hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p, pl.wts32.p, pl.perm.p, pl.xtb.p,
-                               N, pl.slabb.p, pl.tgtb.p);
-        if (pl.nb_items2)
-            hipLaunchKernelGGL((k_spread_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
-                               pl.slabb.p);
-        if (pl.nb_items1)
-            hipLaunchKernelGGL((k_spread_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
-                               pl.slabb.p);
-        if (prof) pl.record_stage_event(st);
-        if (pl.nflist)
-            hipLaunchKernelGGL(k_fold_cols_b, dim3(unsigned(pl.nflist)), dim3(256), 0, st, pl.wins_d.p, pl.P, pl.nflist,
-                               pl.flist.p, pl.fold.p, pl.sbase.p, pl.slabb.p, pl.tgtb.p);
-        if (prof) pl.record_stage_event(st);
-        const int RH = RB / pl.b_rsplit;
-        const size_t lds_yz =
-            size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) * sizeof(float);
-        hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(unsigned(pl.emax[0]), unsigned(pl.P), unsigned(pl.b_rsplit)),
-                           dim3(1024), lds_yz, st, pl.wins_d.p, pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH);
-        const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pl.emax[0]) * sizeof(float);
-        hipLaunchKernelGGL(k_conv_x_b, dim3(unsigned(pl.emax[1]), unsigned(pl.P), unsigned(pl.b_rsplit)), dim3(1024),
-                           lds_x, st, pl.wins_d.p, pl.tmat.p, pl.g1b.p, pl.hb.p, RH);
-        if (prof) pl.record_stage_event(st);
-        if (pl.nwave[3])
-            hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                               pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.wts32.p, pl.hb.p, N, pl.fsb.p);
-        if (pl.nb_items2)
-            hipLaunchKernelGGL((k_gather_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p, pl.nb_items2, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p, pl.hb.p, N,
-                               pl.fsb.p);
-        if (pl.nb_items1)
-            hipLaunchKernelGGL((k_gather_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
-                               pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p,
-                               pl.hb.p, N, pl.fsb.p);
-        if (prof) pl.record_stage_event(st);
-        hipLaunchKernelGGL(k_window_sum_b, dim3(nblk(N, 64)), dim3(256), 0, st, pl.fsb.p, pl.pos.p, pl.wins_d.p, pl.P,
-                           N, rn, yr, ldy);
-        if (prof) pl.record_stage_event(st);
-        ANV_HIP(hipGetLastError());
+        ColPtrs cols{};
+        for (int r = 0; r < rn; ++r) {
+            cols.x[r] = x + int64_t(r0 + r) * ldx;
+            cols.y[r] = y + int64_t(r0 + r) * ldy;
+        }
+        batched_pass(pl, cols, rn, st);
     }
+}
+
+void enqueue_matvec_batched_cols(Plan& pl, const double* const* x, double* const* y, int R, hipStream_t st) {
+    ensure_batched_buffers(pl);
+    for (int r0 = 0; r0 < R; r0 += RB) {
+        const int rn = std::min(RB, R - r0);
+        ColPtrs cols{};
+        for (int r = 0; r < rn; ++r) {
+            cols.x[r] = x[r0 + r];
+            cols.y[r] = y[r0 + r];
+        }
+        batched_pass(pl, cols, rn, st);
+    }
+}
+
+void enqueue_matvec_grouped(Plan* const* plans, const double* const* x, double* const* y, int n, hipStream_t st) {
+    // same-plan vectors of batched plans: one batched pass per 16 of them;
+    // the rest: shared one-vector launches
+    std::vector<int> taken(n, 0);
+    std::vector<Plan*> rp;
+    std::vector<const double*> rx;
+    std::vector<double*> ry;
+    for (int i = 0; i < n; ++i) {
+        if (taken[i]) continue;
+        if (!batched_supported(*plans[i])) {
+            rp.push_back(plans[i]);
+            rx.push_back(x[i]);
+            ry.push_back(y[i]);
+            taken[i] = 1;
+            continue;
+        }
+        std::vector<const double*> gx;
+        std::vector<double*> gy;
+        for (int k = i; k < n; ++k)
+            if (!taken[k] && plans[k] == plans[i]) {
+                gx.push_back(x[k]);
+                gy.push_back(y[k]);
+                taken[k] = 1;
+            }
+        enqueue_matvec_batched_cols(*plans[i], gx.data(), gy.data(), int(gx.size()), st);
+    }
+    if (!rp.empty()) enqueue_matvec_multi(rp.data(), rx.data(), ry.data(), int(rp.size()), st);
 }
 
 }  // namespace anv

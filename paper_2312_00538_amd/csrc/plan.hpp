@@ -88,10 +88,6 @@ struct Plan {
     void record_stage_event(hipStream_t st);
 
     double max_kerr = 0.0;
-    // When set, the solver's one-vector matvecs go through this hook (a request
-    // server uses it to put the matvecs of several resident solves in shared
-    // launches) instead of enqueue_matvec.
-    std::function<void(Plan&, const double*, double*, hipStream_t)> mv_hook;
     ~Plan();
     int64_t device_bytes() const;
 };
@@ -164,6 +160,14 @@ void release_batched_buffers(Plan& pl);
 // stages share launches (grouped by cutoff and precision, up to kMaxJobs plans).
 void enqueue_matvec_multi(Plan* const* plans, const double* const* x, double* const* y, int n,
                           hipStream_t stream);
+// batched matvec of R vectors given by column pointers (N doubles each)
+void enqueue_matvec_batched_cols(Plan& pl, const double* const* x, double* const* y, int R, hipStream_t stream);
+// y_i = K_i x_i for n (plan, vector) pairs in which a plan may repeat: the
+// vectors of a plan that the batched path supports go through it together
+// (any number, also one, so that a vector's result does not depend on the
+// others in the call); the rest as in enqueue_matvec_multi.
+void enqueue_matvec_grouped(Plan* const* plans, const double* const* x, double* const* y, int n,
+                            hipStream_t stream);
 
 void profile_begin(Plan& pl);
 int profile_end(Plan& pl, double* stage_ms, int nstage);  // returns passes measured

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -61,7 +62,10 @@ struct Result {
 // Collects one-vector matvecs from resident solves and runs them in shared launches.
 class Combiner {
   public:
-    Combiner(int device, double gather_us) : device_(device), gather_us_(gather_us) {
+    // grouped: matvecs of one plan from several solves go out as one batched
+    // call (enqueue_matvec_grouped); otherwise one vector per plan and launch
+    Combiner(int device, double gather_us, bool grouped = false)
+        : device_(device), gather_us_(gather_us), grouped_(grouped) {
         ANV_HIP(hipSetDevice(device_));
         ANV_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
         thread_ = std::thread([this] { loop(); });
@@ -141,7 +145,10 @@ class Combiner {
                     xs.push_back(it->x);
                     ys.push_back(it->y);
                 }
-                enqueue_matvec_multi(plans.data(), xs.data(), ys.data(), int(plans.size()), stream_);
+                if (grouped_)
+                    enqueue_matvec_grouped(plans.data(), xs.data(), ys.data(), int(plans.size()), stream_);
+                else
+                    enqueue_matvec_multi(plans.data(), xs.data(), ys.data(), int(plans.size()), stream_);
                 for (Item* it : batch) ANV_HIP(hipEventRecord(it->done, stream_));
                 launches_ += 1;
                 matvecs_ += int64_t(batch.size());
@@ -158,6 +165,7 @@ class Combiner {
     }
     int device_;
     double gather_us_;
+    bool grouped_;
     hipStream_t stream_ = nullptr;
     std::mutex m_;
     std::condition_variable cv_;
@@ -232,11 +240,11 @@ struct Server::Impl {
                                    hipMemcpyHostToDevice, stream));
             std::unique_ptr<Plan> pl(create_plan(Xd.p, r->N, r->d, r->d, r->windows.data(), r->P, r->sigma.data(),
                                                  nullptr, &r->nfft, stream));
-            if (comb)
-                pl->mv_hook = [this, ev_ready, ev_done, &joined](Plan& p, const double* x, double* y, hipStream_t s) {
-                    comb->matvec(p, x, y, s, ev_ready, ev_done, joined);
-                };
-            status = ipm_solve(*pl, yd.p, r->C, r->ipm, ad.p, &lambda, &st, stream);
+            Plan* plp = pl.get();
+            MatvecHook hook = [this, plp, ev_ready, ev_done, &joined](const double* x, double* y, hipStream_t s) {
+                comb->matvec(*plp, x, y, s, ev_ready, ev_done, joined);
+            };
+            status = ipm_solve(*pl, yd.p, r->C, r->ipm, ad.p, &lambda, &st, stream, nullptr, comb ? &hook : nullptr);
             if (comb) comb->solver_leave(joined);
             ANV_HIP(hipMemcpyAsync(alpha_h.data(), ad.p, alpha_h.size() * sizeof(double), hipMemcpyDeviceToHost,
                                    stream));
@@ -374,6 +382,104 @@ int Server::wait(int64_t ticket, double* alpha, anova_result* res) {
 void Server::counters(int64_t* launches, int64_t* matvecs) const {
     *launches = impl_->comb ? impl_->comb->launches() : 0;
     *matvecs = impl_->comb ? impl_->comb->matvecs() : 0;
+}
+
+void grid_solve(const GridProblem* probs, int nprob, const anova_ipm_opts& o, int max_active, double gather_us,
+                int device, int64_t* launches, int64_t* matvecs) {
+    ANV_CHECK(probs && nprob >= 1, "no problems");
+    ANV_CHECK(max_active >= 1 && max_active <= 256, "max_active must be in [1, 256]");
+    ANV_CHECK(std::isfinite(gather_us) && gather_us >= 0.0, "gather_us must be >= 0");
+    struct Task {
+        int p, c;
+    };
+    std::vector<Task> tasks;
+    for (int p = 0; p < nprob; ++p) {
+        const GridProblem& g = probs[p];
+        ANV_CHECK(g.plan && g.labels && g.C && g.alpha && g.lambda && g.stats, "NULL problem field");
+        ANV_CHECK(g.nC >= 1, "every problem needs at least one C");
+        for (int c = 0; c < g.nC; ++c) ANV_CHECK(std::isfinite(g.C[c]) && g.C[c] > 0.0, "C must be > 0");
+        for (int q = 0; q < p; ++q) ANV_CHECK(probs[q].plan != g.plan, "a plan may appear in one problem only");
+        for (int c = 0; c < g.nC; ++c) tasks.push_back({p, c});
+    }
+    struct ProbState {
+        std::once_flag once;
+        LowRankFactor f;
+        int status = ANOVA_OK;
+        std::string err;
+        std::atomic<int> left{0};
+    };
+    std::vector<std::unique_ptr<ProbState>> ps;
+    for (int p = 0; p < nprob; ++p) {
+        ps.emplace_back(new ProbState);
+        ps.back()->left = probs[p].nC;
+    }
+    ANV_HIP(hipSetDevice(device));
+    Combiner comb(device, gather_us, true);
+    std::atomic<size_t> next{0};
+    auto worker = [&] {
+        hipStream_t stream = nullptr;
+        hipEvent_t ready = nullptr, done = nullptr;
+        bool ok = hipSetDevice(device) == hipSuccess &&
+                  hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+        for (;;) {
+            const size_t t = next++;
+            if (t >= tasks.size()) break;
+            const GridProblem& g = probs[tasks[t].p];
+            ProbState& P = *ps[tasks[t].p];
+            const int c = tasks[t].c;
+            anova_ipm_stats st{};
+            double lam = 0.0;
+            int status = ANOVA_HIP_ERROR;
+            if (ok) {
+                try {
+                    // the first solve of a problem builds the factor its C values share
+                    std::call_once(P.once, [&] {
+                        try {
+                            build_low_rank(*g.plan, o, P.f, stream);
+                        } catch (const Error& e) {
+                            P.status = e.code;
+                            P.err = e.what();
+                        }
+                    });
+                    if (P.status != ANOVA_OK) throw Error(P.status, P.err);
+                    bool joined = false;
+                    MatvecHook hook = [&](const double* x, double* y, hipStream_t s) {
+                        comb.matvec(*g.plan, x, y, s, ready, done, joined);
+                    };
+                    try {
+                        status = ipm_solve(*g.plan, g.labels, g.C[c], o, g.alpha + int64_t(c) * g.plan->N, &lam, &st,
+                                           stream, &P.f, &hook);
+                    } catch (...) {
+                        comb.solver_leave(joined);
+                        throw;
+                    }
+                    comb.solver_leave(joined);
+                } catch (const Error& e) {
+                    status = e.code;
+                } catch (const std::exception&) {
+                    status = ANOVA_HIP_ERROR;
+                }
+            }
+            st.status = status;
+            g.lambda[c] = lam;
+            g.stats[c] = st;
+            if (--P.left == 0) P.f.Z.release();  // the problem's last solve has finished
+        }
+        if (stream) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipStreamDestroy(stream);
+        }
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
+    };
+    std::vector<std::thread> pool;
+    const int nthreads = int(std::min<size_t>(size_t(max_active), tasks.size()));
+    for (int i = 0; i < nthreads; ++i) pool.emplace_back(worker);
+    for (auto& th : pool) th.join();
+    if (launches) *launches = comb.launches();
+    if (matvecs) *matvecs = comb.matvecs();
 }
 
 }  // namespace anv

@@ -732,7 +732,7 @@ struct Reducer {
 struct Workspace {
     int64_t N = 0;
     int k = 0;
-    DevBuf<double> Z;                     // N x k column-major low-rank factor Z^T
+    const double* Z = nullptr;            // N x k column-major low-rank factor Z^T
     DevBuf<double> M, Mpart, w, t;        // capacitance and its factor
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
@@ -744,9 +744,9 @@ struct Workspace {
 };
 
 // kernel matvec of one vector (device pointers, length N)
-void kmv(Plan& pl, const double* x, double* y, hipStream_t st) {
-    if (pl.mv_hook)
-        pl.mv_hook(pl, x, y, st);
+void kmv(Plan& pl, const MatvecHook* hook, const double* x, double* y, hipStream_t st) {
+    if (hook)
+        (*hook)(x, y, st);
     else
         enqueue_matvec(pl, x, 1, pl.N, y, pl.N, st);
 }
@@ -757,13 +757,13 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
     const int64_t N = pl.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
-        hipLaunchKernelGGL(k_gemv_t_seg, dim3(ws.k, ws.nseg), dim3(kT), 0, st, ws.Z.p, N, ws.tmp.p, ws.seg,
+        hipLaunchKernelGGL(k_gemv_t_seg, dim3(ws.k, ws.nseg), dim3(kT), 0, st, ws.Z, N, ws.tmp.p, ws.seg,
                            ws.wpart.p);
         hipLaunchKernelGGL(k_gemv_t_fold, dim3(nblk(ws.k)), dim3(kT), 0, st, ws.wpart.p, ws.nseg, ws.k, ws.w.p);
         hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.w.p,
                            ws.t.p);
     }
-    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z.p, N, ws.k, ws.t.p,
+    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p,
                        1.0 / s, has_last ? 1 : 0, out);
 }
 
@@ -771,7 +771,7 @@ void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t 
     if (ws.k == 0) return;
     const int k = ws.k;
     const int ns = (k + kST - 1) / kST;
-    hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st, ws.Z.p,
+    hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st, ws.Z,
                        pl.N, k, th, ws.chunk, ws.Mpart.p);
     hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
@@ -979,8 +979,11 @@ void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st
         dmax = std::max(dmax, Cm[size_t(i) * k + i]);
     }
     ANV_CHECK(std::isfinite(dmax), "non-finite Q^T K Q");
-    const double tau = 1e-12 * dmax;
-    // LDL^T without pivoting; D entries below tau are raised to tau (Section 4)
+    // LDL^T without pivoting; D entries below tau are raised to tau (Section 4).
+    // tau sits at the operator's relative accuracy: below it, directions of
+    // Q^T K Q are rounding noise of the matvec (FP32 grids: about 1e-7), and
+    // raising them to a much smaller value would amplify that noise in Z.
+    const double tau = (pl.precision == ANOVA_PREC_FP64 ? 1e-12 : 1e-6) * dmax;
     std::vector<double> L(size_t(k) * k, 0.0), D(k);
     for (int j = 0; j < k; ++j) {
         double dj = Cm[size_t(j) * k + j];
@@ -1042,8 +1045,38 @@ void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, i
 }
 
 // ------------------------------------------------------------------ Algorithm 1
+void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStream_t st) {
+    using clk = std::chrono::steady_clock;
+    const int64_t N = pl.N;
+    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
+                  o.precond == ANOVA_PRECOND_NYSTROM,
+              "unknown preconditioner");
+    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
+              "rank must be in [1, min(N, 1024)]");
+    const auto t0 = clk::now();
+    f.precond = o.precond;
+    f.rank = 0;
+    if (o.precond == ANOVA_PRECOND_PCHOL) {
+        f.Z.alloc(size_t(N) * o.rank);
+        std::vector<int64_t> piv(o.rank);
+        f.rank = pchol_into(pl, o.rank, o.err_tol, f.Z.p, N, piv.data(), st);
+    } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
+        f.rank = o.rank;
+        f.Z.alloc(size_t(N) * o.rank);
+        DevBuf<double> Gd, Y;
+        Gd.alloc(size_t(N) * o.rank);
+        Y.alloc(size_t(N) * o.rank);
+        hipLaunchKernelGGL(k_gaussian, dim3(nblk(N), unsigned(o.rank)), dim3(kT), 0, st, Gd.p, N, o.rank, o.seed);
+        enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
+        nystrom_core(pl, Y, o.rank, f.Z.p, st);
+    }
+    ANV_HIP(hipStreamSynchronize(st));
+    f.t_setup_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
 int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o, double* alpha,
-              double* lambda_out, anova_ipm_stats* stats, hipStream_t st) {
+              double* lambda_out, anova_ipm_stats* stats, hipStream_t st, const LowRankFactor* factor,
+              const MatvecHook* hook) {
     using clk = std::chrono::steady_clock;
     const auto t_start = clk::now();
     const int64_t N = pl.N;
@@ -1076,28 +1109,18 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
 
     Reducer red;
     Workspace ws;
-    std::vector<int64_t> piv;
-    int rank_used = 0;
-    const auto t_setup0 = clk::now();
-    if (o.precond == ANOVA_PRECOND_PCHOL) {
-        ws.Z.alloc(size_t(N) * o.rank);
-        piv.resize(o.rank);
-        rank_used = pchol_into(pl, o.rank, o.err_tol, ws.Z.p, N, piv.data(), st);
-        setup_factor_storage(ws, N, rank_used);
-    } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
-        rank_used = o.rank;
-        ws.Z.alloc(size_t(N) * o.rank);
-        DevBuf<double> Gd, Y;
-        Gd.alloc(size_t(N) * o.rank);
-        Y.alloc(size_t(N) * o.rank);
-        hipLaunchKernelGGL(k_gaussian, dim3(nblk(N), unsigned(o.rank)), dim3(kT), 0, st, Gd.p, N, o.rank, o.seed);
-        enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
-        nystrom_core(pl, Y, o.rank, ws.Z.p, st);
-        setup_factor_storage(ws, N, rank_used);
+    LowRankFactor own;
+    if (factor) {
+        ANV_CHECK(factor->precond == o.precond && (o.precond == ANOVA_PRECOND_NONE || factor->Z.n >= size_t(N) * factor->rank),
+                  "shared factor does not match the preconditioner options or the plan");
     } else {
-        setup_factor_storage(ws, N, 0);
+        build_low_rank(pl, o, own, st);
+        factor = &own;
     }
-    const double t_setup_ms = std::chrono::duration<double, std::milli>(clk::now() - t_setup0).count();
+    const int rank_used = factor->rank;
+    ws.Z = factor->Z.p;
+    setup_factor_storage(ws, N, o.precond == ANOVA_PRECOND_NONE ? 0 : rank_used);
+    const double t_setup_ms = factor->t_setup_ms;
 
     // state
     DevBuf<double> ya, kya, th, rhs, sol, xk, rprev, rcur, zcur, zold, pv, d1, d2, ytmp;
@@ -1126,7 +1149,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
 
     auto eval_stats = [&](double& xa, double& xl, double& D, double& Pr, double& G) {
         hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, N, ya.p);
-        kmv(pl, ya.p, kya.p, st);
+        kmv(pl, hook, ya.p, kya.p, st);
         ++matvecs;
         hipLaunchKernelGGL(k_ipm_stats, dim3(rb), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, spart.p);
         hipLaunchKernelGGL(k_fold_partials, dim3(5), dim3(64), 0, st, spart.p, int(rb), 5, sout.p);
@@ -1144,7 +1167,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         // automatic start: the mean complementarity implied by the reduced
         // gradient at the starting point, never below the value 1 of Algorithm 1
         hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, N, ya.p);
-        kmv(pl, ya.p, kya.p, st);
+        kmv(pl, hook, ya.p, kya.p, st);
         ++matvecs;
         hipLaunchKernelGGL(k_compl_scale, dim3(nblk(N)), dim3(kT), 0, st, labels, alpha, kya.p, N, C, ytmp.p);
         hipLaunchKernelGGL(k_fill, dim3(nblk(N)), dim3(kT), 0, st, th.p, N, 1.0);
@@ -1215,7 +1238,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
                 ++kit;
                 // p = A (z / beta) - (beta / beta_prev) r_prev
                 hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
-                kmv(pl, ws.tmp.p, ws.kyz.p, st);
+                kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
                 ++matvecs;
                 const double ytz = red.dot(labels, zc, N, st);
                 const double cprev = kit > 1 ? beta / beta_prev : 0.0;

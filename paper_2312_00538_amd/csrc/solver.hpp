@@ -1,11 +1,34 @@
 // Low-rank factors, preconditioned MINRES and the interior point method.
 #pragma once
+#include <functional>
+
 #include "plan.hpp"
 
 namespace anv {
 
+// y = K x of one vector on a stream; replaces the plan's own matvec inside a
+// solve (shared launches of several solves)
+using MatvecHook = std::function<void(const double* x, double* y, hipStream_t st)>;
+
+// Low-rank factor Z^T (N x rank, column-major) of the kernel matrix, which the
+// solves of one plan with different C share: it depends on K only.
+struct LowRankFactor {
+    int precond = ANOVA_PRECOND_NONE;
+    int rank = 0;             // columns used
+    DevBuf<double> Z;
+    double t_setup_ms = 0.0;
+};
+
+// Builds the preconditioner factor that o.precond, o.rank, o.err_tol and
+// o.seed ask for (nothing for ANOVA_PRECOND_NONE).
+void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStream_t st);
+
+// Algorithm 1. `factor` (may be NULL) is a factor built by build_low_rank with
+// the same preconditioner options; without it the solve builds its own.
+// `hook` (may be NULL) performs the kernel matvecs of the iteration.
 int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o, double* alpha,
-              double* lambda, anova_ipm_stats* stats, hipStream_t st);
+              double* lambda, anova_ipm_stats* stats, hipStream_t st, const LowRankFactor* factor = nullptr,
+              const MatvecHook* hook = nullptr);
 
 // returns the rank used
 int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv,

@@ -94,3 +94,15 @@ def test_server_options_and_footprint(L):
     assert L.anova_server_destroy(None) == lib.OK
     t = ctypes.c_int64(0)
     assert L.anova_server_submit(None, None, ctypes.byref(t)) == lib.INVALID_ARG
+
+
+def test_grid_solve_rejects_bad_arguments(L):
+    # checked before any device work: no problems, a NULL plan
+    assert L.anova_grid_solve(None, 1, None, 8, 200.0, None, None) == lib.INVALID_ARG
+    probs = (lib.GridProblem * 1)()
+    assert L.anova_grid_solve(probs, 0, None, 8, 200.0, None, None) == lib.INVALID_ARG
+    assert L.anova_grid_solve(probs, 1, None, 8, 200.0, None, None) == lib.INVALID_ARG
+    assert b"NULL plan" in L.anova_last_error()
+    o = lib.default_ipm_opts()
+    o.version = 99
+    assert L.anova_grid_solve(probs, 1, ctypes.byref(o), 8, 200.0, None, None) == lib.INVALID_ARG

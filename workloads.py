@@ -125,3 +125,36 @@ def serving_stream(seed: int, n_requests: int, rate: float = 2.0,
         C = float(math.exp(rng.uniform(math.log(C_range[0]), math.log(C_range[1]))))
         out.append(dict(id=i, arrival=t, N=N, d=d, sigma=sigma, C=C, data_seed=int(rng.integers(0, 2**31 - 1))))
     return out
+
+
+def cv_grid(seed: int = 0, N: int = 50_000, d: int = 15, folds: int = 5,
+            n_sigma: int = 8, sigma_range=(0.25, 4.0), n_C: int = 8, C_range=(0.1, 1000.0)) -> dict:
+    """Hyperparameter grid over cross-validation folds (a stand-in for the
+    paper's parameter search, Section 6.3). Data as gaussian_mixture(seed, N, d)
+    (shift 0.5, no noise). Folds: a permutation of the N points (drawn after the
+    data, from rng(seed + 1)) cut into `folds` equal holdout blocks; the
+    training part of each fold is class balanced by keeping a random subset
+    (without replacement, from the same rng) of the majority class of the size
+    of the minority class, so training sizes are uneven and at most
+    N (folds - 1) / folds. sigma: n_sigma log-spaced values, C: n_C log-spaced
+    values. Returns dict(problem, folds=[(train_idx, holdout_idx)], sigmas, Cs)."""
+    p = gaussian_mixture(seed, N=N, d=d, R=0)
+    rng = np.random.default_rng(seed + 1)
+    perm = rng.permutation(N)
+    size = N // folds
+    out = []
+    for f in range(folds):
+        hold = np.sort(perm[f * size:(f + 1) * size])
+        train = np.sort(np.concatenate([perm[:f * size], perm[(f + 1) * size:]]))
+        pos = train[p.labels[train] > 0]
+        neg = train[p.labels[train] < 0]
+        m = min(len(pos), len(neg))
+        if len(pos) > m:
+            pos = np.sort(rng.choice(pos, m, replace=False))
+        if len(neg) > m:
+            neg = np.sort(rng.choice(neg, m, replace=False))
+        out.append((np.sort(np.concatenate([pos, neg])), hold))
+    sigmas = np.geomspace(sigma_range[0], sigma_range[1], n_sigma)
+    Cs = np.geomspace(C_range[0], C_range[1], n_C)
+    p.meta["workload"] = "cv-grid"
+    return dict(problem=p, folds=out, sigmas=sigmas, Cs=Cs)
