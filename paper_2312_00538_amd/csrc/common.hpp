@@ -32,6 +32,19 @@ struct Error : std::runtime_error {
 
 void set_last_error(const std::string& m);
 
+// Host waits of the solver. By default a wait spins (lowest latency, right for
+// one solve at a time); a thread that runs one of many concurrent solves turns
+// on blocking waits (BlockingWaits), which sleep until the GPU signals, so
+// that dozens of waiting threads leave the host cores to the threads that
+// launch work.
+extern thread_local bool t_blocking_waits;
+void host_wait(hipStream_t st);
+struct BlockingWaits {
+    bool prev;
+    BlockingWaits() : prev(t_blocking_waits) { t_blocking_waits = true; }
+    ~BlockingWaits() { t_blocking_waits = prev; }
+};
+
 // Device allocation owned by a plan or a solver; freed in the destructor.
 template <class T>
 struct DevBuf {

@@ -28,6 +28,34 @@
 
 namespace anv {
 
+thread_local bool t_blocking_waits = false;
+
+void host_wait(hipStream_t st) {
+    if (!t_blocking_waits) {
+        ANV_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    // one blocking-sync event per thread and device, destroyed when the thread ends
+    struct Ev {
+        hipEvent_t e = nullptr;
+        int dev = -1;
+        ~Ev() {
+            if (e) (void)hipEventDestroy(e);
+        }
+    };
+    thread_local Ev ev;
+    int dev = 0;
+    ANV_HIP(hipGetDevice(&dev));
+    if (!ev.e || ev.dev != dev) {
+        if (ev.e) (void)hipEventDestroy(ev.e);
+        ev.e = nullptr;
+        ANV_HIP(hipEventCreateWithFlags(&ev.e, hipEventBlockingSync | hipEventDisableTiming));
+        ev.dev = dev;
+    }
+    ANV_HIP(hipEventRecord(ev.e, st));
+    ANV_HIP(hipEventSynchronize(ev.e));
+}
+
 namespace {
 
 using clk = std::chrono::steady_clock;
@@ -217,6 +245,7 @@ struct Server::Impl {
     }
 
     void run_request(std::unique_ptr<Request> r) {
+        BlockingWaits blocking;
         Result out;
         std::vector<double> alpha_h(size_t(r->N), 0.0);
         anova_ipm_stats st{};
@@ -417,6 +446,7 @@ void grid_solve(const GridProblem* probs, int nprob, const anova_ipm_opts& o, in
     Combiner comb(device, gather_us, true);
     std::atomic<size_t> next{0};
     auto worker = [&] {
+        BlockingWaits blocking;
         hipStream_t stream = nullptr;
         hipEvent_t ready = nullptr, done = nullptr;
         bool ok = hipSetDevice(device) == hipSuccess &&

@@ -279,25 +279,29 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const double* __restrict__ Z,
             }
 }
 
-// M[a][b] = diag [a == b] + sum_c part[c][max(a,b)][min(a,b)] (chunks in order)
+// M[a][b] = M[b][a] = diag [a == b] + sum_c part[c][a][b] for a >= b (chunks in
+// order); threads run along rows of the lower triangle, so the partial sums are
+// read contiguously
 __global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, double diag,
                             double* __restrict__ M) {
     const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
     if (e >= int64_t(k) * k) return;
     const int a = int(e / k), b = int(e % k);
-    const int64_t src = int64_t(a >= b ? a : b) * k + (a >= b ? b : a);
+    if (b > a) return;
     double s = (a == b) ? diag : 0.0;
-    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * k * k + src];
+    for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * k * k + e];
     M[e] = s;
+    M[int64_t(b) * k + a] = s;
 }
 
 // row chunks of k_syrk_mfma: enough blocks to fill the GPU, partials within 256 MB,
-// chunks a whole number of panels
+// at least 256 rows per chunk (the fold reads nchunk k x k partials), chunks a
+// whole number of panels
 void syrk_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
     const int ns = (k + kST - 1) / kST, pairs = ns * (ns + 1) / 2;
     int64_t want = std::max<int64_t>(1, (1024 + pairs - 1) / pairs);
     want = std::min<int64_t>(want, std::max<int64_t>(1, (int64_t(256) << 20) / (int64_t(k) * k * 8)));
-    want = std::min<int64_t>(want, std::max<int64_t>(1, N / kSP));
+    want = std::min<int64_t>(want, std::max<int64_t>(1, N / 256));
     chunk = (N + want - 1) / want;
     chunk = (chunk + kSP - 1) / kSP * kSP;
     nchunk = int((N + chunk - 1) / chunk);
@@ -327,14 +331,6 @@ __global__ void k_gemv_t_seg(const double* __restrict__ Z, int64_t N, const doub
     if (threadIdx.x == 0) wpart[int64_t(sgi) * gridDim.x + j] = sh[0];
 }
 
-__global__ void k_gemv_t_fold(const double* __restrict__ wpart, int nseg, int k, double* __restrict__ w) {
-    const int j = blockIdx.x * kT + threadIdx.x;
-    if (j >= k) return;
-    double s = 0.0;
-    for (int q = 0; q < nseg; ++q) s += wpart[int64_t(q) * k + j];
-    w[j] = s;
-}
-
 __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, double diag,
                             double* __restrict__ M) {
     int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
@@ -345,13 +341,41 @@ __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, 
 }
 
 // In-place Cholesky of the k x k SPD matrix M (row-major, lower triangle used),
-// one block, right-looking in panels of 16 columns: the first wavefront factors
+// one block, right-looking in panels of kCB columns: the first wavefront factors
 // the diagonal block in registers (lane r holds row r, shuffles broadcast the
-// pivots), all threads solve the panel below it (one row each) and update the
-// trailing lower triangle. status[0] = 0 ok, 1 = non-positive pivot.
-constexpr int kCB = 16;
-__global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int k, int* __restrict__ status) {
-    __shared__ double D[kCB][kCB + 1];
+// pivots), all threads solve the panel below it (one row each), then the
+// trailing lower triangle is updated in kTT x kTT tiles whose two panel slices
+// are staged in LDS. status[0] = 0 ok, 1 = non-positive pivot.
+// Launched with kCholT threads (8 x 4 trailing elements per thread).
+constexpr int kCB = 16, kTT = 128, kCholT = 512;
+// rows i >= j0 + nb of the panel: x L_D^T = m, with L_D in D (reciprocal
+// pivots on its diagonal); kept out of line so that its registers are not
+// allocated together with the diagonal factorisation's
+__device__ __attribute__((noinline)) void chol_panel(double* __restrict__ M, int k, int j0, int nb,
+                                                     const double (*D)[kCB + 1]) {
+    for (int i = j0 + nb + int(threadIdx.x); i < k; i += kCholT) {
+        double x[kCB];
+        double* mi = M + int64_t(i) * k + j0;
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) x[c] = c < nb ? mi[c] : 0.0;  // all loads before any store
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) {
+            if (c < nb) {
+                double v = x[c];
+#pragma unroll
+                for (int q = 0; q < c; ++q) v -= x[q] * D[c][q];
+                x[c] = v * D[c][c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kCB; ++c)
+            if (c < nb) mi[c] = x[c];
+    }
+}
+
+__global__ __launch_bounds__(kCholT) void k_chol(double* __restrict__ M, int k, int* __restrict__ status) {
+    __shared__ double D[kCB][kCB + 1];  // diagonal block, reciprocals on its diagonal
+    __shared__ double Pa[kTT][kCB + 1], Pb[kTT][kCB + 1];
     __shared__ int bad;
     const int t = threadIdx.x;
     if (t == 0) bad = 0;
@@ -371,8 +395,9 @@ __global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int k, in
                         dcc = 1e-300;
                     }
                     dcc = sqrt(dcc);
+                    const double rdc = 1.0 / dcc;
                     if (t == c) d[c] = dcc;
-                    else if (t > c) d[c] /= dcc;
+                    else if (t > c) d[c] *= rdc;
 #pragma unroll
                     for (int cc = c + 1; cc < kCB; ++cc) {
                         const double lcc = __shfl(d[c], cc, 64);  // L[cc][c], from lane cc
@@ -385,56 +410,70 @@ __global__ __launch_bounds__(1024) void k_chol(double* __restrict__ M, int k, in
                 for (int c = 0; c < kCB; ++c)
                     if (c <= t) {
                         M[int64_t(j0 + t) * k + j0 + c] = d[c];
-                        D[t][c] = d[c];
+                        D[t][c] = c == t ? 1.0 / d[c] : d[c];  // reciprocal on the diagonal
                     }
             }
         }
         __syncthreads();
-        // panel: rows below the block, x L_D^T = m
-        for (int i = j0 + nb + t; i < k; i += blockDim.x) {
-            double x[kCB];
-            double* mi = M + int64_t(i) * k + j0;
-#pragma unroll
-            for (int c = 0; c < kCB; ++c) x[c] = c < nb ? mi[c] : 0.0;  // all loads before any store
-#pragma unroll
-            for (int c = 0; c < kCB; ++c) {
-                if (c < nb) {
-                    double v = x[c];
-#pragma unroll
-                    for (int q = 0; q < c; ++q) v -= x[q] * D[c][q];
-                    x[c] = v / D[c][c];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kCB; ++c)
-                if (c < nb) mi[c] = x[c];
-        }
+        chol_panel(M, k, j0, nb, D);
         __syncthreads();
-        // trailing lower triangle
-        const int m = k - j0 - nb;
-        for (int e = t; e < m * m; e += blockDim.x) {
-            const int r = e / m, cc = e % m;
-            if (cc > r) continue;
-            const double* li = M + int64_t(j0 + nb + r) * k + j0;
-            const double* lc = M + int64_t(j0 + nb + cc) * k + j0;
-            double sacc = 0.0;
-            for (int q = 0; q < nb; ++q) sacc += li[q] * lc[q];
-            M[int64_t(j0 + nb + r) * k + j0 + nb + cc] -= sacc;
-        }
+        // trailing lower triangle, tile (R, Cc) with Cc <= R
+        const int j1 = j0 + nb, m = k - j1, nt = (m + kTT - 1) / kTT;
+        const int ty = t / 32, tx = t % 32;
+        for (int R = 0; R < nt; ++R)
+            for (int Cc = 0; Cc <= R; ++Cc) {
+                for (int e = t; e < kTT * kCB; e += kCholT) {
+                    const int r = e / kCB, q = e % kCB;
+                    const int ia = j1 + R * kTT + r, ib = j1 + Cc * kTT + r;
+                    Pa[r][q] = (ia < k && q < nb) ? M[int64_t(ia) * k + j0 + q] : 0.0;
+                    Pb[r][q] = (ib < k && q < nb) ? M[int64_t(ib) * k + j0 + q] : 0.0;
+                }
+                __syncthreads();
+                double acc[8][4];
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 4
+                for (int q = 0; q < kCB; ++q) {
+                    double pa[8], pb[4];
+#pragma unroll
+                    for (int a = 0; a < 8; ++a) pa[a] = Pa[ty + 16 * a][q];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) pb[b] = Pb[tx + 32 * b][q];
+#pragma unroll
+                    for (int a = 0; a < 8; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] += pa[a] * pb[b];
+                }
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int r = R * kTT + ty + 16 * a, c = Cc * kTT + tx + 32 * b;
+                        if (r < m && c <= r) M[int64_t(j1 + r) * k + j1 + c] -= acc[a][b];
+                    }
+                __syncthreads();  // before the panel slices are staged again
+            }
     }
     __syncthreads();
     if (t == 0) status[0] = bad;
 }
 
-// t = (L L^T)^{-1} w with L the Cholesky factor in M (one block, panels of 16).
-// The first wavefront solves each diagonal block in registers (forward: lane j
-// holds row j of the block; backward: lane j holds column j), all threads then
-// update the remaining entries.
-__global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double* __restrict__ w,
+// t = (L L^T)^{-1} w with L the Cholesky factor in the lower triangle of M and
+// w the sum of the nseg partial vectors wpart[g][:] (segments in order); one
+// block, panels of kCB. The first wavefront solves each diagonal block in
+// registers (forward: lane j holds row j of the block; backward: lane j holds
+// column j), all threads then update the remaining entries.
+__global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double* __restrict__ wpart, int nseg,
                              double* __restrict__ t) {
     extern __shared__ double sx[];
     const int tid = threadIdx.x;
-    for (int i = tid; i < k; i += blockDim.x) sx[i] = w[i];
+    for (int i = tid; i < k; i += blockDim.x) {
+        double v = 0.0;
+        for (int g = 0; g < nseg; ++g) v += wpart[int64_t(g) * k + i];
+        sx[i] = v;
+    }
     __syncthreads();
     for (int j0 = 0; j0 < k; j0 += kCB) {  // forward: L z = w
         const int nb = min(kCB, k - j0);
@@ -718,7 +757,7 @@ struct Reducer {
         hipLaunchKernelGGL(k_dots<NS>, dim3(nb), dim3(kT), 0, st, d, n, part.p);
         hipLaunchKernelGGL(k_fold_partials, dim3(NS), dim3(64), 0, st, part.p, int(nb), NS, out.p);
         ANV_HIP(hipMemcpyAsync(host, out.p, NS * sizeof(double), hipMemcpyDeviceToHost, st));
-        ANV_HIP(hipStreamSynchronize(st));
+        host_wait(st);
         return host;
     }
     double dot(const double* a, const double* b, int64_t n, hipStream_t st) {
@@ -733,7 +772,7 @@ struct Workspace {
     int64_t N = 0;
     int k = 0;
     const double* Z = nullptr;            // N x k column-major low-rank factor Z^T
-    DevBuf<double> M, Mpart, w, t;        // capacitance and its factor
+    DevBuf<double> M, Mpart, t;           // capacitance (its factor in place), partials, M^{-1} w
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
     DevBuf<double> wpart;                 // per-segment partials of Z^T u
@@ -759,9 +798,8 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
         hipLaunchKernelGGL(k_gemv_t_seg, dim3(ws.k, ws.nseg), dim3(kT), 0, st, ws.Z, N, ws.tmp.p, ws.seg,
                            ws.wpart.p);
-        hipLaunchKernelGGL(k_gemv_t_fold, dim3(nblk(ws.k)), dim3(kT), 0, st, ws.wpart.p, ws.nseg, ws.k, ws.w.p);
-        hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.w.p,
-                           ws.t.p);
+        hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.wpart.p,
+                           ws.nseg, ws.t.p);
     }
     hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p,
                        1.0 / s, has_last ? 1 : 0, out);
@@ -775,10 +813,10 @@ void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t 
                        pl.N, k, th, ws.chunk, ws.Mpart.p);
     hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, st, ws.M.p, k, ws.status.p);
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
     int bad = 0;
     ANV_HIP(hipMemcpyAsync(&bad, ws.status.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     if (bad) throw Error(ANOVA_NUMERICAL, "capacitance matrix is not positive definite");
 }
 
@@ -787,7 +825,6 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
     ws.k = k;
     if (k > 0) {
         ws.M.alloc(size_t(k) * k);
-        ws.w.alloc(k);
         ws.t.alloc(k);
         ws.status.alloc(1);
         syrk_chunks(N, k, ws.nchunk, ws.chunk);
@@ -836,14 +873,14 @@ int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64
             hipLaunchKernelGGL(k_argmax_sum, dim3(nb), dim3(kT), 0, st, dres.p, N, pv.p, pi.p, ps.p);
             hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, pv.p, pi.p, ps.p, int(nb), fin.p);
             ANV_HIP(hipMemcpyAsync(hfin, fin.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
-            ANV_HIP(hipStreamSynchronize(st));
+            host_wait(st);
             const double best = hfin[0], rest = hfin[2];
             const int64_t p = int64_t(hfin[1]);
             if (!(best > 0.0)) break;
             if (err_tol > 0.0 && rest <= err_tol * trace0) break;
             hipLaunchKernelGGL(k_pivot_value, dim3(1), dim3(1), 0, st, L, N, p, r, kpp, fin.p + 3);
             ANV_HIP(hipMemcpyAsync(hfin + 3, fin.p + 3, sizeof(double), hipMemcpyDeviceToHost, st));
-            ANV_HIP(hipStreamSynchronize(st));
+            host_wait(st);
             const double pivval = hfin[3];
             if (!(pivval > 0.0)) break;
             hipLaunchKernelGGL(k_pchol_column, dim3(nblk(N)), dim3(kT), 0, st, pl.xw.p, N, P, is2.p, et.p, p,
@@ -856,7 +893,7 @@ int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64
         throw;
     }
     (void)hipHostFree(hfin);
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     return r;
 }
 
@@ -923,7 +960,7 @@ struct Gram {
         }
         std::vector<double> h(size_t(k) * k);
         ANV_HIP(hipMemcpyAsync(h.data(), M.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        ANV_HIP(hipStreamSynchronize(st));
+        host_wait(st);
         return h;
     }
 };
@@ -957,7 +994,7 @@ void orthonormalize(DevBuf<double>& Y, DevBuf<double>& tmp, int64_t N, int k, hi
                            Y.p, N, k, T.p, k, tmp.p);
         std::swap(Y.p, tmp.p);
     }
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
 }
 
 // Z^T (N x k, column-major, ld N) = (K Q) L^{-T} D^{-1/2} with Q^T K Q = L D L^T (clamped)
@@ -1006,7 +1043,7 @@ void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st
     hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((k + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
                        tmp.p, N, k, Td.p, k, Zt);
     ANV_HIP(hipGetLastError());
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
 }
 
 }  // namespace
@@ -1019,7 +1056,7 @@ int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl,
     if (r > 0)
         ANV_HIP(hipMemcpy2DAsync(L, ldl * sizeof(double), tmp.p, pl.N * sizeof(double), pl.N * sizeof(double), r,
                                  hipMemcpyDeviceToDevice, st));
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     return r;
 }
 
@@ -1040,7 +1077,7 @@ void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, i
         nystrom_core(pl, Y, k, Z.p, st);
         ANV_HIP(hipMemcpy2DAsync(Zt, ldz * sizeof(double), Z.p, N * sizeof(double), N * sizeof(double), k,
                                  hipMemcpyDeviceToDevice, st));
-        ANV_HIP(hipStreamSynchronize(st));
+        host_wait(st);
     }
 }
 
@@ -1070,7 +1107,7 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
         enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
         nystrom_core(pl, Y, o.rank, f.Z.p, st);
     }
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     f.t_setup_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
 
@@ -1097,7 +1134,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     // labels: must be +-1 with both classes present
     std::vector<double> yh(N);
     ANV_HIP(hipMemcpyAsync(yh.data(), labels, N * sizeof(double), hipMemcpyDeviceToHost, st));
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     double ysum = 0.0;
     int64_t npos = 0;
     for (double v : yh) {
@@ -1154,7 +1191,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         hipLaunchKernelGGL(k_ipm_stats, dim3(rb), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, spart.p);
         hipLaunchKernelGGL(k_fold_partials, dim3(5), dim3(64), 0, st, spart.p, int(rb), 5, sout.p);
         ANV_HIP(hipMemcpyAsync(sh, sout.p, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
-        ANV_HIP(hipStreamSynchronize(st));
+        host_wait(st);
         const double quad = sh[1];
         D = sh[0] - 0.5 * quad;
         Pr = 0.5 * quad + C * sh[2];
@@ -1277,7 +1314,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         double smax_dl[2];
         ANV_HIP(hipMemcpyAsync(&smax_dl[0], sout.p, sizeof(double), hipMemcpyDeviceToHost, st));
         ANV_HIP(hipMemcpyAsync(&smax_dl[1], sol.p + N, sizeof(double), hipMemcpyDeviceToHost, st));
-        ANV_HIP(hipStreamSynchronize(st));
+        host_wait(st);
         const double step = o.gamma0 * std::min(1.0, smax_dl[0]);
         s_prev = step;
         hipLaunchKernelGGL(k_step, dim3(nblk(N)), dim3(kT), 0, st, alpha, sol.p, N, step);
@@ -1285,7 +1322,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         ++it;
         eval_stats(xa, xl, D, Pr, G);
     }
-    ANV_HIP(hipStreamSynchronize(st));
+    host_wait(st);
     *lambda_out = lam;
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
