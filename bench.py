@@ -14,7 +14,10 @@ beside it. Accuracy is checked every run on sampled rows against the FP64
 direct-sum oracle; a run above relative l2 error 1e-4 reports value 0.
 
 Also reported: IPM solve latency p50/p99 for the small plain problem and the
-full N = 500000 problem, and the oracle's rate on the host cores.
+full N = 500000 problem; the request server (continuous batching against one
+solve at a time); the hyperparameter grid over cross-validation folds (solves
+per second against FP64 solves one at a time); and the oracle's rate on the
+host cores.
 
 Prints ONE JSON line. --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -59,6 +62,11 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests of the Poisson serving stream (0 = skip)")
     ap.add_argument("--serving-rate", type=float, default=2.0)
+    ap.add_argument("--grid-folds", type=int, default=5,
+                    help="folds of the hyperparameter grid (8 sigma x 8 C solves each); 0 skips it")
+    ap.add_argument("--grid-max-active", type=int, default=8)
+    ap.add_argument("--grid-reference-solves", type=int, default=8,
+                    help="solves of the grid repeated one at a time with FP64 plans")
     ap.add_argument("--serving-max-active", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 256 MiB device-to-device three times (a known-size "
@@ -138,7 +146,7 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
             "ip_iters_p50": float(np.percentile([s["ip_iters"] for s in stats], 50)),
             "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
             "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
-            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom"}[precond], "precision": "fp64"}
+            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom", 3: "barrier-diagonal"}[precond], "precision": "fp64"}
 
 
 def serving(lib, workloads, n, rate, max_active, share):
@@ -179,6 +187,53 @@ def serving(lib, workloads, n, rate, max_active, share):
             "solves_per_s": n / span, "converged": int(sum(r["status"] == 0 for r in res)),
             "matvecs_in_shared_launches": matvecs, "shared_launch_count": launches,
             "N_max": int(max(r["N"] for r in stream)), "N_median": int(np.median([r["N"] for r in stream]))}
+
+
+def grid(lib, torch, workloads, dev, folds, max_active, ref_solves):
+    """Hyperparameter grid over cross-validation folds: 8 sigma x 8 C per fold,
+    mixed-precision plans, solves of a plan sharing its pivoted-Cholesky
+    factor, matvecs of concurrent solves in shared launches."""
+    g = workloads.cv_grid(seed=0)
+    p = g["problem"]
+    folds = min(folds, len(g["folds"]))
+    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0)
+    t0 = time.perf_counter()
+    probs, data = [], []
+    for tr, _ in g["folds"][:folds]:
+        Xd = torch.from_numpy(p.X[tr]).to(dev)
+        yd = torch.from_numpy(p.labels[tr]).to(dev)
+        data.append((Xd, yd))
+        for s in g["sigmas"]:
+            probs.append((lib.Plan(Xd, p.windows, float(s), precision=lib.PREC_MIXED), yd, list(g["Cs"])))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res, launches, matvecs = lib.grid_solve(probs, max_active=max_active, **kw)
+    t2 = time.perf_counter()
+    st = [x for r in res for x in r[2]]
+    status = {}
+    for x in st:
+        status[str(x["status"])] = status.get(str(x["status"]), 0) + 1
+    out = {"workload": f"cross-validation grid: N=50000, d=15 (5 windows of 3), {folds} of 5 folds (class-balanced "
+                       "training parts of 39874..39982 points), sigma 8 log-spaced in 0.25..4, C 8 log-spaced in "
+                       "0.1..1000; mixed-precision plans, pivoted-Cholesky rank 200 shared per plan, automatic "
+                       "initial barrier parameter, at most 100 iterations",
+           "solves": len(st), "plans": len(probs), "plan_s": t1 - t0, "wall_s": t2 - t1,
+           "solves_per_s": len(st) / (t2 - t1), "status_counts": status,
+           "ip_iters_mean": float(np.mean([x["ip_iters"] for x in st])),
+           "shared_launches": launches, "matvecs": matvecs, "max_active": max_active}
+    if ref_solves > 0:
+        # the same solves one at a time, FP64 plans (a sample spread over sigma and C)
+        Xd, yd = data[0]
+        pairs = [(g["sigmas"][i % 8], g["Cs"][(3 * i) % 8]) for i in range(ref_solves)]
+        t3 = time.perf_counter()
+        for s, C in pairs:
+            pl = lib.Plan(Xd, p.windows, float(s))
+            pl.solve(yd, float(C), allow_not_converged=True, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t3
+        out["reference_fp64_one_at_a_time"] = {"solves": ref_solves, "solves_per_s": ref_solves / dt,
+                                               "note": "plan creation and factor build per solve included"}
+    return out
 
 
 def cpu_baseline(p, seconds):
@@ -317,8 +372,9 @@ def main():
     ipm = []
     if a.ipm_small_solves > 0:
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.small_plain(seed=s, N=2000, d=9, R=0),
-                               a.ipm_small_solves, lib.PRECOND_PCHOL, 200,
-                               "plain-small: N=2000 d=9, 3 windows, sigma=1, C=1"))
+                               a.ipm_small_solves, lib.PRECOND_DIAG, 0,
+                               "plain-small: N=2000 d=9, 3 windows, sigma=1, C=1; MINRES without a kernel "
+                               "preconditioner (barrier diagonal only)"))
     if a.ipm_full_solves > 0:
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
                                a.ipm_full_solves, lib.PRECOND_NYSTROM, 200,
@@ -332,6 +388,8 @@ def main():
         cont = serving(lib, workloads, a.serving_requests, a.serving_rate, a.serving_max_active, True)
         one = serving(lib, workloads, a.serving_requests, a.serving_rate, 1, False)
         out["serving"] = {"workload": label, "continuous_batching": cont, "one_at_a_time": one}
+    if a.grid_folds > 0:
+        out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
     if a.copy_calibration:

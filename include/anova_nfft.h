@@ -43,9 +43,12 @@ extern "C" {
 #define ANOVA_PRECOND_NONE     0  /* unpreconditioned MINRES                           */
 #define ANOVA_PRECOND_PCHOL    1  /* greedy pivoted Cholesky, Algorithm 2 (Section 4)   */
 #define ANOVA_PRECOND_NYSTROM  2  /* randomized Nystrom, Q = orth(K G) (Section 4)      */
+#define ANOVA_PRECOND_DIAG     3  /* the block-diagonal preconditioner of Section 5
+                                     with no low-rank term: diag(Theta, y^T Theta^{-1} y),
+                                     the barrier diagonal only (no approximation of K) */
 
 #define ANOVA_OPTS_VERSION 1
-#define ANOVA_IPM_OPTS_VERSION 1
+#define ANOVA_IPM_OPTS_VERSION 2
 
 typedef struct anova_plan_s* anova_plan_t;
 
@@ -170,6 +173,10 @@ typedef struct {
                             1: constant sigma_bar (Section 2 allows either)      */
     double  err_tol;     /* pivoted-Cholesky trace tolerance (Table 1: 1e-5)     */
     uint64_t seed;       /* Gaussian test matrix of the Nystrom method           */
+    int32_t graphs;      /* 1: each MINRES iteration is captured once as a HIP
+                            graph and replayed (solves outside a server or grid);
+                            0: launched kernel by kernel. Same arithmetic.       */
+    int32_t reserved;
 } anova_ipm_opts;
 
 typedef struct {
@@ -192,7 +199,7 @@ typedef struct {
 /* Fill `o` with the defaults: Table 1 values (max_ip = 50 raised to 100,
  * max_kry = 100, tol_kry = 1e-3, sigma_bar = 0.6, gamma0 = 0.99995,
  * mu0 = 1, err_tol = 1e-5), tol = 1e-6, tol_inf = 1e-1, precond = PCHOL,
- * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0. */
+ * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0, graphs = 1. */
 int anova_ipm_opts_default(anova_ipm_opts* o);
 
 /* Train: alpha (device, N FP64 out), lambda (host, 1 FP64 out; the bias of

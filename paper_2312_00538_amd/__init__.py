@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libanova_nfft.so")
 
 OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, NUMERICAL = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
-PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM = 0, 1, 2
+PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG = 0, 1, 2, 3
 
 EXPORTED = [
     "anova_opts_default", "anova_plan_create", "anova_matvec", "anova_plan_destroy",
@@ -54,7 +54,8 @@ class IpmOpts(ctypes.Structure):
                 ("precond", ctypes.c_int32), ("tol", ctypes.c_double), ("tol_inf", ctypes.c_double),
                 ("tol_kry", ctypes.c_double), ("sigma_bar", ctypes.c_double), ("gamma0", ctypes.c_double),
                 ("mu0", ctypes.c_double), ("rank", ctypes.c_int32), ("mu_rule", ctypes.c_int32),
-                ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64)]
+                ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):

@@ -146,6 +146,7 @@ int anova_ipm_opts_default(anova_ipm_opts* o) {
     o->rank = 200;
     o->err_tol = 1e-5;
     o->seed = 0;
+    o->graphs = 1;
     return ANOVA_OK;
 }
 

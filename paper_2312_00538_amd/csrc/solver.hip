@@ -617,7 +617,134 @@ __global__ void k_step(double* __restrict__ a, const double* __restrict__ da, in
 // p = (A z) * sc - cprev * rprev, with A = [[Y K Y + Theta, -y], [-y^T, 0]] and
 // kyz = K (y * z[0:N]) already computed; p[N] gets -y^T z[0:N] * sc - cprev*rprev[N]
 // from the host-provided dot value.
+// preconditioners with a low-rank factor of K (the others need none)
+inline bool low_rank_precond(int p) { return p == ANOVA_PRECOND_PCHOL || p == ANOVA_PRECOND_NYSTROM; }
+
+// MINRES iterations whose convergence flag the host reads before queueing the next
+constexpr int kEagerChecks = 4;
+
+// sqrt(a^2 + b^2) from correctly rounded operations only (one fma), so that
+// the host loop and the device kernel of MINRES round identically
+__host__ __device__ inline double hypot_ieee(double a, double b) {
+    a = fabs(a);
+    b = fabs(b);
+    const double m = a > b ? a : b, n = a > b ? b : a;
+    if (m == 0.0) return 0.0;
+    const double r = n / m;
+    return m * sqrt(fma(r, r, 1.0));
+}
+
+// Scalars of one MINRES solve, kept on the device so that an iteration needs
+// no host round trip: the three inner products of the iteration, the Lanczos
+// and Givens recurrences, and the coefficients of the solution update.
+struct KryScal {
+    double dot_ytz, dot_a, dot_rz;             // y^T z, z^T p, r^T M^{-1} r
+    double beta, beta_prev, beta1, c, s, dbar, eps_next, phibar;
+    double rtol, inv_s;                        // relative tolerance; 1 / (y^T A_hat^{-1} y)
+    double inv_beta_prev, eps_cur, delta, inv_gam, phi;  // update of this iteration
+    int done;                                  // converged: later iterations change nothing
+    int active;                                // this iteration updates the solution
+    int kit;                                   // iterations that updated the solution
+};
+
+// start of a Newton solve: tolerance, preconditioner scalar, Givens state
+__global__ void k_kry_start(KryScal* ks, double rtol, double s_last) {
+    ks->rtol = rtol;
+    ks->inv_s = 1.0 / s_last;
+    ks->beta_prev = 0.0;
+    ks->c = -1.0;
+    ks->s = 0.0;
+    ks->dbar = 0.0;
+    ks->eps_next = 0.0;
+    ks->done = 0;
+    ks->active = 0;
+    ks->kit = 0;
+}
+
+// beta_1 = sqrt(r0^T M^{-1} r0) from dot_rz
+__global__ void k_kry_beta1(KryScal* ks) {
+    const double b = sqrt(fmax(0.0, ks->dot_rz));
+    ks->beta = b;
+    ks->beta1 = b;
+    ks->phibar = b;
+    ks->done = b > 0.0 ? 0 : 1;
+}
+
+// p = A (z / beta) - (beta / beta_prev) r_prev, with A z = [Y K Y z + Theta z - y z_N ; -y^T z]
 __global__ void k_newton_out(const double* __restrict__ y, const double* __restrict__ th,
+                             const double* __restrict__ z, const double* __restrict__ kyz, int64_t N,
+                             const KryScal* __restrict__ ks, const double* __restrict__ rprev,
+                             double* __restrict__ p) {
+    if (ks->done) return;
+    const double sc = 1.0 / ks->beta;
+    const double cprev = ks->kit > 0 ? ks->beta / ks->beta_prev : 0.0;
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) {
+        double v = y[i] * kyz[i] + th[i] * z[i] - y[i] * z[N];
+        p[i] = v * sc - cprev * rprev[i];
+    } else if (i == N) {
+        p[N] = -ks->dot_ytz * sc - cprev * rprev[N];
+    }
+}
+
+// p -= (a / beta) r with a = z^T p / beta
+__global__ void k_kry_axpy(double* __restrict__ p, const double* __restrict__ r, int64_t n,
+                           const KryScal* __restrict__ ks) {
+    if (ks->done) return;
+    const double a = ks->dot_a / ks->beta;
+    const double sa = -a / ks->beta;
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) p[i] += sa * r[i];
+}
+
+// Lanczos and Givens recurrences of one iteration (one thread), after the new
+// beta's inner product
+__global__ void k_kry_scalars(KryScal* ks) {
+#pragma clang fp contract(off)  // round as the host loop does (no fused multiply-adds)
+    if (ks->done) {
+        ks->active = 0;
+        return;
+    }
+    ks->active = 1;
+    ks->kit += 1;
+    const double a = ks->dot_a / ks->beta;
+    const double beta_prev = ks->beta;
+    const double beta = sqrt(fmax(0.0, ks->dot_rz));
+    const double c = ks->c, s = ks->s, dbar = ks->dbar;
+    const double eps_cur = ks->eps_next;
+    const double delta = c * dbar + s * a;
+    const double gbar = s * dbar - c * a;
+    ks->eps_next = s * beta;
+    ks->dbar = -c * beta;
+    double gam = hypot_ieee(gbar, beta);
+    if (gam == 0.0) gam = 1e-300;
+    ks->c = gbar / gam;
+    ks->s = beta / gam;
+    ks->phi = ks->c * ks->phibar;
+    ks->phibar = ks->s * ks->phibar;
+    ks->beta_prev = beta_prev;
+    ks->beta = beta;
+    ks->inv_beta_prev = 1.0 / beta_prev;
+    ks->eps_cur = eps_cur;
+    ks->delta = delta;
+    ks->inv_gam = 1.0 / gam;
+    ks->done = (!(ks->phibar > ks->rtol * ks->beta1) || !(beta > 0.0)) ? 1 : 0;
+}
+
+// d_new = (z / beta_prev - eps d2 - delta d1) / gam; x += phi d_new; rotates d2 <- d1 <- d_new
+__global__ void k_minres_update(const double* __restrict__ z, int64_t n, const KryScal* __restrict__ ks,
+                                double* __restrict__ d1, double* __restrict__ d2, double* __restrict__ x) {
+    if (!ks->active) return;
+    int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= n) return;
+    double dn = (z[i] * ks->inv_beta_prev - ks->eps_cur * d2[i] - ks->delta * d1[i]) * ks->inv_gam;
+    d2[i] = d1[i];
+    d1[i] = dn;
+    x[i] += ks->phi * dn;
+}
+
+// by-value forms of the MINRES kernels, for solves whose host loop keeps the scalars
+__global__ void k_newton_out_v(const double* __restrict__ y, const double* __restrict__ th,
                              const double* __restrict__ z, const double* __restrict__ kyz, int64_t N,
                              double sc, double cprev, const double* __restrict__ rprev,
                              double lastv, double* __restrict__ p) {
@@ -636,7 +763,7 @@ __global__ void k_axpy(double* __restrict__ x, const double* __restrict__ v, int
 }
 
 // d_new = (z / beta - e * d2 - dl * d1) / gam; x += phi * d_new; rotates d2 <- d1 <- d_new
-__global__ void k_minres_update(const double* __restrict__ z, int64_t n, double inv_beta, double e,
+__global__ void k_minres_update_v(const double* __restrict__ z, int64_t n, double inv_beta, double e,
                                 double dl, double inv_gam, double phi, double* __restrict__ d1,
                                 double* __restrict__ d2, double* __restrict__ x) {
     int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
@@ -657,7 +784,7 @@ __global__ void k_wb_in(const double* __restrict__ y, const double* __restrict__
 // second half: out = r / theta - (y / theta) * (Z t); out[N] = r[N] / s
 __global__ void k_wb_out(const double* __restrict__ y, const double* __restrict__ th,
                          const double* __restrict__ r, const double* __restrict__ Z, int64_t N, int k,
-                         const double* __restrict__ t, double inv_s, int has_last,
+                         const double* __restrict__ t, const double* __restrict__ inv_s, int has_last,
                          double* __restrict__ out) {
     __shared__ double ts[1024];
     for (int j = threadIdx.x; j < k; j += kT) ts[j] = t[j];
@@ -669,7 +796,7 @@ __global__ void k_wb_out(const double* __restrict__ y, const double* __restrict_
         double ti = 1.0 / th[i];
         out[i] = r[i] * ti - y[i] * ti * zt;
     } else if (i == N && has_last) {
-        out[N] = r[N] * inv_s;
+        out[N] = r[N] * *inv_s;
     }
 }
 
@@ -766,6 +893,15 @@ struct Reducer {
         d.b[0] = b;
         return dots<1>(d, n, st)[0];
     }
+    // a^T b into out (device), no host wait
+    void dot_dev(const double* a, const double* b, int64_t n, double* out, hipStream_t st) {
+        DotArgs d{};
+        d.a[0] = a;
+        d.b[0] = b;
+        const unsigned nb = blocks(n);
+        hipLaunchKernelGGL(k_dots<1>, dim3(nb), dim3(kT), 0, st, d, n, part.p);
+        hipLaunchKernelGGL(k_fold_partials, dim3(1), dim3(64), 0, st, part.p, int(nb), 1, out);
+    }
 };
 
 struct Workspace {
@@ -790,9 +926,9 @@ void kmv(Plan& pl, const MatvecHook* hook, const double* x, double* y, hipStream
         enqueue_matvec(pl, x, 1, pl.N, y, pl.N, st);
 }
 
-// A_hat^{-1} applied to r (first N entries); out[N] = r[N]/s when has_last
+// A_hat^{-1} applied to r (first N entries); out[N] = r[N] * inv_s[0] (device) when has_last
 void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, const double* r,
-                    double s, bool has_last, double* out, hipStream_t st) {
+                    const double* inv_s, bool has_last, double* out, hipStream_t st) {
     const int64_t N = pl.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
@@ -801,8 +937,8 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
         hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.wpart.p,
                            ws.nseg, ws.t.p);
     }
-    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p,
-                       1.0 / s, has_last ? 1 : 0, out);
+    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p, inv_s,
+                       has_last ? 1 : 0, out);
 }
 
 void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t st) {
@@ -1086,9 +1222,9 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
     using clk = std::chrono::steady_clock;
     const int64_t N = pl.N;
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
-                  o.precond == ANOVA_PRECOND_NYSTROM,
+                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG,
               "unknown preconditioner");
-    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
+    ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");
     const auto t0 = clk::now();
     f.precond = o.precond;
@@ -1126,9 +1262,9 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
               "tolerances must be > 0 and mu0 finite");
     ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
-                  o.precond == ANOVA_PRECOND_NYSTROM,
+                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG,
               "unknown preconditioner");
-    ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
+    ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");
 
     // labels: must be +-1 with both classes present
@@ -1144,11 +1280,47 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     }
     ANV_CHECK(npos > 0 && npos < N, "both classes must be present");
 
+    // Krylov iterations: device scalars, host flags, and (direct path) graphs
+    // replayed on a stream of the solve's own
+    struct KryRes {
+        hipStream_t caller = nullptr, own = nullptr;
+        hipEvent_t fev[2] = {nullptr, nullptr};
+        int* hflag = nullptr;  // done flags of two iterations, iteration count
+        hipGraphExec_t g[6] = {};
+        ~KryRes() {
+            (void)hipStreamSynchronize(own ? own : caller);
+            for (auto& x : g)
+                if (x) (void)hipGraphExecDestroy(x);
+            if (own) (void)hipStreamDestroy(own);
+            for (auto e : fev)
+                if (e) (void)hipEventDestroy(e);
+            if (hflag) (void)hipHostFree(hflag);
+        }
+    } kr;
+    kr.caller = st;
+    const bool use_graphs = o.graphs != 0 && hook == nullptr && !pl.profiling;
+    bool warmed = false;
+    if (use_graphs) {
+        ANV_HIP(hipStreamCreateWithFlags(&kr.own, hipStreamNonBlocking));
+        hipEvent_t e = nullptr;
+        ANV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        const hipError_t r1 = hipEventRecord(e, st);
+        const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(kr.own, e, 0) : r1;
+        (void)hipEventDestroy(e);
+        ANV_HIP(r2);
+        st = kr.own;
+    }
+    ANV_HIP(hipHostMalloc(&kr.hflag, 4 * sizeof(int)));
+    for (auto& e : kr.fev)
+        ANV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming | (t_blocking_waits ? hipEventBlockingSync : 0)));
+    DevBuf<KryScal> ksd;
+    ksd.alloc(1);
+
     Reducer red;
     Workspace ws;
     LowRankFactor own;
     if (factor) {
-        ANV_CHECK(factor->precond == o.precond && (o.precond == ANOVA_PRECOND_NONE || factor->Z.n >= size_t(N) * factor->rank),
+        ANV_CHECK(factor->precond == o.precond && (!low_rank_precond(o.precond) || factor->Z.n >= size_t(N) * factor->rank),
                   "shared factor does not match the preconditioner options or the plan");
     } else {
         build_low_rank(pl, o, own, st);
@@ -1156,7 +1328,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     }
     const int rank_used = factor->rank;
     ws.Z = factor->Z.p;
-    setup_factor_storage(ws, N, o.precond == ANOVA_PRECOND_NONE ? 0 : rank_used);
+    setup_factor_storage(ws, N, low_rank_precond(o.precond) ? rank_used : 0);
     const double t_setup_ms = factor->t_setup_ms;
 
     // state
@@ -1236,75 +1408,157 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
                            rhs.p);
         // preconditioner for this iteration: diag(A_hat, s), s = y^T A_hat^{-1} y
         double s_last = 1.0;
-        const bool prec = o.precond != ANOVA_PRECOND_NONE;
+        const bool prec = o.precond != ANOVA_PRECOND_NONE;  // diag(A_hat, s); without a factor A_hat = Theta
         if (prec) {
             refresh_capacitance(pl, ws, th.p, st);
-            woodbury_apply(pl, ws, labels, th.p, labels, 1.0, false, ytmp.p, st);
+            woodbury_apply(pl, ws, labels, th.p, labels, nullptr, false, ytmp.p, st);
             s_last = red.dot(labels, ytmp.p, N, st);
             if (!(s_last > 0.0)) {
                 status = ANOVA_NUMERICAL;
                 break;
             }
         }
+        KryScal* ks = ksd.p;
+        const double* inv_s = &ks->inv_s;  // device address
         auto precond = [&](const double* r, double* out) {
             if (prec)
-                woodbury_apply(pl, ws, labels, th.p, r, s_last, true, out, st);
+                woodbury_apply(pl, ws, labels, th.p, r, inv_s, true, out, st);
             else
                 hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, r, out, n1);
         };
-        // ---- preconditioned MINRES on A sol = rhs (Lanczos in the M-inner product + Givens QR)
+        // ---- preconditioned MINRES on A sol = rhs (Lanczos in the M-inner product + Givens QR).
+        // Own matvecs: the recurrence scalars stay on the device, the host learns
+        // of convergence after the iteration or, past the first few, one iteration
+        // late (an iteration that starts after convergence leaves the solution
+        // untouched, so the result is that of a loop that stops at once), and
+        // iterations are replayed from graphs.
         const double rtol = std::max(1e-10, std::min(o.tol_kry, 0.1 * G));
         const int kcap = prec ? o.max_kry : std::max<int64_t>(o.max_kry, 2 * n1);
+        hipLaunchKernelGGL(k_kry_start, dim3(1), dim3(1), 0, st, ks, rtol, s_last);
         hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, sol.p, n1, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, rprev.p, n1, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d1.p, n1, 0.0);
         hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d2.p, n1, 0.0);
         hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, rhs.p, rcur.p, n1);
         precond(rcur.p, zcur.p);
-        double beta = std::sqrt(std::max(0.0, red.dot(rcur.p, zcur.p, n1, st)));
-        const double beta1 = beta;
-        double beta_prev = 0.0, c = -1.0, s = 0.0, dbar = 0.0, eps_next = 0.0, phibar = beta1;
         int kit = 0;
-        double* rp = rprev.p;
-        double* rc = rcur.p;
-        double* zc = zcur.p;
-        double* zo = zold.p;
-        double* pp = pv.p;
-        if (beta1 > 0.0) {
-            while (kit < kcap) {
-                ++kit;
-                // p = A (z / beta) - (beta / beta_prev) r_prev
-                hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
-                kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
-                ++matvecs;
-                const double ytz = red.dot(labels, zc, N, st);
-                const double cprev = kit > 1 ? beta / beta_prev : 0.0;
-                hipLaunchKernelGGL(k_newton_out, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N,
-                                   1.0 / beta, cprev, rp, -ytz, pp);
-                const double a = red.dot(zc, pp, n1, st) / beta;
-                hipLaunchKernelGGL(k_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, -a / beta);
-                // rotate r_prev <- r_cur <- p; z_old <- z_cur; z_cur <- M^{-1} r_cur
-                std::swap(rp, rc);
-                std::swap(rc, pp);
-                std::swap(zo, zc);
-                precond(rc, zc);
-                beta_prev = beta;
-                beta = std::sqrt(std::max(0.0, red.dot(rc, zc, n1, st)));
-                const double eps_cur = eps_next;
-                const double delta = c * dbar + s * a;
-                const double gbar = s * dbar - c * a;
-                eps_next = s * beta;
-                dbar = -c * beta;
-                double gam = std::hypot(gbar, beta);
-                if (gam == 0.0) gam = 1e-300;
-                c = gbar / gam;
-                s = beta / gam;
-                const double phi = c * phibar;
-                phibar = s * phibar;
-                hipLaunchKernelGGL(k_minres_update, dim3(nblk(n1)), dim3(kT), 0, st, zo, n1, 1.0 / beta_prev,
-                                   eps_cur, delta, 1.0 / gam, phi, d1.p, d2.p, sol.p);
-                if (!(phibar > rtol * beta1) || !(beta > 0.0)) break;
+        if (hook) {
+            // matvecs through a hook (shared launches of a server or grid): the
+            // host keeps the scalars and waits for each inner product
+            double beta = std::sqrt(std::max(0.0, red.dot(rcur.p, zcur.p, n1, st)));
+            const double beta1 = beta;
+            double beta_prev = 0.0, c = -1.0, s = 0.0, dbar = 0.0, eps_next = 0.0, phibar = beta1;
+            double* rp = rprev.p;
+            double* rc = rcur.p;
+            double* zc = zcur.p;
+            double* zo = zold.p;
+            double* pp = pv.p;
+            if (beta1 > 0.0) {
+                while (kit < kcap) {
+                    ++kit;
+                    // p = A (z / beta) - (beta / beta_prev) r_prev
+                    hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+                    kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
+                    ++matvecs;
+                    const double ytz = red.dot(labels, zc, N, st);
+                    const double cprev = kit > 1 ? beta / beta_prev : 0.0;
+                    hipLaunchKernelGGL(k_newton_out_v, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N,
+                                       1.0 / beta, cprev, rp, -ytz, pp);
+                    const double a = red.dot(zc, pp, n1, st) / beta;
+                    hipLaunchKernelGGL(k_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, -a / beta);
+                    // rotate r_prev <- r_cur <- p; z_old <- z_cur; z_cur <- M^{-1} r_cur
+                    std::swap(rp, rc);
+                    std::swap(rc, pp);
+                    std::swap(zo, zc);
+                    precond(rc, zc);
+                    beta_prev = beta;
+                    beta = std::sqrt(std::max(0.0, red.dot(rc, zc, n1, st)));
+                    const double eps_cur = eps_next;
+                    const double delta = c * dbar + s * a;
+                    const double gbar = s * dbar - c * a;
+                    eps_next = s * beta;
+                    dbar = -c * beta;
+                    double gam = hypot_ieee(gbar, beta);
+                    if (gam == 0.0) gam = 1e-300;
+                    c = gbar / gam;
+                    s = beta / gam;
+                    const double phi = c * phibar;
+                    phibar = s * phibar;
+                    hipLaunchKernelGGL(k_minres_update_v, dim3(nblk(n1)), dim3(kT), 0, st, zo, n1, 1.0 / beta_prev,
+                                       eps_cur, delta, 1.0 / gam, phi, d1.p, d2.p, sol.p);
+                    if (!(phibar > rtol * beta1) || !(beta > 0.0)) break;
+                }
             }
+        } else {
+            red.dot_dev(rcur.p, zcur.p, n1, &ks->dot_rz, st);
+            hipLaunchKernelGGL(k_kry_beta1, dim3(1), dim3(1), 0, st, ks);
+            // iteration j starts with r_prev, r, p = Rb[j], Rb[j + 1], Rb[j + 2] (mod 3) and
+            // z, z_old = Zb[j], Zb[j + 1] (mod 2): the buffers rotate with period 6
+            double* const Rb[3] = {rprev.p, rcur.p, pv.p};
+            double* const Zb[2] = {zcur.p, zold.p};
+            auto iteration = [&](int j) {
+                double* rp = Rb[j % 3];
+                double* rc = Rb[(j + 1) % 3];
+                double* pp = Rb[(j + 2) % 3];
+                double* zc = Zb[j % 2];
+                double* zo = Zb[(j + 1) % 2];
+                // p = A (z / beta) - (beta / beta_prev) r_prev; p -= (z^T p / beta^2) r
+                hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+                red.dot_dev(labels, zc, N, &ks->dot_ytz, st);
+                kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
+                hipLaunchKernelGGL(k_newton_out, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N, ks, rp,
+                                   pp);
+                red.dot_dev(zc, pp, n1, &ks->dot_a, st);
+                hipLaunchKernelGGL(k_kry_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, ks);
+                // p becomes the residual r; its preconditioned form goes to z_old's buffer
+                precond(pp, zo);
+                red.dot_dev(pp, zo, n1, &ks->dot_rz, st);
+                hipLaunchKernelGGL(k_kry_scalars, dim3(1), dim3(1), 0, st, ks);
+                hipLaunchKernelGGL(k_minres_update, dim3(nblk(n1)), dim3(kT), 0, st, zc, n1, ks, d1.p, d2.p, sol.p);
+            };
+            for (int j = 0; j < kcap; ++j) {
+                const int state = j % 6;
+                if (use_graphs && warmed) {
+                    if (!kr.g[state]) {
+                        // capture once per solve: every kernel argument is fixed for the solve
+                        hipGraph_t g = nullptr;
+                        ANV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                        try {
+                            iteration(state);
+                        } catch (...) {
+                            hipGraph_t tmp = nullptr;
+                            (void)hipStreamEndCapture(st, &tmp);
+                            if (tmp) (void)hipGraphDestroy(tmp);
+                            throw;
+                        }
+                        ANV_HIP(hipStreamEndCapture(st, &g));
+                        const hipError_t e = hipGraphInstantiate(&kr.g[state], g, nullptr, nullptr, 0);
+                        (void)hipGraphDestroy(g);
+                        ANV_HIP(e);
+                    }
+                    ANV_HIP(hipGraphLaunch(kr.g[state], st));
+                } else {
+                    iteration(j);
+                    warmed = true;
+                }
+                ++matvecs;
+                // the iteration's done flag, in stream order, to the host
+                ANV_HIP(hipMemcpyAsync(kr.hflag + (j & 1), &ks->done, sizeof(int), hipMemcpyDeviceToHost, st));
+                ANV_HIP(hipEventRecord(kr.fev[j & 1], st));
+                // the first iterations are checked at once (a well-preconditioned
+                // solve takes only a few); later ones one iteration late, so that
+                // the GPU always has the next iteration queued
+                if (j < kEagerChecks) {
+                    ANV_HIP(hipEventSynchronize(kr.fev[j & 1]));
+                    if (kr.hflag[j & 1]) break;
+                } else {
+                    ANV_HIP(hipEventSynchronize(kr.fev[(j - 1) & 1]));
+                    if (kr.hflag[(j - 1) & 1]) break;
+                }
+            }
+            ANV_HIP(hipMemcpyAsync(kr.hflag + 2, &ks->kit, sizeof(int), hipMemcpyDeviceToHost, st));
+            host_wait(st);
+            kit = kr.hflag[2];
         }
         kry_total += kit;
         kry_max = std::max(kry_max, kit);

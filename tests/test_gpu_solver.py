@@ -78,6 +78,16 @@ def test_ipm_small_plain_parity(dev):
     _check_solve(p, 1.0, dev)
 
 
+def test_ipm_small_plain_without_kernel_preconditioner(dev):
+    # the plain small problem with MINRES scaled by the barrier diagonal only
+    # (the block-diagonal preconditioner with no low-rank term): the same
+    # optimum as the dense-KKT oracle, to the same bar
+    import paper_2312_00538_amd as lib
+    p = workloads.small_plain(seed=0, N=2000, d=9)
+    a, lam, st = _check_solve(p, 1.0, dev, precond=lib.PRECOND_DIAG)
+    assert st["rank_used"] == 0
+
+
 @pytest.mark.parametrize("seed,N,C,sigma", [(1, 600, 10.0, 0.8), (2, 999, 0.5, 0.4)])
 def test_ipm_mixture_parity(dev, seed, N, C, sigma):
     p = workloads.gaussian_mixture(seed=seed, N=N, d=20, noise=0.1, sigma=sigma, C=C)
@@ -177,3 +187,28 @@ def test_ipm_automatic_initial_barrier_reaches_the_optimum(dev):
     d_svc = oracle.dual_objective(K, p.labels, a)
     d_gpu = oracle.dual_objective(K, p.labels, alpha.cpu().numpy())
     assert d_gpu == pytest.approx(d_svc, rel=1e-6)
+
+
+@pytest.mark.parametrize("precond", ["diag", "pchol", "nystrom"])
+def test_ipm_graph_replay_equals_kernel_launches(dev, precond):
+    # Each MINRES iteration is replayed from a captured HIP graph (many replays
+    # per solve, with eager work and host waits between them); the result must
+    # be bit-identical to launching the same kernels one by one, on every solve.
+    import paper_2312_00538_amd as lib
+    if precond == "diag":   # the small plain problem, which runs without a kernel preconditioner
+        p, C = workloads.small_plain(seed=0, N=800), 1.0
+    else:
+        p, C = workloads.gaussian_mixture(seed=4, N=1500, d=9, sigma=0.7, C=2.0, R=0), 2.0
+    pl = _plan(p, dev)
+    y = to_dev(p.labels, dev)
+    kw = dict(precond={"diag": lib.PRECOND_DIAG, "pchol": lib.PRECOND_PCHOL, "nystrom": lib.PRECOND_NYSTROM}[precond],
+              rank=100)
+    a0, l0, s0 = pl.solve(y, C, graphs=0, **kw)
+    for _ in range(2):
+        a1, l1, s1 = pl.solve(y, C, graphs=1, **kw)
+        print(precond, s0["ip_iters"], s0["kry_iters_total"], s1["kry_iters_total"], s0["t_solve_ms"], s1["t_solve_ms"])
+        assert s1["status"] == s0["status"] == 0
+        assert np.array_equal(a1.cpu().numpy(), a0.cpu().numpy())
+        assert l1 == l0
+        assert (s1["ip_iters"], s1["kry_iters_total"], s1["kry_iters_max"]) == \
+            (s0["ip_iters"], s0["kry_iters_total"], s0["kry_iters_max"])
