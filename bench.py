@@ -10,8 +10,10 @@ Y = sum_l K_l X over all windows for the 16 right-hand sides, inputs and
 outputs resident in HBM (column-major FP64). Headline: the batched
 mixed-precision path (FP32 weights, grids and matrix-core contractions, FP64
 window sums). The FP64 and mixed one-vector forms on the same GPU are reported
-beside it. Accuracy is checked every run on sampled rows against the FP64
-direct-sum oracle; a run above relative l2 error 1e-4 reports value 0.
+beside it. Accuracy: every run compares all rows and right-hand sides with
+the FP64 one-vector path on the GPU, and the oracle leg (the cpu_baseline
+measurement) checks the first right-hand side on the rows it samples; a run
+above relative l2 error 1e-4 reports value 0.
 
 Also reported: IPM solve latency p50/p99 for the small plain problem and the
 full N = 500000 problem; the request server (continuous batching against one
@@ -55,7 +57,6 @@ def parse():
                     help="timed steps of the one-vector FP64 and mixed forms (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--check-rows", type=int, default=128)
     ap.add_argument("--ipm-small-solves", type=int, default=20)
     ap.add_argument("--ipm-full-solves", type=int, default=5)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
@@ -96,10 +97,9 @@ def time_matvec(lib, torch, plan, xb, yb, N, R, steps, warmup):
     return el / steps, stages, passes
 
 
-def sampled_error(p, y_rows, rows, R):
-    import oracle
-    ref = oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, :R], rows=rows)
-    return max(float(np.linalg.norm(y_rows[:, r] - ref[:, r]) / np.linalg.norm(ref[:, r])) for r in range(R))
+def rel_err_cols(y, ref):
+    """max over columns of ||y - ref|| / ||ref|| (N x R host arrays)"""
+    return max(float(np.linalg.norm(y[:, r] - ref[:, r]) / np.linalg.norm(ref[:, r])) for r in range(y.shape[1]))
 
 
 def traffic_record():
@@ -239,23 +239,26 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves):
 def cpu_baseline(p, seconds):
     """The oracle (FP64 direct sum, C + OpenMP) on a bounded sample of target
     rows of the same workload (one right-hand side), scaled to
-    points*windows/s of a full matvec."""
+    points*windows/s of a full matvec. Also returns the sampled rows and the
+    oracle's values there, against which the GPU results are checked."""
     import oracle
     P = p.windows.shape[0]
     N = p.X.shape[0]
     order = np.random.default_rng(7).permutation(N)
     done, t0, chunk = 0, time.perf_counter(), 512
+    vals = []
     while True:
         rows = order[done:done + chunk]
-        oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, 0], rows=rows)
+        vals.append(oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, 0], rows=rows).reshape(-1))
         done += len(rows)
         el = time.perf_counter() - t0
         if el >= seconds or done >= N:
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done * P / el, "unit": "points*windows/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} of {N} target rows x all {N} sources x {P} windows, one right-hand side "
-                      f"(FP64 direct sum), {el:.1f} s; full-matvec rate = rows * windows / time"}
+    rec = {"value": done * P / el, "unit": "points*windows/s", "cores": threads, "kind": "oracle",
+           "sample": f"{done} of {N} target rows x all {N} sources x {P} windows, one right-hand side "
+                     f"(FP64 direct sum), {el:.1f} s; full-matvec rate = rows * windows / time"}
+    return rec, order[:done], np.concatenate(vals)
 
 
 def main():
@@ -284,8 +287,16 @@ def main():
     yb = torch.empty((R, N), dtype=torch.float64, device=dev)
     plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
     torch.cuda.synchronize()
-    rows = np.random.default_rng(123).choice(N, min(a.check_rows, N), replace=False)
-    rel_err = sampled_error(p, yb.cpu().numpy().T[rows], rows, R)
+    y_head = yb.cpu().numpy().T.copy()          # N x R, checked below
+    # accuracy against the FP64 GPU path (one vector per pass, all rows and
+    # columns); the FP64 path's own accuracy against the oracle is what the
+    # parity tests establish, and the oracle leg below checks a sample again
+    plr = lib.Plan(X, p.windows, p.sigma, precision=lib.PREC_FP64, batch_min_rhs=-1)
+    yr = torch.empty((R, N), dtype=torch.float64, device=dev)
+    plr.matvec_raw(xb.data_ptr(), R, N, yr.data_ptr(), N)
+    torch.cuda.synchronize()
+    rel_err = rel_err_cols(y_head, yr.cpu().numpy().T)
+    del plr, yr
 
     t_step, stages, passes = time_matvec(lib, torch, plan, xb, yb, N, R, a.steps, a.warmup)
     value = N * P * R / t_step
@@ -341,7 +352,7 @@ def main():
                    "N": N, "d": d, "windows": P, "rhs": R,
                    "precision": "mixed (FP32 spread/grid/gather, FP64 window sums)" if prec else "fp64",
                    "path": "batched 16-wide" if batched else "one vector per pass"},
-        "rel_err_sampled": rel_err,
+        "rel_err_vs_fp64_path": rel_err,
         "stage_ms_per_pass": per_pass,
         "passes_per_step": npass,
         "plan_ms": 1e3 * t_plan,
@@ -350,10 +361,11 @@ def main():
     }
     if rel_err > 1e-4:
         out["value"] = 0.0
-        out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4"
+        out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4 against the FP64 path"
     del plan, xb, yb
 
     # the one-vector forms on the same GPU at the same accuracy bar
+    one_vec = {}
     if a.reference_steps > 0:
         refs = {}
         for name, pr in (("fp64_1rhs", lib.PREC_FP64), ("mixed_1rhs", lib.PREC_MIXED)):
@@ -362,10 +374,9 @@ def main():
             y1 = torch.empty((1, N), dtype=torch.float64, device=dev)
             pl.matvec_raw(x1.data_ptr(), 1, N, y1.data_ptr(), N)
             torch.cuda.synchronize()
-            e1 = sampled_error(p, y1.cpu().numpy().T[rows], rows, 1)
+            one_vec[name] = y1.cpu().numpy().reshape(-1).copy()
             t1, st1, _ = time_matvec(lib, torch, pl, x1, y1, N, 1, a.reference_steps, 3)
-            refs[name] = {"value": N * P / t1, "ms_per_step": 1e3 * t1, "rel_err_sampled": e1,
-                          "stage_ms": st1}
+            refs[name] = {"value": N * P / t1, "ms_per_step": 1e3 * t1, "stage_ms": st1}
             del pl
         out["reference"] = refs
 
@@ -391,7 +402,16 @@ def main():
     if a.grid_folds > 0:
         out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, a.cpu_seconds)
+        rec, rows, ref = cpu_baseline(p, a.cpu_seconds)
+        out["cpu_baseline"] = rec
+        # the GPU results on the oracle's sampled rows (first right-hand side)
+        err = {"headline": float(np.linalg.norm(y_head[rows, 0] - ref) / np.linalg.norm(ref))}
+        for name, y1 in one_vec.items():
+            err[name] = float(np.linalg.norm(y1[rows] - ref) / np.linalg.norm(ref))
+        out["rel_err_oracle_sampled"] = {"rows": int(len(rows)), "rhs": 1, **err}
+        if err["headline"] > 1e-4:
+            out["value"] = 0.0
+            out["error"] = f"accuracy bar missed: rel_err {err['headline']:.3e} > 1e-4 against the oracle"
     if a.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
