@@ -364,6 +364,49 @@ typedef struct {
 int anova_grid_solve(const anova_grid_problem* problems, int32_t n_problems, const anova_ipm_opts* opts,
                      int32_t max_active, double gather_us, int64_t* launches, int64_t* matvecs);
 
+/* ---- Autotuner -------------------------------------------------------------
+ * Chooses the fast-summation options for one data set and kernel widths: the
+ * bandwidth N and cutoff m (Section 3 leaves both to the user: the error of
+ * the NFFT-based sum falls and its cost grows with each), the precision and the
+ * number of points per spreading work item. Every candidate plan multiplies a
+ * seeded random block of `rhs` columns; its relative l2 error is measured
+ * against an FP64 plan with bandwidth 64 and cutoff 4 (bandwidth 32 when the
+ * data's occupied grid box does not fit), and the candidates within the target
+ * are timed on `stream` (HIP events, `reps` calls each after one warm-up). The
+ * fastest wins; a second pass tries two other work-item sizes for it.
+ * Candidates: cutoff 2, 3, 4 x bandwidth 16, 24, 32, 48, 64 for each selected
+ * precision. */
+#define ANOVA_TUNE_OPTS_VERSION 1
+typedef struct {
+    int32_t  version;         /* ANOVA_TUNE_OPTS_VERSION                              */
+    int32_t  rhs;             /* right-hand sides per timed matvec call, 1..64        */
+    double   target_rel_err;  /* admissible relative l2 error (> 0)                   */
+    int32_t  precisions;      /* bit 0: FP64 candidates, bit 1: mixed-precision ones   */
+    int32_t  reps;            /* timed calls per admissible candidate, 1..100         */
+    uint64_t seed;            /* the random test block                                */
+} anova_tune_opts;
+
+typedef struct {
+    int32_t n_bw, cutoff_m, precision, seg_points;
+    double  rel_err;          /* against the reference plan; < 0: the data set cannot
+                                 use this size (the plan could not be built)          */
+    double  ms;               /* mean time per call; < 0: not timed (error too large) */
+} anova_tune_candidate;
+
+/* rhs = 1, target_rel_err = 1e-4, both precisions, reps = 3, seed = 0. */
+int anova_tune_opts_default(anova_tune_opts* t);
+
+/* Run the search. Inputs as for anova_plan_create (X device; windows, sigma,
+ * eta host); t host or NULL (defaults); best (host out) receives complete plan
+ * options (defaults for the fields not searched). cands (host, may be NULL)
+ * receives up to max_cands candidates in the order tried, *n_cands (host, may
+ * be NULL) the number tried. Synchronises `stream`. Errors: ANOVA_INVALID_ARG,
+ * ANOVA_NOT_CONVERGED (no candidate within the target; cands still filled),
+ * ANOVA_OUT_OF_MEMORY, ANOVA_HIP_ERROR. */
+int anova_autotune(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows, int32_t P,
+                   const double* sigma, const double* eta, const anova_tune_opts* t, void* stream,
+                   anova_opts* best, anova_tune_candidate* cands, int32_t max_cands, int32_t* n_cands);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* anova_last_error(void);
 

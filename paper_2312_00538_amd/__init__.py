@@ -26,6 +26,7 @@ EXPORTED = [
     "anova_nystrom", "anova_last_error", "anova_profile_begin", "anova_profile_end",
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
+    "anova_tune_opts_default", "anova_autotune",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -87,6 +88,16 @@ class GridProblem(ctypes.Structure):
                 ("lambda_", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("rhs", ctypes.c_int32), ("target_rel_err", ctypes.c_double),
+                ("precisions", ctypes.c_int32), ("reps", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class TuneCandidate(ctypes.Structure):
+    _fields_ = [("n_bw", ctypes.c_int32), ("cutoff_m", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("seg_points", ctypes.c_int32), ("rel_err", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
 class ServerResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("footprint", ctypes.c_int64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double), ("latency_ms", ctypes.c_double),
@@ -131,6 +142,9 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(i64)], ctypes.c_int),
         "anova_grid_solve": ([ctypes.POINTER(GridProblem), i32, ctypes.POINTER(IpmOpts), i32, dbl,
                               ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+        "anova_tune_opts_default": ([ctypes.POINTER(TuneOpts)], ctypes.c_int),
+        "anova_autotune": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(TuneOpts), P, ctypes.POINTER(Opts),
+                            ctypes.POINTER(TuneCandidate), i32, ctypes.POINTER(i32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -303,6 +317,40 @@ def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: Ipm
     _check(lib.anova_request_footprint(int(N), int(d), int(P), ctypes.byref(nfft) if nfft else None,
                                        ctypes.byref(ipm) if ipm else None, ctypes.byref(b)))
     return b.value
+
+
+def autotune(X, windows, sigma, eta=None, target_rel_err: float = 1e-4, rhs: int = 1,
+             precisions=("fp64", "mixed"), reps: int = 3, seed: int = 0, stream=None):
+    """Choose the fast-summation options for this data set (anova_autotune).
+    Returns (Opts, candidates, chosen index); candidates are dicts with n_bw,
+    cutoff_m, precision, seg_points, rel_err (< 0: size not usable) and ms
+    (< 0: not timed). Raises AnovaError(NOT_CONVERGED) when nothing reaches
+    the target."""
+    lib = load_library()
+    X = _dev_f64(X, "X")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D row-major tensor")
+    N, d = int(X.shape[0]), int(X.shape[1])
+    win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 3))
+    Pw = int(win.shape[0])
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (Pw,)))
+    et = None if eta is None else np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float64), (Pw,)))
+    t = TuneOpts()
+    _check(lib.anova_tune_opts_default(ctypes.byref(t)))
+    t.rhs, t.target_rel_err, t.reps, t.seed = int(rhs), float(target_rel_err), int(reps), int(seed)
+    t.precisions = (1 if "fp64" in precisions else 0) | (2 if "mixed" in precisions else 0)
+    best = Opts()
+    cands = (TuneCandidate * 64)()
+    n = ctypes.c_int32(0)
+    rc = lib.anova_autotune(ctypes.c_void_p(X.data_ptr()), N, d, X.stride(0), win.ctypes.data_as(ctypes.c_void_p),
+                            Pw, sig.ctypes.data_as(ctypes.c_void_p),
+                            et.ctypes.data_as(ctypes.c_void_p) if et is not None else None, ctypes.byref(t),
+                            _stream(stream), ctypes.byref(best), cands, 64, ctypes.byref(n))
+    out = [{f[0]: getattr(cands[i], f[0]) for f in TuneCandidate._fields_} for i in range(min(n.value, 64))]
+    _check(rc)
+    chosen = next(i for i, c in enumerate(out) if c["n_bw"] == best.n_bw and c["cutoff_m"] == best.cutoff_m
+                  and c["precision"] == best.precision and c["seg_points"] == best.seg_points)
+    return best, out, chosen
 
 
 def grid_solve(problems, opts: IpmOpts | None = None, max_active: int = 64, gather_us: float = 200.0,

@@ -8,6 +8,7 @@
 #include "plan.hpp"
 #include "server.hpp"
 #include "solver.hpp"
+#include "tune.hpp"
 
 namespace anv {
 static thread_local std::string g_last_error;
@@ -289,6 +290,36 @@ int anova_grid_solve(const anova_grid_problem* problems, int32_t n_problems, con
         int device = 0;
         ANV_HIP(hipGetDevice(&device));
         anv::grid_solve(g.data(), n_problems, o, max_active, gather_us, device, launches, matvecs);
+        return ANOVA_OK;
+    });
+}
+
+int anova_tune_opts_default(anova_tune_opts* t) {
+    if (!t) return ANOVA_INVALID_ARG;
+    std::memset(t, 0, sizeof(*t));
+    t->version = ANOVA_TUNE_OPTS_VERSION;
+    t->rhs = 1;
+    t->target_rel_err = 1e-4;
+    t->precisions = 3;
+    t->reps = 3;
+    t->seed = 0;
+    return ANOVA_OK;
+}
+
+int anova_autotune(const double* X, int64_t N, int32_t d, int64_t ldx, const int32_t* windows, int32_t P,
+                   const double* sigma, const double* eta, const anova_tune_opts* t, void* stream,
+                   anova_opts* best, anova_tune_candidate* cands, int32_t max_cands, int32_t* n_cands) {
+    return guarded([&] {
+        ANV_CHECK(best != nullptr, "NULL output");
+        ANV_CHECK(cands == nullptr || max_cands >= 0, "max_cands < 0");
+        anova_tune_opts o;
+        anova_tune_opts_default(&o);
+        if (t) {
+            ANV_CHECK(t->version == ANOVA_TUNE_OPTS_VERSION, "anova_tune_opts.version mismatch");
+            o = *t;
+        }
+        anv::autotune(X, N, d, ldx, windows, P, sigma, eta, o, static_cast<hipStream_t>(stream), best, cands,
+                      max_cands, n_cands);
         return ANOVA_OK;
     });
 }

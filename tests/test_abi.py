@@ -106,3 +106,21 @@ def test_grid_solve_rejects_bad_arguments(L):
     o = lib.default_ipm_opts()
     o.version = 99
     assert L.anova_grid_solve(probs, 1, ctypes.byref(o), 8, 200.0, None, None) == lib.INVALID_ARG
+
+
+def test_autotune_options_and_argument_checks(L):
+    t = lib.TuneOpts()
+    assert L.anova_tune_opts_default(ctypes.byref(t)) == lib.OK
+    assert (t.rhs, t.target_rel_err, t.precisions, t.reps) == (1, 1e-4, 3, 3)
+    best = lib.Opts()
+    fake = ctypes.c_void_p(0x1000)
+    import numpy as np
+    win = np.array([[0, 1, 2]], dtype=np.int32)
+    sig = np.array([1.0])
+    args = (fake, 10, 3, 3, win.ctypes.data_as(ctypes.c_void_p), 1, sig.ctypes.data_as(ctypes.c_void_p), None)
+    assert L.anova_autotune(*args, None, None, None, None, 0, None) == lib.INVALID_ARG   # NULL best
+    t.version = 99
+    assert L.anova_autotune(*args, ctypes.byref(t), None, ctypes.byref(best), None, 0, None) == lib.INVALID_ARG
+    t.version = lib.TuneOpts().version or 1
+    t.rhs = 0
+    assert L.anova_autotune(*args, ctypes.byref(t), None, ctypes.byref(best), None, 0, None) == lib.INVALID_ARG
