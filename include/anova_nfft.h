@@ -43,6 +43,9 @@ extern "C" {
 #define ANOVA_PRECOND_NONE     0  /* unpreconditioned MINRES                           */
 #define ANOVA_PRECOND_PCHOL    1  /* greedy pivoted Cholesky, Algorithm 2 (Section 4)   */
 #define ANOVA_PRECOND_NYSTROM  2  /* randomized Nystrom, Q = orth(K G) (Section 4)      */
+#define ANOVA_PRECOND_RPCHOL   4  /* randomly pivoted Cholesky (Section 4 cites it as
+                                     the random-pivot variant of Algorithm 2); pivot
+                                     draws from anova_ipm_opts.seed                  */
 #define ANOVA_PRECOND_DIAG     3  /* the block-diagonal preconditioner of Section 5
                                      with no low-rank term: diag(Theta, y^T Theta^{-1} y),
                                      the barrier diagonal only (no approximation of K) */
@@ -226,6 +229,16 @@ int svm_ipm_solve(anova_plan_t plan, const double* labels, double C,
 int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol,
                            double* L, int64_t ldl, int64_t* piv, int32_t* rank_used,
                            void* stream);
+
+/* Randomly pivoted Cholesky of the plan's kernel: Algorithm 2 with the pivot
+ * of step j drawn with probability proportional to the residual diagonal.
+ * With C_i = sum_{t <= i} max(d_t, 0) over the residual diagonal d, step j
+ * takes the smallest i with C_i > uniforms[j] * C_{N-1}.
+ *   uniforms host, rank FP64 values in [0, 1) (the draws, supplied by the
+ *            caller so that results are reproducible and checkable).
+ * Other arguments, outputs and errors as for anova_pivoted_cholesky. */
+int anova_rp_cholesky(anova_plan_t plan, int32_t rank, double err_tol, const double* uniforms,
+                      double* L, int64_t ldl, int64_t* piv, int32_t* rank_used, void* stream);
 
 /* Randomized Nystrom factor (Section 4): Q = orth(K G) and
  * K ~= (KQ)(Q^T K Q)^{-1}(KQ)^T = Z^T Z, with Q^T K Q = L D L^T and diagonal

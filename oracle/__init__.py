@@ -243,6 +243,42 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
 
 # ----------------------------------------------------------------------------- Algorithm 2
 
+def rp_cholesky(K, u, err_tol=0.0):
+    """Randomly pivoted Cholesky: Algorithm 2 (Section 4) with the pivot of step j
+    drawn with probability proportional to the residual diagonal, the variant
+    Section 4 cites beside the greedy rule. With the clamped residual diagonal
+    d+ = max(d, 0), its running sums C and total T, step j takes the smallest i
+    with C_i > u[j] * T. The column of the pivot p is K[:, p] - L L[p]^T over the
+    steps so far, scaled by 1 / sqrt(K_pp - |L[p]|^2); then d -= column^2 and
+    d_p = 0. Stops when T = 0, when T <= err_tol * trace(K), or when the pivot
+    value is not positive. Returns (L, piv) with L N x r in the original row
+    order and the pivots in the order chosen."""
+    K = np.asarray(K, dtype=np.float64)
+    n = K.shape[0]
+    u = np.asarray(u, dtype=np.float64)
+    L = np.zeros((n, len(u)))
+    d = np.diag(K).copy()
+    trace0 = float(d.sum())
+    piv = []
+    for j in range(len(u)):
+        dp = np.maximum(d, 0.0)
+        total = float(dp.sum())
+        if not total > 0.0:
+            break
+        if err_tol > 0.0 and total <= err_tol * trace0:
+            break
+        p = int(np.argmax(np.cumsum(dp) > u[j] * total))
+        pivval = K[p, p] - float(L[p, :j] @ L[p, :j])
+        if not (d[p] > 0.0 and pivval > 0.0):
+            break
+        col = (K[:, p] - L[:, :j] @ L[p, :j]) / np.sqrt(pivval)
+        L[:, j] = col
+        d = d - col * col
+        d[p] = 0.0
+        piv.append(p)
+    return L[:, :len(piv)], np.array(piv, dtype=np.int64)
+
+
 def pivoted_cholesky(K, k, err_tol=0.0):
     """Greedy pivoted Cholesky of rank <= k (Algorithm 2, Section 4) on a copy of
     the dense K: at step j pick the largest remaining diagonal entry (lowest

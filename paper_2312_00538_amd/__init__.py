@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libanova_nfft.so")
 
 OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, NUMERICAL = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
-PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG, PRECOND_RPCHOL = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "anova_opts_default", "anova_plan_create", "anova_matvec", "anova_plan_destroy",
@@ -26,7 +26,7 @@ EXPORTED = [
     "anova_nystrom", "anova_last_error", "anova_profile_begin", "anova_profile_end",
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
-    "anova_tune_opts_default", "anova_autotune",
+    "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -143,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "anova_grid_solve": ([ctypes.POINTER(GridProblem), i32, ctypes.POINTER(IpmOpts), i32, dbl,
                               ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "anova_tune_opts_default": ([ctypes.POINTER(TuneOpts)], ctypes.c_int),
+        "anova_rp_cholesky": ([P, i32, dbl, P, P, i64, P, ctypes.POINTER(i32), P], ctypes.c_int),
         "anova_autotune": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(TuneOpts), P, ctypes.POINTER(Opts),
                             ctypes.POINTER(TuneCandidate), i32, ctypes.POINTER(i32)], ctypes.c_int),
     }
@@ -285,6 +286,20 @@ class Plan:
         _check(_lib.anova_pivoted_cholesky(self._h, rank, float(err_tol), ctypes.c_void_p(L.data_ptr()),
                                            self.N, piv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(used),
                                            _stream(stream)))
+        r = used.value
+        return L[:r].t(), piv[:r]
+
+    def rp_cholesky(self, uniforms, err_tol: float = 0.0, stream=None):
+        """Randomly pivoted Cholesky with the given draws (one per step, in [0, 1))."""
+        import torch
+        u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1))
+        rank = int(u.shape[0])
+        L = torch.empty((rank, self.N), dtype=torch.float64, device=self.device)
+        piv = np.zeros(rank, dtype=np.int64)
+        used = ctypes.c_int32(0)
+        _check(_lib.anova_rp_cholesky(self._h, rank, float(err_tol), u.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.c_void_p(L.data_ptr()), self.N, piv.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(used), _stream(stream)))
         r = used.value
         return L[:r].t(), piv[:r]
 

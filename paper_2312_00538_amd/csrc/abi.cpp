@@ -180,6 +180,22 @@ int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol, doub
     });
 }
 
+int anova_rp_cholesky(anova_plan_t plan, int32_t rank, double err_tol, const double* uniforms, double* L,
+                      int64_t ldl, int64_t* piv, int32_t* rank_used, void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(L && piv && rank_used && uniforms, "NULL argument");
+        ANV_CHECK(rank >= 1 && rank <= plan->p->N, "rank must be in [1, N]");
+        ANV_CHECK(ldl >= plan->p->N, "ldl < N");
+        ANV_CHECK(err_tol >= 0.0, "err_tol < 0");
+        for (int32_t j = 0; j < rank; ++j)
+            ANV_CHECK(uniforms[j] >= 0.0 && uniforms[j] < 1.0, "uniforms must lie in [0, 1)");
+        *rank_used = anv::pivoted_cholesky(*plan->p, rank, err_tol, L, ldl, piv, static_cast<hipStream_t>(stream),
+                                           uniforms);
+        return ANOVA_OK;
+    });
+}
+
 int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg, double* Zt, int64_t ldz,
                   void* stream) {
     return guarded([&] {

@@ -324,7 +324,8 @@ int64_t request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts& nff
     b += pw * (24 + 12 + 3 * W * eb + 16 + 8 * eb);                  // plan per point-window
     b += int64_t(P) * E * E * E * (W * W + 4) * eb;                  // grids and fold target
     b += 18 * (N + 1) * 8;                                           // IPM vectors
-    const int64_t k = (ipm.precond == ANOVA_PRECOND_PCHOL || ipm.precond == ANOVA_PRECOND_NYSTROM) ? ipm.rank : 0;
+    const int64_t k = (ipm.precond == ANOVA_PRECOND_PCHOL || ipm.precond == ANOVA_PRECOND_NYSTROM ||
+                       ipm.precond == ANOVA_PRECOND_RPCHOL) ? ipm.rank : 0;
     b += (ipm.precond == ANOVA_PRECOND_NYSTROM ? 4 : 2) * N * k * 8;  // factor and its build
     b += 260 * k * k * 8;                                            // capacitance partial sums
     return b + b / 4;                                                // margin

@@ -98,6 +98,51 @@ __global__ void k_pchol_column(const double* __restrict__ xw, int64_t N, int32_t
     dres[i] = (i == p) ? 0.0 : dn;
 }
 
+// Randomly pivoted Cholesky (Section 4 names it beside the greedy rule): the
+// pivot is drawn with probability proportional to the residual diagonal. With
+// C_i = sum_{t <= i} max(d_t, 0) and a uniform u in [0, 1), the pivot is the
+// smallest i with C_i > u C_{N-1}. Block b sums [b chunk, (b + 1) chunk).
+__global__ void k_block_sums(const double* __restrict__ d, int64_t n, int64_t chunk, double* __restrict__ psum) {
+    __shared__ double ss[kT];
+    const int64_t i0 = int64_t(blockIdx.x) * chunk, i1 = std::min<int64_t>(n, i0 + chunk);
+    double s = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kT) s += fmax(d[i], 0.0);
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = kT / 2; k > 0; k >>= 1) {
+        if (int(threadIdx.x) < k) ss[threadIdx.x] += ss[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) psum[blockIdx.x] = ss[0];
+}
+
+// one thread: out = {d[pivot], pivot, total}; the block whose range holds the
+// crossing is found from the block sums, then its elements are walked in order
+__global__ void k_sample_pivot(const double* __restrict__ d, int64_t n, int64_t chunk,
+                               const double* __restrict__ psum, int nb, double u, double* __restrict__ out) {
+    double total = 0.0;
+    for (int b = 0; b < nb; ++b) total += psum[b];
+    const double target = u * total;
+    double acc = 0.0;
+    int b = 0;
+    while (b + 1 < nb && acc + psum[b] <= target) acc += psum[b++];
+    int64_t i = int64_t(b) * chunk, pick = -1, last = -1;
+    const int64_t i1 = std::min<int64_t>(n, i + chunk);
+    for (; i < i1; ++i) {
+        const double v = fmax(d[i], 0.0);
+        if (v > 0.0) last = i;
+        acc += v;
+        if (acc > target && v > 0.0) {
+            pick = i;
+            break;
+        }
+    }
+    if (pick < 0) pick = last >= 0 ? last : 0;  // rounding at the end of the range
+    out[0] = d[pick];
+    out[1] = double(pick);
+    out[2] = total;
+}
+
 // residual diagonal of the pivot: K_pp - sum_j L_pj^2 (one thread)
 __global__ void k_pivot_value(const double* __restrict__ L, int64_t N, int64_t p, int r, double kpp,
                               double* __restrict__ out) {
@@ -618,7 +663,23 @@ __global__ void k_step(double* __restrict__ a, const double* __restrict__ da, in
 // kyz = K (y * z[0:N]) already computed; p[N] gets -y^T z[0:N] * sc - cprev*rprev[N]
 // from the host-provided dot value.
 // preconditioners with a low-rank factor of K (the others need none)
-inline bool low_rank_precond(int p) { return p == ANOVA_PRECOND_PCHOL || p == ANOVA_PRECOND_NYSTROM; }
+inline bool low_rank_precond(int p) {
+    return p == ANOVA_PRECOND_PCHOL || p == ANOVA_PRECOND_NYSTROM || p == ANOVA_PRECOND_RPCHOL;
+}
+
+// uniforms in [0, 1) for randomly pivoted Cholesky: splitmix64 (Steele, Lea and
+// Flood 2014) of seed + j, top 53 bits
+std::vector<double> pivot_uniforms(uint64_t seed, int n) {
+    std::vector<double> u(static_cast<size_t>(n));
+    for (int j = 0; j < n; ++j) {
+        uint64_t z = seed + uint64_t(j) + 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        u[size_t(j)] = double(z >> 11) * 0x1.0p-53;
+    }
+    return u;
+}
 
 // MINRES iterations whose convergence flag the host reads before queueing the next
 constexpr int kEagerChecks = 4;
@@ -975,7 +1036,10 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
 }
 
 // greedy pivoted Cholesky into a column-major N x ldl buffer; returns rank
-int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st) {
+// greedy pivoted Cholesky (uniforms == NULL) or randomly pivoted Cholesky with
+// one uniform per step (host array of `rank` values in [0, 1))
+int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st,
+               const double* uniforms = nullptr) {
     const int64_t N = pl.N;
     const int P = pl.P;
     ANV_CHECK(ldl == N, "internal: pivoted Cholesky storage must have ldl == N");
@@ -1006,8 +1070,16 @@ int pchol_into(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64
     int r = 0;
     try {
         for (; r < rank; ++r) {
-            hipLaunchKernelGGL(k_argmax_sum, dim3(nb), dim3(kT), 0, st, dres.p, N, pv.p, pi.p, ps.p);
-            hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, pv.p, pi.p, ps.p, int(nb), fin.p);
+            if (uniforms) {
+                const int64_t chunk = (N + nb - 1) / nb;
+                const unsigned nbs = unsigned((N + chunk - 1) / chunk);
+                hipLaunchKernelGGL(k_block_sums, dim3(nbs), dim3(kT), 0, st, dres.p, N, chunk, ps.p);
+                hipLaunchKernelGGL(k_sample_pivot, dim3(1), dim3(1), 0, st, dres.p, N, chunk, ps.p, int(nbs),
+                                   uniforms[r], fin.p);
+            } else {
+                hipLaunchKernelGGL(k_argmax_sum, dim3(nb), dim3(kT), 0, st, dres.p, N, pv.p, pi.p, ps.p);
+                hipLaunchKernelGGL(k_argmax_final, dim3(1), dim3(64), 0, st, pv.p, pi.p, ps.p, int(nb), fin.p);
+            }
             ANV_HIP(hipMemcpyAsync(hfin, fin.p, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
             host_wait(st);
             const double best = hfin[0], rest = hfin[2];
@@ -1184,11 +1256,12 @@ void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st
 
 }  // namespace
 
-int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st) {
-    if (ldl == pl.N) return pchol_into(pl, rank, err_tol, L, ldl, piv, st);
+int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st,
+                     const double* uniforms) {
+    if (ldl == pl.N) return pchol_into(pl, rank, err_tol, L, ldl, piv, st, uniforms);
     DevBuf<double> tmp;
     tmp.alloc(size_t(pl.N) * rank);
-    int r = pchol_into(pl, rank, err_tol, tmp.p, pl.N, piv, st);
+    int r = pchol_into(pl, rank, err_tol, tmp.p, pl.N, piv, st, uniforms);
     if (r > 0)
         ANV_HIP(hipMemcpy2DAsync(L, ldl * sizeof(double), tmp.p, pl.N * sizeof(double), pl.N * sizeof(double), r,
                                  hipMemcpyDeviceToDevice, st));
@@ -1222,17 +1295,20 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
     using clk = std::chrono::steady_clock;
     const int64_t N = pl.N;
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
-                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG,
+                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG ||
+                  o.precond == ANOVA_PRECOND_RPCHOL,
               "unknown preconditioner");
     ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");
     const auto t0 = clk::now();
     f.precond = o.precond;
     f.rank = 0;
-    if (o.precond == ANOVA_PRECOND_PCHOL) {
+    if (o.precond == ANOVA_PRECOND_PCHOL || o.precond == ANOVA_PRECOND_RPCHOL) {
         f.Z.alloc(size_t(N) * o.rank);
         std::vector<int64_t> piv(o.rank);
-        f.rank = pchol_into(pl, o.rank, o.err_tol, f.Z.p, N, piv.data(), st);
+        std::vector<double> u;
+        if (o.precond == ANOVA_PRECOND_RPCHOL) u = pivot_uniforms(o.seed, o.rank);
+        f.rank = pchol_into(pl, o.rank, o.err_tol, f.Z.p, N, piv.data(), st, u.empty() ? nullptr : u.data());
     } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
         f.rank = o.rank;
         f.Z.alloc(size_t(N) * o.rank);
@@ -1262,7 +1338,8 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
               "tolerances must be > 0 and mu0 finite");
     ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
-                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG,
+                  o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG ||
+                  o.precond == ANOVA_PRECOND_RPCHOL,
               "unknown preconditioner");
     ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");

@@ -31,8 +31,10 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
               const MatvecHook* hook = nullptr);
 
 // returns the rank used
+// uniforms: NULL for the greedy rule (Algorithm 2), else one value in [0, 1)
+// per step for randomly pivoted Cholesky
 int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv,
-                     hipStream_t st);
+                     hipStream_t st, const double* uniforms = nullptr);
 
 void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, int64_t ldz,
                     hipStream_t st);

@@ -212,3 +212,23 @@ def test_ipm_graph_replay_equals_kernel_launches(dev, precond):
         assert l1 == l0
         assert (s1["ip_iters"], s1["kry_iters_total"], s1["kry_iters_max"]) == \
             (s0["ip_iters"], s0["kry_iters_total"], s0["kry_iters_max"])
+
+
+def test_rp_cholesky_matches_oracle(dev):
+    # the same draws on both sides: identical pivots, L to 1e-9
+    p = workloads.gaussian_mixture(seed=3, N=300, d=9, sigma=0.3)
+    pl = _plan(p, dev)
+    u = np.random.default_rng(5).uniform(size=40)
+    L, piv = pl.rp_cholesky(u)
+    K = oracle.anova_dense(p.X, p.windows, p.sigma)
+    Lo, pivo = oracle.rp_cholesky(K, u)
+    print("pivots gpu", piv[:10], "oracle", pivo[:10])
+    assert list(piv) == list(pivo)
+    assert np.allclose(L.cpu().numpy(), Lo, rtol=1e-9, atol=1e-11)
+
+
+def test_ipm_randomly_pivoted_cholesky_preconditioner(dev):
+    import paper_2312_00538_amd as lib
+    p = workloads.gaussian_mixture(seed=1, N=600, d=20, noise=0.1, sigma=0.8, C=10.0)
+    a, lam, st = _check_solve(p, 10.0, dev, rank=100, precond=lib.PRECOND_RPCHOL, seed=3)
+    assert st["kry_iters_max"] <= 20

@@ -268,3 +268,35 @@ def test_saddle_point_preconditioner_spectra():
     evd = np.linalg.eigvals(np.linalg.solve(Pd, A)).real
     targets = np.array([1.0, (1 + 5 ** 0.5) / 2, (1 - 5 ** 0.5) / 2])
     assert np.all(np.min(np.abs(evd[:, None] - targets[None, :]), axis=1) < 1e-8)
+
+
+def test_rp_cholesky_full_rank_reproduces_k():
+    # rank N: every diagonal entry becomes a pivot and L L^T = K whatever the draws
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((7, 7))
+    K = A @ A.T + 0.1 * np.eye(7)
+    u = rng.uniform(size=7)
+    L, piv = oracle.rp_cholesky(K, u)
+    assert sorted(piv.tolist()) == list(range(7))
+    assert np.allclose(L @ L.T, K, atol=1e-12, rtol=1e-12)
+
+
+def test_rp_cholesky_draws_on_the_identity():
+    # K = I: the remaining indices all carry weight 1, so draw u picks the
+    # floor(u * m)-th remaining index (0-based) among the m left
+    u = np.array([0.95, 0.0, 0.5, 0.34, 0.99, 0.2])
+    L, piv = oracle.rp_cholesky(np.eye(6), u)
+    left, expect = list(range(6)), []
+    for x in u:
+        q = left[int(np.floor(x * len(left)))]
+        expect.append(q)
+        left.remove(q)
+    assert piv.tolist() == expect
+    assert np.allclose(np.abs(L[piv, range(6)]), 1.0)
+
+
+def test_rp_cholesky_zero_draw_takes_the_first_positive_diagonal():
+    K = np.diag([0.0, 0.0, 2.0, 3.0])
+    L, piv = oracle.rp_cholesky(K, [0.0, 0.0])
+    assert piv.tolist() == [2, 3]
+    assert np.allclose(L[:, 0], [0, 0, np.sqrt(2.0), 0])
