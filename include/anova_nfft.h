@@ -340,6 +340,23 @@ int anova_server_destroy(anova_server_t s);
 int anova_request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts* nfft,
                             const anova_ipm_opts* ipm, int64_t* bytes);
 
+/* Decision values of a trained SVM at M new points (Section 2: the classifier
+ * is f(x) = sum_j alpha_j y_j k(x, x_j) - lambda): the kernel sum with targets
+ * other than its sources. One plan is built over the union of the training
+ * and the new points, so that one torus map covers both, and one matvec of
+ * [y * alpha ; 0] gives f at the new points.
+ *   X       device, N x d FP64 training points, row i at X + i*ldx (ldx >= d).
+ *   Xnew    device, M x d FP64 new points, row j at Xnew + j*ldn (ldn >= d).
+ *   windows, P, sigma, eta, opts  as for anova_plan_create (the training plan's).
+ *   labels, alpha  device, N FP64: the training labels and svm_ipm_solve's alpha.
+ *   lambda  svm_ipm_solve's lambda.
+ *   f       device, M FP64 output.
+ * Synchronises `stream`. Errors as for anova_plan_create; ANOVA_OUT_OF_MEMORY. */
+int anova_decision_function(const double* X, int64_t N, int64_t ldx, const double* Xnew, int64_t M,
+                            int64_t ldn, int32_t d, const int32_t* windows, int32_t P, const double* sigma,
+                            const double* eta, const anova_opts* opts, const double* labels,
+                            const double* alpha, double lambda, double* f, void* stream);
+
 /* ---- Hyperparameter grid -------------------------------------------------
  * Parameter search (Section 6.3 selects sigma and C by a search over
  * parameter combinations): many IPM solves that differ in the data (folds),

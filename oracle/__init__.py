@@ -129,6 +129,25 @@ def anova_dense(X, windows, sigma, eta=None):
     return K
 
 
+def anova_cross(Xt, Xs, windows, sigma, v, eta=None):
+    """y_j = sum_l eta_l sum_i exp(-sum_{a in W_l}(Xt_ja - Xs_ia)^2 / sigma_l^2) v_i for
+    targets Xt (M x d) and sources Xs (N x d): the kernel of Section 3 between two
+    point sets (the decision function of Section 2 evaluates it at new points).
+    Numpy, explicit differences, target blocks to bound memory."""
+    Xs, win, sig, et = _prep(Xs, windows, sigma, eta)
+    Xt = np.ascontiguousarray(np.asarray(Xt, dtype=np.float64))
+    v = np.asarray(v, dtype=np.float64)
+    M, N = Xt.shape[0], Xs.shape[0]
+    y = np.zeros(M)
+    blk = max(1, int(2e7 // max(N, 1)))
+    for l in range(win.shape[0]):
+        f = [int(c) for c in win[l] if c >= 0]
+        for s in range(0, M, blk):
+            diff = Xt[s:s + blk, None, f] - Xs[None, :, f]
+            y[s:s + blk] += et[l] * (np.exp(-(diff * diff).sum(-1) / sig[l] ** 2) @ v)
+    return y
+
+
 # ----------------------------------------------------------------------------- objectives
 
 def dual_objective(K, y, alpha):

@@ -26,7 +26,7 @@ EXPORTED = [
     "anova_nystrom", "anova_last_error", "anova_profile_begin", "anova_profile_end",
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
-    "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky",
+    "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -144,6 +144,8 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "anova_tune_opts_default": ([ctypes.POINTER(TuneOpts)], ctypes.c_int),
         "anova_rp_cholesky": ([P, i32, dbl, P, P, i64, P, ctypes.POINTER(i32), P], ctypes.c_int),
+        "anova_decision_function": ([P, i64, i64, P, i64, i64, i32, P, i32, P, P, ctypes.POINTER(Opts), P, P,
+                                     dbl, P, P], ctypes.c_int),
         "anova_autotune": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(TuneOpts), P, ctypes.POINTER(Opts),
                             ctypes.POINTER(TuneCandidate), i32, ctypes.POINTER(i32)], ctypes.c_int),
     }
@@ -332,6 +334,36 @@ def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: Ipm
     _check(lib.anova_request_footprint(int(N), int(d), int(P), ctypes.byref(nfft) if nfft else None,
                                        ctypes.byref(ipm) if ipm else None, ctypes.byref(b)))
     return b.value
+
+
+def decision_function(X, Xnew, windows, sigma, labels, alpha, lam: float, eta=None, opts: Opts | None = None,
+                      stream=None, **opt_kw):
+    """f(Xnew) = sum_j alpha_j y_j k(x, x_j) - lam (anova_decision_function);
+    X, Xnew row-major device tensors, labels and alpha device vectors."""
+    import torch
+    lib = load_library()
+    X = _dev_f64(X, "X")
+    Xn = _dev_f64(Xnew, "Xnew")
+    if X.dim() != 2 or Xn.dim() != 2 or X.stride(1) != 1 or Xn.stride(1) != 1 or X.shape[1] != Xn.shape[1]:
+        raise ValueError("X and Xnew must be 2-D row-major tensors with the same number of columns")
+    labels = _dev_f64(labels, "labels").contiguous()
+    alpha = _dev_f64(alpha, "alpha").contiguous()
+    win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 3))
+    Pw = int(win.shape[0])
+    sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (Pw,)))
+    et = None if eta is None else np.ascontiguousarray(np.broadcast_to(np.asarray(eta, dtype=np.float64), (Pw,)))
+    if opts is None:
+        opts = default_opts(**opt_kw)
+    M = int(Xn.shape[0])
+    f = torch.empty(M, dtype=torch.float64, device=Xn.device)
+    _check(lib.anova_decision_function(ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), X.stride(0),
+                                       ctypes.c_void_p(Xn.data_ptr()), M, Xn.stride(0), int(X.shape[1]),
+                                       win.ctypes.data_as(ctypes.c_void_p), Pw, sig.ctypes.data_as(ctypes.c_void_p),
+                                       et.ctypes.data_as(ctypes.c_void_p) if et is not None else None,
+                                       ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()),
+                                       ctypes.c_void_p(alpha.data_ptr()), float(lam), ctypes.c_void_p(f.data_ptr()),
+                                       _stream(stream)))
+    return f
 
 
 def autotune(X, windows, sigma, eta=None, target_rel_err: float = 1e-4, rhs: int = 1,

@@ -310,6 +310,17 @@ int anova_grid_solve(const anova_grid_problem* problems, int32_t n_problems, con
     });
 }
 
+int anova_decision_function(const double* X, int64_t N, int64_t ldx, const double* Xnew, int64_t M,
+                            int64_t ldn, int32_t d, const int32_t* windows, int32_t P, const double* sigma,
+                            const double* eta, const anova_opts* opts, const double* labels,
+                            const double* alpha, double lambda, double* f, void* stream) {
+    return guarded([&] {
+        anv::decision_function(X, N, ldx, Xnew, M, ldn, d, windows, P, sigma, eta, opts, labels, alpha, lambda, f,
+                               static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
 int anova_tune_opts_default(anova_tune_opts* t) {
     if (!t) return ANOVA_INVALID_ARG;
     std::memset(t, 0, sizeof(*t));

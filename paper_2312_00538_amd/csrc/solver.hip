@@ -1677,4 +1677,45 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     return status;
 }
 
+// ------------------------------------------------------------------ decision function
+namespace {
+// x = [y * alpha ; 0]
+__global__ void k_pad_coeffs(const double* __restrict__ y, const double* __restrict__ a, int64_t N, int64_t M,
+                             double* __restrict__ x) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) x[i] = y[i] * a[i];
+    else if (i < N + M) x[i] = 0.0;
+}
+// f_j = (K x)_{N + j} - lambda
+__global__ void k_take_shift(const double* __restrict__ ye, int64_t N, int64_t M, double lam, double* __restrict__ f) {
+    const int64_t j = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (j < M) f[j] = ye[N + j] - lam;
+}
+}  // namespace
+
+void decision_function(const double* X, int64_t N, int64_t ldx, const double* Xnew, int64_t M, int64_t ldn,
+                       int32_t d, const int32_t* windows, int32_t P, const double* sigma, const double* eta,
+                       const anova_opts* opts, const double* labels, const double* alpha, double lambda, double* f,
+                       hipStream_t st) {
+    ANV_CHECK(X && Xnew && labels && alpha && f, "NULL argument");
+    ANV_CHECK(N >= 1 && M >= 1 && d >= 1, "need N >= 1, M >= 1, d >= 1");
+    ANV_CHECK(ldx >= d && ldn >= d, "leading dimension < d");
+    ANV_CHECK(std::isfinite(lambda), "lambda must be finite");
+    const int64_t T = N + M;
+    DevBuf<double> U, xe, ye;
+    U.alloc(size_t(T) * d);
+    ANV_HIP(hipMemcpy2DAsync(U.p, d * sizeof(double), X, ldx * sizeof(double), d * sizeof(double), N,
+                             hipMemcpyDeviceToDevice, st));
+    ANV_HIP(hipMemcpy2DAsync(U.p + N * d, d * sizeof(double), Xnew, ldn * sizeof(double), d * sizeof(double), M,
+                             hipMemcpyDeviceToDevice, st));
+    std::unique_ptr<Plan> pl(create_plan(U.p, T, d, d, windows, P, sigma, eta, opts, st));
+    xe.alloc(T);
+    ye.alloc(T);
+    hipLaunchKernelGGL(k_pad_coeffs, dim3(nblk(T)), dim3(kT), 0, st, labels, alpha, N, M, xe.p);
+    enqueue_matvec(*pl, xe.p, 1, T, ye.p, T, st);
+    hipLaunchKernelGGL(k_take_shift, dim3(nblk(M)), dim3(kT), 0, st, ye.p, N, M, lambda, f);
+    ANV_HIP(hipGetLastError());
+    host_wait(st);
+}
+
 }  // namespace anv

@@ -39,4 +39,10 @@ int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl,
 void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, int64_t ldz,
                     hipStream_t st);
 
+// f = K(Xnew, X) (y * alpha) - lambda through one plan over both point sets
+void decision_function(const double* X, int64_t N, int64_t ldx, const double* Xnew, int64_t M, int64_t ldn,
+                       int32_t d, const int32_t* windows, int32_t P, const double* sigma, const double* eta,
+                       const anova_opts* opts, const double* labels, const double* alpha, double lambda, double* f,
+                       hipStream_t st);
+
 }  // namespace anv

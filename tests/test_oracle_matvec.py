@@ -133,3 +133,24 @@ def test_feature_choice_matters():
     a = oracle.anova_matvec(X, np.array([[0, 1, -1]]), 0.2, v)
     b = oracle.anova_matvec(X, np.array([[0, 2, -1]]), 0.2, v)
     assert np.abs(a - b).max() > 1e-3
+
+
+def test_cross_kernel_on_the_same_points_is_the_direct_sum():
+    # targets = sources: the two-set sum equals the C direct sum of the same matvec
+    p = workloads.small_plain(seed=4, N=300)
+    y2 = oracle.anova_cross(p.X, p.X, p.windows, p.sigma, p.v[:, 0])
+    y1 = oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, 0]).reshape(-1)
+    assert np.allclose(y2, y1, rtol=1e-12, atol=1e-12)
+
+
+def test_cross_kernel_closed_forms():
+    # a target on a source point with a unit coefficient sees every window's
+    # K(x, x) = 1: the value is the sum of eta; a far target sees nothing
+    p = workloads.small_plain(seed=5, N=50)
+    e = np.zeros(50)
+    e[7] = 1.0
+    eta = np.array([1.0, 2.0, 0.5])
+    y = oracle.anova_cross(p.X[[7]], p.X, p.windows, p.sigma, e, eta=eta)
+    assert np.isclose(y[0], eta.sum(), rtol=0, atol=1e-15)
+    far = p.X[[7]] + 100.0
+    assert oracle.anova_cross(far, p.X, p.windows, p.sigma, np.ones(50))[0] == 0.0
