@@ -46,6 +46,8 @@ extern "C" {
 #define ANOVA_PRECOND_RPCHOL   4  /* randomly pivoted Cholesky (Section 4 cites it as
                                      the random-pivot variant of Algorithm 2); pivot
                                      draws from anova_ipm_opts.seed                  */
+#define ANOVA_PRECOND_RFF      5  /* random Fourier features (Section 4): rank split
+                                     over the windows, draws from anova_ipm_opts.seed */
 #define ANOVA_PRECOND_DIAG     3  /* the block-diagonal preconditioner of Section 5
                                      with no low-rank term: diag(Theta, y^T Theta^{-1} y),
                                      the barrier diagonal only (no approximation of K) */
@@ -239,6 +241,20 @@ int anova_pivoted_cholesky(anova_plan_t plan, int32_t rank, double err_tol,
  * Other arguments, outputs and errors as for anova_pivoted_cholesky. */
 int anova_rp_cholesky(anova_plan_t plan, int32_t rank, double err_tol, const double* uniforms,
                       double* L, int64_t ldl, int64_t* piv, int32_t* rank_used, void* stream);
+
+/* Random Fourier features of the plan's kernel (Section 4): K ~= Z Z^T with
+ * rank k split over the windows (k_l = floor(k / P), the first k mod P windows
+ * one more). Feature j of window l is
+ *     sqrt(eta_l) sqrt(2 / k_l) cos(w_j^T x^{W_l} + b_j),
+ * which for w_j ~ N(0, (2 / sigma_l^2) I) and b_j ~ U(0, 2 pi) has expectation
+ * K_l (Bochner's theorem for the Gaussian).
+ *   w   host, k x 3 FP64: row j holds w_j for the window's features in order
+ *       (entries past the window's size are ignored).
+ *   b   host, k FP64.
+ *   Z   device, N x k FP64 output, column j at Z + j*ldz (ldz >= N).
+ * Synchronises `stream`. Errors: ANOVA_INVALID_ARG, ANOVA_HIP_ERROR. */
+int anova_rff_factor(anova_plan_t plan, int32_t k, const double* w, const double* b, double* Z, int64_t ldz,
+                     void* stream);
 
 /* Randomized Nystrom factor (Section 4): Q = orth(K G) and
  * K ~= (KQ)(Q^T K Q)^{-1}(KQ)^T = Z^T Z, with Q^T K Q = L D L^T and diagonal

@@ -298,6 +298,32 @@ def rp_cholesky(K, u, err_tol=0.0):
     return L[:, :len(piv)], np.array(piv, dtype=np.int64)
 
 
+def rff_counts(k, P):
+    """Features per window: k // P each, the first k % P windows one more."""
+    return [k // P + (1 if l < k % P else 0) for l in range(P)]
+
+
+def rff_features(X, windows, sigma, w, b, eta=None):
+    """Random Fourier features (Section 4) of the ANOVA kernel sum: Z (N x k) with
+    the rank split over the windows (rff_counts). Feature j of window l is
+    sqrt(eta_l * 2 / k_l) cos(w_j . x^{W_l} + b_j), w_j holding one frequency per
+    feature of the window in order (w is k x 3, entries past the window's size
+    unused). For w_j ~ N(0, (2 / sigma_l^2) I) and b_j ~ U(0, 2 pi), E[Z Z^T] = K
+    (Bochner's theorem for the Gaussian of each window)."""
+    X, win, sig, et = _prep(X, windows, sigma, eta)
+    w = np.asarray(w, dtype=np.float64).reshape(-1, 3)
+    b = np.asarray(b, dtype=np.float64).reshape(-1)
+    k = b.shape[0]
+    Z = np.zeros((X.shape[0], k))
+    j = 0
+    for l, cl in enumerate(rff_counts(k, win.shape[0])):
+        f = [int(c) for c in win[l] if c >= 0]
+        for _ in range(cl):
+            Z[:, j] = np.sqrt(et[l] * 2.0 / cl) * np.cos(X[:, f] @ w[j, :len(f)] + b[j])
+            j += 1
+    return Z
+
+
 def pivoted_cholesky(K, k, err_tol=0.0):
     """Greedy pivoted Cholesky of rank <= k (Algorithm 2, Section 4) on a copy of
     the dense K: at step j pick the largest remaining diagonal entry (lowest

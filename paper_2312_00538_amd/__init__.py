@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libanova_nfft.so")
 
 OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, NUMERICAL = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
-PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG, PRECOND_RPCHOL = 0, 1, 2, 3, 4
+PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG, PRECOND_RPCHOL, PRECOND_RFF = 0, 1, 2, 3, 4, 5
 
 EXPORTED = [
     "anova_opts_default", "anova_plan_create", "anova_matvec", "anova_plan_destroy",
@@ -27,6 +27,7 @@ EXPORTED = [
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
     "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
+    "anova_rff_factor",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -144,6 +145,7 @@ def load_library(path: str = LIB_PATH):
                               ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "anova_tune_opts_default": ([ctypes.POINTER(TuneOpts)], ctypes.c_int),
         "anova_rp_cholesky": ([P, i32, dbl, P, P, i64, P, ctypes.POINTER(i32), P], ctypes.c_int),
+        "anova_rff_factor": ([P, i32, P, P, P, i64, P], ctypes.c_int),
         "anova_decision_function": ([P, i64, i64, P, i64, i64, i32, P, i32, P, P, ctypes.POINTER(Opts), P, P,
                                      dbl, P, P], ctypes.c_int),
         "anova_autotune": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(TuneOpts), P, ctypes.POINTER(Opts),
@@ -304,6 +306,17 @@ class Plan:
                                       ctypes.byref(used), _stream(stream)))
         r = used.value
         return L[:r].t(), piv[:r]
+
+    def rff_factor(self, w, b, stream=None):
+        """Random Fourier features Z (N x k) for draws w (k x 3) and b (k)."""
+        import torch
+        w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1, 3))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+        k = int(b.shape[0])
+        Z = torch.empty((k, self.N), dtype=torch.float64, device=self.device)
+        _check(_lib.anova_rff_factor(self._h, k, w.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
+                                     ctypes.c_void_p(Z.data_ptr()), self.N, _stream(stream)))
+        return Z.t()
 
     def nystrom(self, G, stream=None):
         import torch

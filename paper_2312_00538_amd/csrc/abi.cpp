@@ -1,6 +1,7 @@
 // extern "C" entry points: argument checks, exception-to-status translation
 // and the thread-local error message.
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -192,6 +193,18 @@ int anova_rp_cholesky(anova_plan_t plan, int32_t rank, double err_tol, const dou
             ANV_CHECK(uniforms[j] >= 0.0 && uniforms[j] < 1.0, "uniforms must lie in [0, 1)");
         *rank_used = anv::pivoted_cholesky(*plan->p, rank, err_tol, L, ldl, piv, static_cast<hipStream_t>(stream),
                                            uniforms);
+        return ANOVA_OK;
+    });
+}
+
+int anova_rff_factor(anova_plan_t plan, int32_t k, const double* w, const double* b, double* Z, int64_t ldz,
+                     void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(w && b && Z, "NULL argument");
+        for (int64_t i = 0; i < int64_t(k) * 3; ++i) ANV_CHECK(std::isfinite(w[i]), "w must be finite");
+        for (int32_t j = 0; j < k; ++j) ANV_CHECK(std::isfinite(b[j]), "b must be finite");
+        anv::rff_factor(*plan->p, k, w, b, Z, ldz, static_cast<hipStream_t>(stream));
         return ANOVA_OK;
     });
 }

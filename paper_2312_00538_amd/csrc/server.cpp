@@ -325,7 +325,7 @@ int64_t request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts& nff
     b += int64_t(P) * E * E * E * (W * W + 4) * eb;                  // grids and fold target
     b += 18 * (N + 1) * 8;                                           // IPM vectors
     const int64_t k = (ipm.precond == ANOVA_PRECOND_PCHOL || ipm.precond == ANOVA_PRECOND_NYSTROM ||
-                       ipm.precond == ANOVA_PRECOND_RPCHOL) ? ipm.rank : 0;
+                       ipm.precond == ANOVA_PRECOND_RPCHOL || ipm.precond == ANOVA_PRECOND_RFF) ? ipm.rank : 0;
     b += (ipm.precond == ANOVA_PRECOND_NYSTROM ? 4 : 2) * N * k * 8;  // factor and its build
     b += 260 * k * k * 8;                                            // capacitance partial sums
     return b + b / 4;                                                // margin

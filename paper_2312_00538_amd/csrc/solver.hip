@@ -143,6 +143,20 @@ __global__ void k_sample_pivot(const double* __restrict__ d, int64_t n, int64_t 
     out[2] = total;
 }
 
+// Random Fourier features (Section 4, with Bochner's theorem for the Gaussian of
+// each window): column j of Z^T (N x k, column-major) belongs to window fwin[j]
+// and is fscale[j] cos(w_j^T x^{W} + b_j), w_j given per coordinate slot.
+__global__ void k_rff(const double* __restrict__ xw, int64_t N, int32_t P, const int32_t* __restrict__ fwin,
+                      const double* __restrict__ fw, const double* __restrict__ fb,
+                      const double* __restrict__ fscale, double* __restrict__ Z) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= N) return;
+    const double* x = xw + (i * P + fwin[j]) * 3;
+    const double t = fb[j] + fw[3 * j] * x[0] + fw[3 * j + 1] * x[1] + fw[3 * j + 2] * x[2];
+    Z[int64_t(j) * N + i] = fscale[j] * cos(t);
+}
+
 // residual diagonal of the pivot: K_pp - sum_j L_pj^2 (one thread)
 __global__ void k_pivot_value(const double* __restrict__ L, int64_t N, int64_t p, int r, double kpp,
                               double* __restrict__ out) {
@@ -664,7 +678,8 @@ __global__ void k_step(double* __restrict__ a, const double* __restrict__ da, in
 // from the host-provided dot value.
 // preconditioners with a low-rank factor of K (the others need none)
 inline bool low_rank_precond(int p) {
-    return p == ANOVA_PRECOND_PCHOL || p == ANOVA_PRECOND_NYSTROM || p == ANOVA_PRECOND_RPCHOL;
+    return p == ANOVA_PRECOND_PCHOL || p == ANOVA_PRECOND_NYSTROM || p == ANOVA_PRECOND_RPCHOL ||
+           p == ANOVA_PRECOND_RFF;
 }
 
 // uniforms in [0, 1) for randomly pivoted Cholesky: splitmix64 (Steele, Lea and
@@ -1269,6 +1284,55 @@ int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl,
     return r;
 }
 
+std::vector<int> rff_counts(int k, int P) {
+    std::vector<int> c(size_t(P), k / P);
+    for (int l = 0; l < k % P; ++l) ++c[size_t(l)];
+    return c;
+}
+
+void rff_factor(Plan& pl, int k, const double* w, const double* b, double* Z, int64_t ldz, hipStream_t st) {
+    const int64_t N = pl.N;
+    const int P = pl.P;
+    ANV_CHECK(k >= 1 && k <= 65535, "k must be in [1, 65535]");
+    ANV_CHECK(ldz >= N, "ldz < N");
+    const std::vector<int> cnt = rff_counts(k, P);
+    std::vector<int32_t> fwin(size_t(k), 0);
+    std::vector<double> fw(static_cast<size_t>(k) * 3, 0.0), fb(static_cast<size_t>(k)), fs(static_cast<size_t>(k));
+    int j = 0;
+    for (int l = 0; l < P; ++l) {
+        int nf = 0;
+        for (int a = 0; a < 3; ++a) nf += pl.slot_feat[size_t(l)][size_t(a)] >= 0;
+        for (int q = 0; q < cnt[size_t(l)]; ++q, ++j) {
+            fwin[size_t(j)] = l;
+            for (int a = 0; a < nf; ++a) fw[size_t(j) * 3 + size_t(3 - nf + a)] = w[size_t(j) * 3 + size_t(a)];
+            fb[size_t(j)] = b[size_t(j)];
+            fs[size_t(j)] = std::sqrt(pl.eta[size_t(l)] * 2.0 / cnt[size_t(l)]);
+        }
+    }
+    DevBuf<int32_t> dwin;
+    DevBuf<double> dw, db, ds, Zc;
+    dwin.alloc(size_t(k));
+    dw.alloc(size_t(k) * 3);
+    db.alloc(size_t(k));
+    ds.alloc(size_t(k));
+    ANV_HIP(hipMemcpyAsync(dwin.p, fwin.data(), fwin.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    ANV_HIP(hipMemcpyAsync(dw.p, fw.data(), fw.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    ANV_HIP(hipMemcpyAsync(db.p, fb.data(), fb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    ANV_HIP(hipMemcpyAsync(ds.p, fs.data(), fs.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    double* out = Z;
+    if (ldz != N) {
+        Zc.alloc(size_t(N) * k);
+        out = Zc.p;
+    }
+    hipLaunchKernelGGL(k_rff, dim3(nblk(N), unsigned(k)), dim3(kT), 0, st, pl.xw.p, N, P, dwin.p, dw.p, db.p, ds.p,
+                       out);
+    ANV_HIP(hipGetLastError());
+    if (ldz != N)
+        ANV_HIP(hipMemcpy2DAsync(Z, ldz * sizeof(double), out, N * sizeof(double), N * sizeof(double), k,
+                                 hipMemcpyDeviceToDevice, st));
+    host_wait(st);
+}
+
 void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, int64_t ldz, hipStream_t st) {
     const int64_t N = pl.N;
     ANV_CHECK(k <= 1024, "k must be <= 1024");
@@ -1296,7 +1360,7 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
     const int64_t N = pl.N;
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
                   o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG ||
-                  o.precond == ANOVA_PRECOND_RPCHOL,
+                  o.precond == ANOVA_PRECOND_RPCHOL || o.precond == ANOVA_PRECOND_RFF,
               "unknown preconditioner");
     ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");
@@ -1309,6 +1373,26 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
         std::vector<double> u;
         if (o.precond == ANOVA_PRECOND_RPCHOL) u = pivot_uniforms(o.seed, o.rank);
         f.rank = pchol_into(pl, o.rank, o.err_tol, f.Z.p, N, piv.data(), st, u.empty() ? nullptr : u.data());
+    } else if (o.precond == ANOVA_PRECOND_RFF) {
+        // draws: w ~ N(0, 2 / sigma_l^2) per window coordinate (Box-Muller on
+        // splitmix64 uniforms), b ~ U(0, 2 pi)
+        f.rank = o.rank;
+        f.Z.alloc(size_t(N) * o.rank);
+        const std::vector<int> cnt = rff_counts(o.rank, pl.P);
+        const std::vector<double> u = pivot_uniforms(o.seed, 8 * o.rank);
+        std::vector<double> w(size_t(o.rank) * 3), b(size_t(o.rank));
+        int j = 0;
+        for (int l = 0; l < pl.P; ++l)
+            for (int q = 0; q < cnt[size_t(l)]; ++q, ++j) {
+                const double sw = std::sqrt(2.0) / pl.sigma[size_t(l)];
+                const double* uu = u.data() + size_t(8) * j;
+                const double r0 = std::sqrt(-2.0 * std::log(1.0 - uu[0])), r1 = std::sqrt(-2.0 * std::log(1.0 - uu[2]));
+                w[size_t(j) * 3 + 0] = sw * r0 * std::cos(2.0 * M_PI * uu[1]);
+                w[size_t(j) * 3 + 1] = sw * r0 * std::sin(2.0 * M_PI * uu[1]);
+                w[size_t(j) * 3 + 2] = sw * r1 * std::cos(2.0 * M_PI * uu[3]);
+                b[size_t(j)] = 2.0 * M_PI * uu[4];
+            }
+        rff_factor(pl, o.rank, w.data(), b.data(), f.Z.p, N, st);
     } else if (o.precond == ANOVA_PRECOND_NYSTROM) {
         f.rank = o.rank;
         f.Z.alloc(size_t(N) * o.rank);
@@ -1339,7 +1423,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
                   o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG ||
-                  o.precond == ANOVA_PRECOND_RPCHOL,
+                  o.precond == ANOVA_PRECOND_RPCHOL || o.precond == ANOVA_PRECOND_RFF,
               "unknown preconditioner");
     ANV_CHECK(!low_rank_precond(o.precond) || (o.rank >= 1 && o.rank <= std::min<int64_t>(N, 1024)),
               "rank must be in [1, min(N, 1024)]");

@@ -39,6 +39,11 @@ int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl,
 void nystrom_factor(Plan& pl, const double* G, int k, int64_t ldg, double* Zt, int64_t ldz,
                     hipStream_t st);
 
+// random Fourier features of the plan's kernel: Z^T (N x k, column j at Z + j*ldz),
+// features split over the windows as evenly as possible (earlier windows take
+// the remainder); w host k x 3 (the window's coordinates in order), b host k
+void rff_factor(Plan& pl, int k, const double* w, const double* b, double* Z, int64_t ldz, hipStream_t st);
+
 // f = K(Xnew, X) (y * alpha) - lambda through one plan over both point sets
 void decision_function(const double* X, int64_t N, int64_t ldx, const double* Xnew, int64_t M, int64_t ldn,
                        int32_t d, const int32_t* windows, int32_t P, const double* sigma, const double* eta,

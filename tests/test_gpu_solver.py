@@ -232,3 +232,22 @@ def test_ipm_randomly_pivoted_cholesky_preconditioner(dev):
     p = workloads.gaussian_mixture(seed=1, N=600, d=20, noise=0.1, sigma=0.8, C=10.0)
     a, lam, st = _check_solve(p, 10.0, dev, rank=100, precond=lib.PRECOND_RPCHOL, seed=3)
     assert st["kry_iters_max"] <= 20
+
+
+def test_rff_factor_matches_oracle(dev):
+    p = workloads.gaussian_mixture(seed=8, N=500, d=8, sigma=0.7)   # windows of 3, 3 and 2 features
+    pl = _plan(p, dev)
+    rng = np.random.default_rng(6)
+    k = 37
+    w = rng.standard_normal((k, 3)) * np.sqrt(2.0) / p.sigma
+    b = rng.uniform(0, 2 * np.pi, size=k)
+    Z = pl.rff_factor(w, b).cpu().numpy()
+    Zo = oracle.rff_features(p.X, p.windows, p.sigma, w, b)
+    assert np.allclose(Z, Zo, rtol=1e-12, atol=1e-13)
+
+
+def test_ipm_random_fourier_feature_preconditioner(dev):
+    import paper_2312_00538_amd as lib
+    p = workloads.gaussian_mixture(seed=1, N=600, d=20, noise=0.1, sigma=0.8, C=10.0)
+    a, lam, st = _check_solve(p, 10.0, dev, rank=200, precond=lib.PRECOND_RFF, seed=3)
+    print("rff krylov", st["kry_iters_total"], st["kry_iters_max"])

@@ -300,3 +300,32 @@ def test_rp_cholesky_zero_draw_takes_the_first_positive_diagonal():
     L, piv = oracle.rp_cholesky(K, [0.0, 0.0])
     assert piv.tolist() == [2, 3]
     assert np.allclose(L[:, 0], [0, 0, np.sqrt(2.0), 0])
+
+
+def test_rff_zero_draws_give_the_normalisation():
+    # w = 0, b = 0: every feature of window l is sqrt(2 eta_l / k_l), so every
+    # entry of Z Z^T is sum_l 2 eta_l
+    p = workloads.small_plain(seed=2, N=20)
+    eta = np.array([1.0, 0.5, 2.0])
+    Z = oracle.rff_features(p.X, p.windows, p.sigma, np.zeros((11, 3)), np.zeros(11), eta=eta)
+    assert np.allclose(Z @ Z.T, 2.0 * eta.sum(), rtol=1e-14, atol=0)
+
+
+def test_rff_expectation_is_the_kernel():
+    # many features drawn as specified reproduce K (points about sigma apart, so
+    # a wrong frequency variance would miss by far more than the tolerance)
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-0.5, 0.5, size=(25, 6))
+    win = workloads.consecutive_windows(6)
+    sigma = 0.5
+    k = 2 * 40000
+    w = rng.standard_normal((k, 3)) * np.sqrt(2.0) / sigma
+    b = rng.uniform(0, 2 * np.pi, size=k)
+    Z = oracle.rff_features(X, win, sigma, w, b)
+    K = oracle.anova_dense(X, win, sigma)
+    err = np.abs(Z @ Z.T - K).max()
+    print("max |Z Z^T - K|", err)
+    assert err < 0.04
+    # half the frequency variance misses clearly
+    Z2 = oracle.rff_features(X, win, sigma, w / np.sqrt(2.0), b)
+    assert np.abs(Z2 @ Z2.T - K).max() > 0.1
