@@ -16,7 +16,8 @@ Contents, each following the paper (arXiv 2312.00538):
   * woodbury_apply — the Sherman-Morrison-Woodbury form of the (1,1)-block
     preconditioner (Section 5).
   * saddle_preconditioners — the block-triangular preconditioner of Section 5
-    and its block-diagonal SPD analogue.
+    and its block-diagonal SPD analogue; block_triangular_apply — its inverse
+    by forward substitution; gmres — right-preconditioned GMRES (Section 5).
   * objectives — dual objective (eq. "kernelsvm"), hinge-loss primal and the
     relative duality gap used as the stopping measure.
 Readings where the paper is silent are listed in the design notes and repeated
@@ -431,3 +432,53 @@ def saddle_preconditioners(Ahat, y):
     Pd[:N, :N] = Ahat
     Pd[N, N] = float(y @ np.linalg.solve(Ahat, y))
     return Pt, Pd
+
+
+def block_triangular_apply(Ahat, y, g):
+    """P^{-1} g for the block-triangular preconditioner of Section 5,
+    P = [[Ahat, 0], [-y^T, -1]]: forward substitution by blocks,
+    x1 = Ahat^{-1} g1, then -y^T x1 - x2 = g2."""
+    N = y.shape[0]
+    x1 = np.linalg.solve(Ahat, g[:N])
+    return np.concatenate([x1, [-(y @ x1) - g[N]]])
+
+
+def gmres(A, b, apply_pinv, tol, maxit):
+    """GMRES (Saad and Schultz 1986) for A x = b, preconditioned from the right
+    (Section 5 pairs GMRES with the non-symmetric P): minimise ||b - A P^{-1} u||
+    over the Krylov space of A P^{-1} started at r0 = b, x = P^{-1} u. Arnoldi by
+    modified Gram-Schmidt, least squares by Givens rotations; stops when the
+    residual estimate |g_{j+1}| <= tol ||b|| or after maxit steps.
+    Returns (x, iterations, residual estimates after each step)."""
+    n = b.shape[0]
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return np.zeros(n), 0, []
+    V = np.zeros((n, maxit + 1))
+    H = np.zeros((maxit + 1, maxit))
+    cs, sn = np.zeros(maxit), np.zeros(maxit)
+    g = np.zeros(maxit + 1)
+    g[0] = beta
+    V[:, 0] = b / beta
+    hist, j = [], 0
+    while j < maxit:
+        w = A @ apply_pinv(V[:, j])
+        for i in range(j + 1):
+            H[i, j] = V[:, i] @ w
+            w = w - H[i, j] * V[:, i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] > 0.0:
+            V[:, j + 1] = w / H[j + 1, j]
+        for i in range(j):   # earlier rotations on the new column
+            a, c = H[i, j], H[i + 1, j]
+            H[i, j], H[i + 1, j] = cs[i] * a + sn[i] * c, -sn[i] * a + cs[i] * c
+        rho = np.hypot(H[j, j], H[j + 1, j])
+        cs[j], sn[j] = H[j, j] / rho, H[j + 1, j] / rho
+        H[j, j], H[j + 1, j] = rho, 0.0
+        g[j + 1], g[j] = -sn[j] * g[j], cs[j] * g[j]
+        j += 1
+        hist.append(abs(g[j]))
+        if abs(g[j]) <= tol * beta:   # also a breakdown (H[j, j-1] = 0), where g[j] = 0
+            break
+    u = V[:, :j] @ np.linalg.solve(np.triu(H[:j, :j]), g[:j])
+    return apply_pinv(u), j, hist

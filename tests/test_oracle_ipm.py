@@ -329,3 +329,50 @@ def test_rff_expectation_is_the_kernel():
     # half the frequency variance misses clearly
     Z2 = oracle.rff_features(X, win, sigma, w / np.sqrt(2.0), b)
     assert np.abs(Z2 @ Z2.T - K).max() > 0.1
+
+
+def _newton_system(seed, N):
+    p = workloads.small_plain(seed=seed, N=N)
+    K = oracle.anova_dense(p.X, p.windows, 0.3)
+    y = p.labels
+    theta = np.random.default_rng(seed + 1).uniform(0.1, 5.0, N)
+    A = oracle.saddle_matrix(K, y, theta)
+    b = np.random.default_rng(seed + 2).standard_normal(N + 1)
+    return A, y, b
+
+
+def test_block_triangular_apply_inverts_p():
+    # P^{-1} applied to P e_j gives e_j back, column by column
+    A, y, _ = _newton_system(4, 30)
+    Pt, _ = oracle.saddle_preconditioners(A[:30, :30], y)
+    back = np.stack([oracle.block_triangular_apply(A[:30, :30], y, Pt[:, j]) for j in range(31)], axis=1)
+    assert np.allclose(back, np.eye(31), atol=1e-10)
+
+
+def test_gmres_without_preconditioner_is_exact_after_n_steps():
+    # Krylov space of dimension n: the minimiser is the solution itself
+    A, y, b = _newton_system(5, 25)
+    x, its, hist = oracle.gmres(A, b, lambda v: v, tol=0.0, maxit=26)
+    assert its == 26
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8, atol=1e-10)
+
+
+def test_gmres_residual_estimates_are_true_residuals_and_decrease():
+    A, y, b = _newton_system(6, 40)
+    Ahat = A[:40, :40] + np.diag(np.linspace(0.0, 0.5, 40))   # an inexact (1,1) block
+    pinv = lambda v: oracle.block_triangular_apply(Ahat, y, v)
+    for m in range(1, 6):
+        x, its, hist = oracle.gmres(A, b, pinv, tol=0.0, maxit=m)
+        assert its == m
+        assert np.linalg.norm(b - A @ x) == pytest.approx(hist[-1], rel=1e-8, abs=1e-12)
+    assert all(h2 <= h1 * (1 + 1e-12) for h1, h2 in zip(hist, hist[1:]))
+
+
+def test_gmres_with_exact_block_converges_in_two_steps():
+    # with Ahat = A the preconditioned matrix has the two eigenvalues 1 and
+    # y^T A^{-1} y and a minimal polynomial of degree 2 (Section 5)
+    A, y, b = _newton_system(7, 40)
+    x, its, hist = oracle.gmres(A, b, lambda v: oracle.block_triangular_apply(A[:40, :40], y, v),
+                                tol=1e-12, maxit=10)
+    assert its == 2
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-9, atol=1e-11)
