@@ -16,12 +16,13 @@ measurement) checks the first right-hand side on the rows it samples; a run
 above relative l2 error 1e-4 reports value 0.
 
 Also reported: IPM solve latency p50/p99 for the small plain problem and the
-full N = 500000 problem; the request server (continuous batching against one
+full N = 500000 problem (MINRES, and GMRES with the block-triangular
+preconditioner); the request server (continuous batching against one
 solve at a time); the hyperparameter grid over cross-validation folds (solves
 per second against FP64 solves one at a time); and the oracle's rate on the
 host cores.
 
-Prints ONE JSON line. --gpus above 1 is refused: this build runs on one GPU.
+Prints ONE JSON line. --gpus above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -60,6 +61,8 @@ def parse():
     ap.add_argument("--ipm-small-solves", type=int, default=20)
     ap.add_argument("--ipm-full-solves", type=int, default=5)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
+    ap.add_argument("--ipm-full-gmres-solves", type=int, default=3,
+                    help="full-ipm solves with GMRES and the block-triangular preconditioner")
     ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests of the Poisson serving stream (0 = skip)")
     ap.add_argument("--serving-rate", type=float, default=2.0)
@@ -119,7 +122,7 @@ def traffic_record():
     return rec if rec.get("source_sha256") == sha else None
 
 
-def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
+def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
     """Wall-clock per svm_ipm_solve call (API call to return, preconditioner
     build included) over seeds 0..n-1; plan creation timed separately."""
     t_solve, t_plan, stats = [], [], []
@@ -132,7 +135,7 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
         plan = lib.Plan(X, p.windows, p.sigma)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        alpha, lam, st = plan.solve(y, p.C, precond=precond, rank=rank, allow_not_converged=True)
+        alpha, lam, st = plan.solve(y, p.C, precond=precond, rank=rank, krylov=krylov, allow_not_converged=True)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         t_plan.append(1e3 * (t1 - t0))
@@ -148,7 +151,8 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label):
             "ip_iters_p50": float(np.percentile([s["ip_iters"] for s in stats], 50)),
             "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
             "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
-            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom", 3: "barrier-diagonal"}[precond], "precision": "fp64"}
+            "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom", 3: "barrier-diagonal"}[precond],
+            "krylov": ("minres", "gmres")[krylov], "precision": "fp64"}
 
 
 def serving(lib, workloads, n, rate, max_active, share):
@@ -266,7 +270,7 @@ def cpu_baseline(p, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build",
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -419,6 +423,12 @@ def main():
                                a.ipm_full_solves, lib.PRECOND_NYSTROM, 200,
                                f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
                                "Nystrom rank 200"))
+    if a.ipm_full_gmres_solves > 0:
+        ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
+                               a.ipm_full_gmres_solves, lib.PRECOND_NYSTROM, 200,
+                               f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
+                               "Nystrom rank 200; GMRES with the block-triangular preconditioner",
+                               krylov=lib.KRYLOV_GMRES))
     out["ipm"] = ipm
     if a.serving_requests > 0:
         label = (f"serving: Poisson stream, rate {a.serving_rate}/s, N log-uniform 5e3..1e6, d uniform 6..60 "

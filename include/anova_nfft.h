@@ -52,6 +52,15 @@ extern "C" {
                                      with no low-rank term: diag(Theta, y^T Theta^{-1} y),
                                      the barrier diagonal only (no approximation of K) */
 
+/* Krylov method of the Newton solves inside the IPM (Section 5) */
+#define ANOVA_KRYLOV_MINRES 0  /* MINRES with the SPD block-diagonal preconditioner
+                                  diag(A_hat, y^T A_hat^{-1} y)                     */
+#define ANOVA_KRYLOV_GMRES  1  /* GMRES preconditioned from the right with the
+                                  block-triangular P = [[A_hat, 0], [-y^T, -1]];
+                                  restarted every min(max_kry, 100) steps; its
+                                  residual is the unpreconditioned 2-norm. With
+                                  ANOVA_PRECOND_NONE, P = I. HIP graphs unused.   */
+
 #define ANOVA_OPTS_VERSION 1
 #define ANOVA_IPM_OPTS_VERSION 2
 
@@ -159,15 +168,17 @@ int anova_profile_end(anova_plan_t plan, double* stage_ms, int32_t nstage, int32
  * "Newton") is solved by MINRES preconditioned with the block-diagonal SPD
  * matrix diag(A_hat, y^T A_hat^{-1} y), A_hat = Theta + Y Z^T Z Y, applied
  * through the Sherman-Morrison-Woodbury identity (Section 5), with the
- * low-rank factor Z^T from Algorithm 2 or the Nystrom method (Section 4). */
+ * low-rank factor Z^T from Algorithm 2 or the Nystrom method (Section 4);
+ * or (krylov = ANOVA_KRYLOV_GMRES) by GMRES with the block-triangular
+ * preconditioner of Section 5 and the same A_hat. */
 typedef struct {
     int32_t version;     /* ANOVA_IPM_OPTS_VERSION                               */
     int32_t max_ip;      /* IPM iteration cap (Table 1: 50)                      */
-    int32_t max_kry;     /* MINRES iterations per Newton solve (Table 1: 100)    */
+    int32_t max_kry;     /* Krylov iterations per Newton solve (Table 1: 100)    */
     int32_t precond;     /* ANOVA_PRECOND_*                                      */
     double  tol;         /* on mu, |y^T a|/|y^T a0| and the relative duality gap */
     double  tol_inf;     /* on ||xi_lambda||/||xi_lambda^0|| (Table 1: 1e-1)    */
-    double  tol_kry;     /* upper bound of the MINRES relative tolerance (1e-3)  */
+    double  tol_kry;     /* upper bound of the Krylov relative tolerance (1e-3)  */
     double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */
     double  gamma0;      /* step-to-boundary factor (Algorithm 1: 0.99995)       */
     double  mu0;         /* initial barrier parameter (Algorithm 1: 1.0); <= 0:
@@ -181,7 +192,7 @@ typedef struct {
     int32_t graphs;      /* 1: each MINRES iteration is captured once as a HIP
                             graph and replayed (solves outside a server or grid);
                             0: launched kernel by kernel. Same arithmetic.       */
-    int32_t reserved;
+    int32_t krylov;      /* ANOVA_KRYLOV_MINRES (0) or ANOVA_KRYLOV_GMRES (1)    */
 } anova_ipm_opts;
 
 typedef struct {
@@ -204,7 +215,8 @@ typedef struct {
 /* Fill `o` with the defaults: Table 1 values (max_ip = 50 raised to 100,
  * max_kry = 100, tol_kry = 1e-3, sigma_bar = 0.6, gamma0 = 0.99995,
  * mu0 = 1, err_tol = 1e-5), tol = 1e-6, tol_inf = 1e-1, precond = PCHOL,
- * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0, graphs = 1. */
+ * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0, graphs = 1,
+ * krylov = MINRES. */
 int anova_ipm_opts_default(anova_ipm_opts* o);
 
 /* Train: alpha (device, N FP64 out), lambda (host, 1 FP64 out; the bias of

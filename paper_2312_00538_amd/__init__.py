@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libanova_nfft.so")
 OK, INVALID_ARG, OUT_OF_MEMORY, HIP_ERROR, NOT_CONVERGED, NUMERICAL = range(6)
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_NONE, PRECOND_PCHOL, PRECOND_NYSTROM, PRECOND_DIAG, PRECOND_RPCHOL, PRECOND_RFF = 0, 1, 2, 3, 4, 5
+KRYLOV_MINRES, KRYLOV_GMRES = 0, 1
 
 EXPORTED = [
     "anova_opts_default", "anova_plan_create", "anova_matvec", "anova_plan_destroy",
@@ -57,7 +58,7 @@ class IpmOpts(ctypes.Structure):
                 ("tol_kry", ctypes.c_double), ("sigma_bar", ctypes.c_double), ("gamma0", ctypes.c_double),
                 ("mu0", ctypes.c_double), ("rank", ctypes.c_int32), ("mu_rule", ctypes.c_int32),
                 ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -179,12 +180,19 @@ def _dev_f64(t, name):
     return t
 
 
+def _set_fields(o, kw):
+    fields = {f[0] for f in type(o)._fields_}
+    for k, v in kw.items():
+        if k not in fields:
+            raise TypeError(f"unknown {type(o).__name__} field {k!r}")
+        setattr(o, k, v)
+
+
 def default_opts(**kw) -> Opts:
     lib = load_library()
     o = Opts()
     _check(lib.anova_opts_default(ctypes.byref(o)))
-    for k, v in kw.items():
-        setattr(o, k, v)
+    _set_fields(o, kw)
     return o
 
 
@@ -192,8 +200,7 @@ def default_ipm_opts(**kw) -> IpmOpts:
     lib = load_library()
     o = IpmOpts()
     _check(lib.anova_ipm_opts_default(ctypes.byref(o)))
-    for k, v in kw.items():
-        setattr(o, k, v)
+    _set_fields(o, kw)
     return o
 
 

@@ -328,6 +328,8 @@ int64_t request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts& nff
                        ipm.precond == ANOVA_PRECOND_RPCHOL || ipm.precond == ANOVA_PRECOND_RFF) ? ipm.rank : 0;
     b += (ipm.precond == ANOVA_PRECOND_NYSTROM ? 4 : 2) * N * k * 8;  // factor and its build
     b += 260 * k * k * 8;                                            // capacitance partial sums
+    if (ipm.krylov == ANOVA_KRYLOV_GMRES)                            // Arnoldi basis and P^{-1} v
+        b += (int64_t(std::min(ipm.max_kry, 100)) + 2) * ((N + 1 + 31) / 32 * 32) * 8;
     return b + b / 4;                                                // margin
 }
 

@@ -698,6 +698,7 @@ std::vector<double> pivot_uniforms(uint64_t seed, int n) {
 
 // MINRES iterations whose convergence flag the host reads before queueing the next
 constexpr int kEagerChecks = 4;
+constexpr int kGmRestart = 100;  // GMRES restart length cap (the basis holds one more column)
 
 // sqrt(a^2 + b^2) from correctly rounded operations only (one fma), so that
 // the host loop and the device kernel of MINRES round identically
@@ -848,6 +849,91 @@ __global__ void k_minres_update_v(const double* __restrict__ z, int64_t n, doubl
     d2[i] = d1[i];
     d1[i] = dn;
     x[i] += phi * dn;
+}
+
+// ---- GMRES (Section 5): the Arnoldi basis V holds up to kGmMaxCols columns of
+// length n = N + 1, column c at V + c * ldv
+constexpr int kGmMaxCols = 128;
+constexpr int kGmRows = 8;  // rows per thread of the basis inner products
+
+// part[b * nc + c] = sum of V_c[i] w[i] over block b's rows (w held in registers)
+__global__ __launch_bounds__(kT) void k_gm_dots(const double* __restrict__ V, int64_t ldv, int nc,
+                                                const double* __restrict__ w, int64_t n, double* __restrict__ part) {
+    const int64_t base = int64_t(blockIdx.x) * (kT * kGmRows) + threadIdx.x;
+    double wr[kGmRows];
+#pragma unroll
+    for (int r = 0; r < kGmRows; ++r) {
+        const int64_t i = base + int64_t(r) * kT;
+        wr[r] = i < n ? w[i] : 0.0;
+    }
+    __shared__ double wsum[kT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < nc; ++c) {
+        const double* v = V + int64_t(c) * ldv;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < kGmRows; ++r) {
+            const int64_t i = base + int64_t(r) * kT;
+            if (i < n) s += v[i] * wr[r];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (lane == 0) wsum[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) part[int64_t(blockIdx.x) * nc + c] = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
+        __syncthreads();
+    }
+}
+
+// w = (keep ? w : 0) - sum_{c < nc} V_c h_c
+__global__ void k_gm_sub(const double* __restrict__ V, int64_t ldv, int nc, const double* __restrict__ h, int keep,
+                         int64_t n, double* __restrict__ w) {
+    __shared__ double hs[kGmMaxCols];
+    for (int c = threadIdx.x; c < nc; c += kT) hs[c] = h[c];
+    __syncthreads();
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < nc; ++c) s += V[int64_t(c) * ldv + i] * hs[c];
+    w[i] = (keep ? w[i] : 0.0) - s;
+}
+
+// w = A [z; z_N] for the Newton matrix A = [[Y K Y + Theta, -y], [-y^T, 0]], with
+// kyz = K (y o z), ytz = y^T z (device), and z_N the last entry of P^{-1} v:
+// -(y^T z) - v_N for the block-triangular P (tri = 1), v_N for P = I (tri = 0)
+__global__ void k_gm_op(const double* __restrict__ y, const double* __restrict__ th, const double* __restrict__ z,
+                        const double* __restrict__ kyz, int64_t N, const double* __restrict__ ytz,
+                        const double* __restrict__ v, int tri, double* __restrict__ w) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    const double d = *ytz;
+    if (i < N) {
+        const double zl = tri ? -d - v[N] : v[N];
+        w[i] = y[i] * kyz[i] + th[i] * z[i] - y[i] * zl;
+    } else if (i == N) {
+        w[N] = -d;
+    }
+}
+
+// r = b - A x, with kx = K (y o x) and ytx = y^T x (device)
+__global__ void k_gm_resid(const double* __restrict__ y, const double* __restrict__ th, const double* __restrict__ x,
+                           const double* __restrict__ kx, int64_t N, const double* __restrict__ ytx,
+                           const double* __restrict__ b, double* __restrict__ r) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) r[i] = b[i] - (y[i] * kx[i] + th[i] * x[i] - y[i] * x[N]);
+    else if (i == N) r[N] = b[N] + *ytx;
+}
+
+// x += P^{-1} u, given z = (P^{-1} u)_{1..N} and ytz = y^T z (device)
+__global__ void k_gm_fin(const double* __restrict__ z, const double* __restrict__ ytz, const double* __restrict__ u,
+                         int64_t N, int tri, double* __restrict__ x) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < N) x[i] += z[i];
+    else if (i == N) x[N] += tri ? -*ytz - u[N] : u[N];
+}
+
+__global__ void k_scale(double* __restrict__ x, int64_t n, double s) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) x[i] *= s;
 }
 
 // Woodbury apply, first half: u = y * r / theta (written to tmp)
@@ -1421,6 +1507,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     ANV_CHECK(std::isfinite(o.mu0) && o.tol > 0.0 && o.tol_inf > 0.0 && o.tol_kry > 0.0,
               "tolerances must be > 0 and mu0 finite");
     ANV_CHECK(o.mu_rule == 0 || o.mu_rule == 1, "mu_rule must be 0 or 1");
+    ANV_CHECK(o.krylov == ANOVA_KRYLOV_MINRES || o.krylov == ANOVA_KRYLOV_GMRES, "krylov must be MINRES or GMRES");
     ANV_CHECK(o.precond == ANOVA_PRECOND_NONE || o.precond == ANOVA_PRECOND_PCHOL ||
                   o.precond == ANOVA_PRECOND_NYSTROM || o.precond == ANOVA_PRECOND_DIAG ||
                   o.precond == ANOVA_PRECOND_RPCHOL || o.precond == ANOVA_PRECOND_RFF,
@@ -1506,6 +1593,26 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     double lam = 0.0, mu = o.mu0;
     int matvecs = 0;
 
+    // GMRES storage: the Arnoldi basis (mr + 1 columns), P^{-1} v, partial inner
+    // products, device scalars and their pinned host mirror
+    const bool gmres = o.krylov == ANOVA_KRYLOV_GMRES;
+    const int mr = gmres ? std::min(kGmRestart, o.max_kry) : 0;  // restart length
+    DevBuf<double> gV, gz, gpart, gd;
+    const int64_t gldv = (n1 + 31) / 32 * 32;
+    const unsigned gnb = unsigned((n1 + kT * kGmRows - 1) / (kT * kGmRows));
+    double* gh = nullptr;
+    if (gmres) {
+        gV.alloc(size_t(mr + 1) * gldv);
+        gz.alloc(N);
+        gpart.alloc(size_t(gnb) * (mr + 1));
+        gd.alloc(3 * size_t(mr + 1) + 2);
+        ANV_HIP(hipHostMalloc(&gh, (3 * size_t(mr + 1) + 2) * sizeof(double)));
+    }
+    struct GhFree {
+        double* p;
+        ~GhFree() { if (p) (void)hipHostFree(p); }
+    } gh_guard{gh};
+
     DevBuf<double> spart, sout;
     spart.alloc(size_t(kRedBlocks) * 5);
     sout.alloc(8);
@@ -1572,11 +1679,13 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         const bool prec = o.precond != ANOVA_PRECOND_NONE;  // diag(A_hat, s); without a factor A_hat = Theta
         if (prec) {
             refresh_capacitance(pl, ws, th.p, st);
-            woodbury_apply(pl, ws, labels, th.p, labels, nullptr, false, ytmp.p, st);
-            s_last = red.dot(labels, ytmp.p, N, st);
-            if (!(s_last > 0.0)) {
-                status = ANOVA_NUMERICAL;
-                break;
+            if (!gmres) {
+                woodbury_apply(pl, ws, labels, th.p, labels, nullptr, false, ytmp.p, st);
+                s_last = red.dot(labels, ytmp.p, N, st);
+                if (!(s_last > 0.0)) {
+                    status = ANOVA_NUMERICAL;
+                    break;
+                }
             }
         }
         KryScal* ks = ksd.p;
@@ -1595,131 +1704,230 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         // iterations are replayed from graphs.
         const double rtol = std::max(1e-10, std::min(o.tol_kry, 0.1 * G));
         const int kcap = prec ? o.max_kry : std::max<int64_t>(o.max_kry, 2 * n1);
-        hipLaunchKernelGGL(k_kry_start, dim3(1), dim3(1), 0, st, ks, rtol, s_last);
-        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, sol.p, n1, 0.0);
-        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, rprev.p, n1, 0.0);
-        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d1.p, n1, 0.0);
-        hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d2.p, n1, 0.0);
-        hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, rhs.p, rcur.p, n1);
-        precond(rcur.p, zcur.p);
         int kit = 0;
-        if (hook) {
-            // matvecs through a hook (shared launches of a server or grid): the
-            // host keeps the scalars and waits for each inner product
-            double beta = std::sqrt(std::max(0.0, red.dot(rcur.p, zcur.p, n1, st)));
-            const double beta1 = beta;
-            double beta_prev = 0.0, c = -1.0, s = 0.0, dbar = 0.0, eps_next = 0.0, phibar = beta1;
-            double* rp = rprev.p;
-            double* rc = rcur.p;
-            double* zc = zcur.p;
-            double* zo = zold.p;
-            double* pp = pv.p;
-            if (beta1 > 0.0) {
-                while (kit < kcap) {
-                    ++kit;
-                    // p = A (z / beta) - (beta / beta_prev) r_prev
-                    hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+        if (gmres) {
+            // ---- GMRES preconditioned from the right with the block-triangular
+            // P = [[A_hat, 0], [-y^T, -1]] of Section 5 (P = I without a preconditioner),
+            // restarted every mr steps. Arnoldi by classical Gram-Schmidt applied twice
+            // (two passes of basis inner products, each one launch), least squares by
+            // Givens rotations on the host; |g_{j+1}| is the residual ||rhs - A sol|| of
+            // the iterate and is tested against rtol ||rhs||.
+            const int64_t hn_at = 2 * int64_t(mr + 1), ytz_at = hn_at + 1, cf_at = hn_at + 2;
+            double* const ytz_d = gd.p + ytz_at;
+            const int tri = prec ? 1 : 0;
+            // first N entries of P^{-1} v, and y^T of them to ytz_d
+            auto pinv_head = [&](const double* v) -> const double* {
+                const double* z = v;
+                if (prec) {
+                    woodbury_apply(pl, ws, labels, th.p, v, nullptr, false, gz.p, st);
+                    z = gz.p;
+                }
+                red.dot_dev(labels, z, N, ytz_d, st);
+                return z;
+            };
+            std::vector<double> H(size_t(mr + 1) * mr), cs(mr), sn(mr), g(mr + 1), tv(mr);
+            hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, sol.p, n1, 0.0);
+            const double beta0 = std::sqrt(std::max(0.0, red.dot(rhs.p, rhs.p, n1, st)));
+            double beta = beta0;
+            if (beta0 > 0.0) hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, rhs.p, gV.p, n1);
+            while (beta > rtol * beta0 && kit < kcap) {
+                // one cycle from the residual in the basis' first column
+                hipLaunchKernelGGL(k_scale, dim3(nblk(n1)), dim3(kT), 0, st, gV.p, n1, 1.0 / beta);
+                std::fill(g.begin(), g.end(), 0.0);
+                g[0] = beta;
+                int jj = 0;
+                double res = beta;
+                while (jj < mr && kit < kcap) {
+                    const double* vj = gV.p + jj * gldv;
+                    double* w = gV.p + (jj + 1) * gldv;
+                    const double* z = pinv_head(vj);
+                    hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, z, N, ws.tmp.p);
                     kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
                     ++matvecs;
-                    const double ytz = red.dot(labels, zc, N, st);
-                    const double cprev = kit > 1 ? beta / beta_prev : 0.0;
-                    hipLaunchKernelGGL(k_newton_out_v, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N,
-                                       1.0 / beta, cprev, rp, -ytz, pp);
-                    const double a = red.dot(zc, pp, n1, st) / beta;
-                    hipLaunchKernelGGL(k_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, -a / beta);
-                    // rotate r_prev <- r_cur <- p; z_old <- z_cur; z_cur <- M^{-1} r_cur
-                    std::swap(rp, rc);
-                    std::swap(rc, pp);
-                    std::swap(zo, zc);
-                    precond(rc, zc);
-                    beta_prev = beta;
-                    beta = std::sqrt(std::max(0.0, red.dot(rc, zc, n1, st)));
-                    const double eps_cur = eps_next;
-                    const double delta = c * dbar + s * a;
-                    const double gbar = s * dbar - c * a;
-                    eps_next = s * beta;
-                    dbar = -c * beta;
-                    double gam = hypot_ieee(gbar, beta);
-                    if (gam == 0.0) gam = 1e-300;
-                    c = gbar / gam;
-                    s = beta / gam;
-                    const double phi = c * phibar;
-                    phibar = s * phibar;
-                    hipLaunchKernelGGL(k_minres_update_v, dim3(nblk(n1)), dim3(kT), 0, st, zo, n1, 1.0 / beta_prev,
-                                       eps_cur, delta, 1.0 / gam, phi, d1.p, d2.p, sol.p);
-                    if (!(phibar > rtol * beta1) || !(beta > 0.0)) break;
-                }
-            }
-        } else {
-            red.dot_dev(rcur.p, zcur.p, n1, &ks->dot_rz, st);
-            hipLaunchKernelGGL(k_kry_beta1, dim3(1), dim3(1), 0, st, ks);
-            // iteration j starts with r_prev, r, p = Rb[j], Rb[j + 1], Rb[j + 2] (mod 3) and
-            // z, z_old = Zb[j], Zb[j + 1] (mod 2): the buffers rotate with period 6
-            double* const Rb[3] = {rprev.p, rcur.p, pv.p};
-            double* const Zb[2] = {zcur.p, zold.p};
-            auto iteration = [&](int j) {
-                double* rp = Rb[j % 3];
-                double* rc = Rb[(j + 1) % 3];
-                double* pp = Rb[(j + 2) % 3];
-                double* zc = Zb[j % 2];
-                double* zo = Zb[(j + 1) % 2];
-                // p = A (z / beta) - (beta / beta_prev) r_prev; p -= (z^T p / beta^2) r
-                hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
-                red.dot_dev(labels, zc, N, &ks->dot_ytz, st);
-                kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
-                hipLaunchKernelGGL(k_newton_out, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N, ks, rp,
-                                   pp);
-                red.dot_dev(zc, pp, n1, &ks->dot_a, st);
-                hipLaunchKernelGGL(k_kry_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, ks);
-                // p becomes the residual r; its preconditioned form goes to z_old's buffer
-                precond(pp, zo);
-                red.dot_dev(pp, zo, n1, &ks->dot_rz, st);
-                hipLaunchKernelGGL(k_kry_scalars, dim3(1), dim3(1), 0, st, ks);
-                hipLaunchKernelGGL(k_minres_update, dim3(nblk(n1)), dim3(kT), 0, st, zc, n1, ks, d1.p, d2.p, sol.p);
-            };
-            for (int j = 0; j < kcap; ++j) {
-                const int state = j % 6;
-                if (use_graphs && warmed) {
-                    if (!kr.g[state]) {
-                        // capture once per solve: every kernel argument is fixed for the solve
-                        hipGraph_t g = nullptr;
-                        ANV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                        try {
-                            iteration(state);
-                        } catch (...) {
-                            hipGraph_t tmp = nullptr;
-                            (void)hipStreamEndCapture(st, &tmp);
-                            if (tmp) (void)hipGraphDestroy(tmp);
-                            throw;
-                        }
-                        ANV_HIP(hipStreamEndCapture(st, &g));
-                        const hipError_t e = hipGraphInstantiate(&kr.g[state], g, nullptr, nullptr, 0);
-                        (void)hipGraphDestroy(g);
-                        ANV_HIP(e);
+                    hipLaunchKernelGGL(k_gm_op, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, z, ws.kyz.p, N, ytz_d,
+                                       vj, tri, w);
+                    const int nc = jj + 1;
+                    for (int pass = 0; pass < 2; ++pass) {
+                        double* h = gd.p + pass * int64_t(mr + 1);
+                        hipLaunchKernelGGL(k_gm_dots, dim3(gnb), dim3(kT), 0, st, gV.p, gldv, nc, w, n1, gpart.p);
+                        hipLaunchKernelGGL(k_fold_partials, dim3(nc), dim3(64), 0, st, gpart.p, int(gnb), nc, h);
+                        hipLaunchKernelGGL(k_gm_sub, dim3(nblk(n1)), dim3(kT), 0, st, gV.p, gldv, nc, h, 1, n1, w);
                     }
-                    ANV_HIP(hipGraphLaunch(kr.g[state], st));
-                } else {
-                    iteration(j);
-                    warmed = true;
+                    red.dot_dev(w, w, n1, gd.p + hn_at, st);
+                    ANV_HIP(hipMemcpyAsync(gh, gd.p, (hn_at + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+                    host_wait(st);
+                    double* hc = &H[size_t(jj) * (mr + 1)];
+                    for (int i = 0; i < nc; ++i) hc[i] = gh[i] + gh[mr + 1 + i];
+                    const double hn = std::sqrt(std::max(0.0, gh[hn_at]));
+                    hc[nc] = hn;
+                    if (hn > 0.0) hipLaunchKernelGGL(k_scale, dim3(nblk(n1)), dim3(kT), 0, st, w, n1, 1.0 / hn);
+                    for (int i = 0; i < jj; ++i) {  // the earlier rotations on the new column
+                        const double a = hc[i], b = hc[i + 1];
+                        hc[i] = cs[i] * a + sn[i] * b;
+                        hc[i + 1] = -sn[i] * a + cs[i] * b;
+                    }
+                    double rho = hypot_ieee(hc[jj], hc[jj + 1]);
+                    if (rho == 0.0) rho = 1e-300;
+                    cs[jj] = hc[jj] / rho;
+                    sn[jj] = hc[jj + 1] / rho;
+                    hc[jj] = rho;
+                    hc[jj + 1] = 0.0;
+                    g[jj + 1] = -sn[jj] * g[jj];
+                    g[jj] = cs[jj] * g[jj];
+                    ++jj;
+                    ++kit;
+                    res = std::fabs(g[jj]);
+                    if (!(res > rtol * beta0) || !(hn > 0.0)) break;
                 }
+                // sol += P^{-1} V t, R t = g by back substitution (coefficients go
+                // to the device negated: k_gm_sub subtracts)
+                for (int i = jj - 1; i >= 0; --i) {
+                    double acc = g[i];
+                    for (int c = i + 1; c < jj; ++c) acc -= H[size_t(c) * (mr + 1) + i] * tv[c];
+                    tv[i] = acc / H[size_t(i) * (mr + 1) + i];
+                    gh[cf_at + i] = -tv[i];
+                }
+                ANV_HIP(hipMemcpyAsync(gd.p + cf_at, gh + cf_at, jj * sizeof(double), hipMemcpyHostToDevice, st));
+                hipLaunchKernelGGL(k_gm_sub, dim3(nblk(n1)), dim3(kT), 0, st, gV.p, gldv, jj, gd.p + cf_at, 0, n1, pv.p);
+                const double* zu = pinv_head(pv.p);
+                hipLaunchKernelGGL(k_gm_fin, dim3(nblk(n1)), dim3(kT), 0, st, zu, ytz_d, pv.p, N, tri, sol.p);
+                if (!(res > rtol * beta0) || kit >= kcap) break;
+                // restart from the residual of the iterate
+                hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, sol.p, N, ws.tmp.p);
+                kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
                 ++matvecs;
-                // the iteration's done flag, in stream order, to the host
-                ANV_HIP(hipMemcpyAsync(kr.hflag + (j & 1), &ks->done, sizeof(int), hipMemcpyDeviceToHost, st));
-                ANV_HIP(hipEventRecord(kr.fev[j & 1], st));
-                // the first iterations are checked at once (a well-preconditioned
-                // solve takes only a few); later ones one iteration late, so that
-                // the GPU always has the next iteration queued
-                if (j < kEagerChecks) {
-                    ANV_HIP(hipEventSynchronize(kr.fev[j & 1]));
-                    if (kr.hflag[j & 1]) break;
-                } else {
-                    ANV_HIP(hipEventSynchronize(kr.fev[(j - 1) & 1]));
-                    if (kr.hflag[(j - 1) & 1]) break;
-                }
+                red.dot_dev(labels, sol.p, N, ytz_d, st);
+                hipLaunchKernelGGL(k_gm_resid, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, sol.p, ws.kyz.p, N,
+                                   ytz_d, rhs.p, gV.p);
+                beta = std::sqrt(std::max(0.0, red.dot(gV.p, gV.p, n1, st)));
             }
-            ANV_HIP(hipMemcpyAsync(kr.hflag + 2, &ks->kit, sizeof(int), hipMemcpyDeviceToHost, st));
             host_wait(st);
-            kit = kr.hflag[2];
+        } else {
+            hipLaunchKernelGGL(k_kry_start, dim3(1), dim3(1), 0, st, ks, rtol, s_last);
+            hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, sol.p, n1, 0.0);
+            hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, rprev.p, n1, 0.0);
+            hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d1.p, n1, 0.0);
+            hipLaunchKernelGGL(k_fill, dim3(nblk(n1)), dim3(kT), 0, st, d2.p, n1, 0.0);
+            hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, rhs.p, rcur.p, n1);
+            precond(rcur.p, zcur.p);
+            if (hook) {
+                // matvecs through a hook (shared launches of a server or grid): the
+                // host keeps the scalars and waits for each inner product
+                double beta = std::sqrt(std::max(0.0, red.dot(rcur.p, zcur.p, n1, st)));
+                const double beta1 = beta;
+                double beta_prev = 0.0, c = -1.0, s = 0.0, dbar = 0.0, eps_next = 0.0, phibar = beta1;
+                double* rp = rprev.p;
+                double* rc = rcur.p;
+                double* zc = zcur.p;
+                double* zo = zold.p;
+                double* pp = pv.p;
+                if (beta1 > 0.0) {
+                    while (kit < kcap) {
+                        ++kit;
+                        // p = A (z / beta) - (beta / beta_prev) r_prev
+                        hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+                        kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
+                        ++matvecs;
+                        const double ytz = red.dot(labels, zc, N, st);
+                        const double cprev = kit > 1 ? beta / beta_prev : 0.0;
+                        hipLaunchKernelGGL(k_newton_out_v, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N,
+                                           1.0 / beta, cprev, rp, -ytz, pp);
+                        const double a = red.dot(zc, pp, n1, st) / beta;
+                        hipLaunchKernelGGL(k_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, -a / beta);
+                        // rotate r_prev <- r_cur <- p; z_old <- z_cur; z_cur <- M^{-1} r_cur
+                        std::swap(rp, rc);
+                        std::swap(rc, pp);
+                        std::swap(zo, zc);
+                        precond(rc, zc);
+                        beta_prev = beta;
+                        beta = std::sqrt(std::max(0.0, red.dot(rc, zc, n1, st)));
+                        const double eps_cur = eps_next;
+                        const double delta = c * dbar + s * a;
+                        const double gbar = s * dbar - c * a;
+                        eps_next = s * beta;
+                        dbar = -c * beta;
+                        double gam = hypot_ieee(gbar, beta);
+                        if (gam == 0.0) gam = 1e-300;
+                        c = gbar / gam;
+                        s = beta / gam;
+                        const double phi = c * phibar;
+                        phibar = s * phibar;
+                        hipLaunchKernelGGL(k_minres_update_v, dim3(nblk(n1)), dim3(kT), 0, st, zo, n1, 1.0 / beta_prev,
+                                           eps_cur, delta, 1.0 / gam, phi, d1.p, d2.p, sol.p);
+                        if (!(phibar > rtol * beta1) || !(beta > 0.0)) break;
+                    }
+                }
+            } else {
+                red.dot_dev(rcur.p, zcur.p, n1, &ks->dot_rz, st);
+                hipLaunchKernelGGL(k_kry_beta1, dim3(1), dim3(1), 0, st, ks);
+                // iteration j starts with r_prev, r, p = Rb[j], Rb[j + 1], Rb[j + 2] (mod 3) and
+                // z, z_old = Zb[j], Zb[j + 1] (mod 2): the buffers rotate with period 6
+                double* const Rb[3] = {rprev.p, rcur.p, pv.p};
+                double* const Zb[2] = {zcur.p, zold.p};
+                auto iteration = [&](int j) {
+                    double* rp = Rb[j % 3];
+                    double* rc = Rb[(j + 1) % 3];
+                    double* pp = Rb[(j + 2) % 3];
+                    double* zc = Zb[j % 2];
+                    double* zo = Zb[(j + 1) % 2];
+                    // p = A (z / beta) - (beta / beta_prev) r_prev; p -= (z^T p / beta^2) r
+                    hipLaunchKernelGGL(k_mul, dim3(nblk(N)), dim3(kT), 0, st, labels, zc, N, ws.tmp.p);
+                    red.dot_dev(labels, zc, N, &ks->dot_ytz, st);
+                    kmv(pl, hook, ws.tmp.p, ws.kyz.p, st);
+                    hipLaunchKernelGGL(k_newton_out, dim3(nblk(n1)), dim3(kT), 0, st, labels, th.p, zc, ws.kyz.p, N, ks, rp,
+                                       pp);
+                    red.dot_dev(zc, pp, n1, &ks->dot_a, st);
+                    hipLaunchKernelGGL(k_kry_axpy, dim3(nblk(n1)), dim3(kT), 0, st, pp, rc, n1, ks);
+                    // p becomes the residual r; its preconditioned form goes to z_old's buffer
+                    precond(pp, zo);
+                    red.dot_dev(pp, zo, n1, &ks->dot_rz, st);
+                    hipLaunchKernelGGL(k_kry_scalars, dim3(1), dim3(1), 0, st, ks);
+                    hipLaunchKernelGGL(k_minres_update, dim3(nblk(n1)), dim3(kT), 0, st, zc, n1, ks, d1.p, d2.p, sol.p);
+                };
+                for (int j = 0; j < kcap; ++j) {
+                    const int state = j % 6;
+                    if (use_graphs && warmed) {
+                        if (!kr.g[state]) {
+                            // capture once per solve: every kernel argument is fixed for the solve
+                            hipGraph_t g = nullptr;
+                            ANV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                            try {
+                                iteration(state);
+                            } catch (...) {
+                                hipGraph_t tmp = nullptr;
+                                (void)hipStreamEndCapture(st, &tmp);
+                                if (tmp) (void)hipGraphDestroy(tmp);
+                                throw;
+                            }
+                            ANV_HIP(hipStreamEndCapture(st, &g));
+                            const hipError_t e = hipGraphInstantiate(&kr.g[state], g, nullptr, nullptr, 0);
+                            (void)hipGraphDestroy(g);
+                            ANV_HIP(e);
+                        }
+                        ANV_HIP(hipGraphLaunch(kr.g[state], st));
+                    } else {
+                        iteration(j);
+                        warmed = true;
+                    }
+                    ++matvecs;
+                    // the iteration's done flag, in stream order, to the host
+                    ANV_HIP(hipMemcpyAsync(kr.hflag + (j & 1), &ks->done, sizeof(int), hipMemcpyDeviceToHost, st));
+                    ANV_HIP(hipEventRecord(kr.fev[j & 1], st));
+                    // the first iterations are checked at once (a well-preconditioned
+                    // solve takes only a few); later ones one iteration late, so that
+                    // the GPU always has the next iteration queued
+                    if (j < kEagerChecks) {
+                        ANV_HIP(hipEventSynchronize(kr.fev[j & 1]));
+                        if (kr.hflag[j & 1]) break;
+                    } else {
+                        ANV_HIP(hipEventSynchronize(kr.fev[(j - 1) & 1]));
+                        if (kr.hflag[(j - 1) & 1]) break;
+                    }
+                }
+                ANV_HIP(hipMemcpyAsync(kr.hflag + 2, &ks->kit, sizeof(int), hipMemcpyDeviceToHost, st));
+                host_wait(st);
+                kit = kr.hflag[2];
+            }
         }
         kry_total += kit;
         kry_max = std::max(kry_max, kit);
