@@ -575,27 +575,51 @@ __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ 
         f4{float(o[0]), float(o[1]), float(o[2]), float(o[3])};
 }
 
-// fold step B + y and z passes; block per (x slice, window, half of the rhs)
+// Blocks are dealt to the 8 XCDs in turn (block i to XCD i mod 8). The nrs
+// right-hand-side slices of one (slice, window) group go to one XCD back to
+// back, so that the slices after the first find the group's 64-byte rows (all
+// 16 right-hand sides) in that XCD's L2. Group g = window * ne + slice; blocks
+// past the last group return.
+__device__ inline bool xcd_group(int nrs, int ne, int ngroups, int& slice, int& l, int& rs) {
+    const int b = int(blockIdx.x), k = b >> 3;
+    rs = k % nrs;
+    const int g = (k / nrs) * 8 + (b & 7);
+    l = g / ne;
+    slice = g % ne;
+    return g < ngroups;
+}
+
+// fold step B + y and z passes; block per (x slice, window, slice of the rhs)
 template <int W>
 __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restrict__ wins,
                                                          const double* __restrict__ tmat,
                                                          const int2* __restrict__ crange,
                                                          const float* __restrict__ tgt, float* __restrict__ g1,
-                                                         int RH) {
-    extern __shared__ float smf[];
-    const int l = blockIdx.y;
+                                                         int RH, int ne, int P) {
+    extern __shared__ __align__(16) float smf[];
+    int x, l, rs;
+    if (!xcd_group(RB / RH, ne, ne * P, x, l, rs)) return;
     const WinDev& wd = wins[l];
-    const int x = blockIdx.x;
-    const int r0 = blockIdx.z * RH;
+    const int r0 = rs * RH;
     if (x >= wd.E[0]) return;
     const int Ey = wd.E[1], Ez = wd.E[2];
+    const int Eyp = (Ey + 3) & ~3, Ezp = (Ez + 3) & ~3;
     const int S = Ey * Ez;
-    float* s0 = smf;            // [y][z][RH]
-    float* s1 = smf + S * RH;
-    float* ty = s1 + S * RH;
-    float* tz = ty + Ey * Ey;
-    for (int e = threadIdx.x; e < Ey * Ey; e += blockDim.x) ty[e] = float(tmat[wd.t_off[1] + e]);
-    for (int e = threadIdx.x; e < Ez * Ez; e += blockDim.x) tz[e] = float(tmat[wd.t_off[2] + e]);
+    // Toeplitz matrices transposed, rows padded to a multiple of 4 with zeros:
+    // tyT[k][y] = Ty[y][k], so that 4 consecutive outputs read their 4
+    // coefficients of tap k in one 16-byte access
+    float* tyT = smf;
+    float* tzT = tyT + Ey * Eyp;
+    float* s0 = tzT + Ez * Ezp;  // [y][z][RH]
+    float* s1 = s0 + S * RH;
+    for (int e = threadIdx.x; e < Ey * Eyp; e += blockDim.x) {
+        const int k = e / Eyp, y = e % Eyp;
+        tyT[e] = y < Ey ? float(tmat[wd.t_off[1] + y * Ey + k]) : 0.f;
+    }
+    for (int e = threadIdx.x; e < Ez * Ezp; e += blockDim.x) {
+        const int k = e / Ezp, z = e % Ezp;
+        tzT[e] = z < Ez ? float(tmat[wd.t_off[2] + z * Ez + k]) : 0.f;
+    }
     __shared__ int2 rng[W][65];
     const int wx = wd.Wslot[0], wy = wd.Wslot[1], nby = wd.nb[1];
     for (int e = threadIdx.x; e < W * nby; e += blockDim.x) {
@@ -604,6 +628,8 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
                                                             : make_int2(1, 0);
     }
     __syncthreads();
+    // fold step B: s0[y][z][r] = sum over the footprint positions (a, b) whose
+    // column holds points at layers reaching z, in (a, b) order
     for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
         const int cell = e / RH, r = e % RH;
         const int y = cell / Ez, zz = cell % Ez;
@@ -615,6 +641,9 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
             for (int b = 0; b < W; ++b) {
                 const int cyy = y - b;
                 const int2 rr = (b < wy && cyy >= 0 && cyy < nby) ? rng[a][cyy] : make_int2(1, 0);
+                // the target holds no valid value where the position's column has
+                // no points reaching layer z; every lane loads (a valid address) so
+                // that all 64 loads are in flight at once, and the select drops it
                 const bool ok = zz >= rr.x && zz <= rr.y;
                 const float v = tl[ok ? int64_t(a * wy + b) * Ez * RB : 0];
                 acc += ok ? v : 0.f;
@@ -622,69 +651,123 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
         s0[e] = acc;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
-        const int cell = e / RH, r = e % RH;
-        const int y = cell / Ez, zz = cell % Ez;
-        float acc = 0.f;
-        for (int k = 0; k < Ey; ++k) acc += ty[y * Ey + k] * s0[(k * Ez + zz) * RH + r];
-        s1[e] = acc;
+    // y pass, s1[y][z][r] = sum_k Ty[y][k] s0[k][z][r] (k ascending); a thread
+    // makes y = y0 .. y0 + 3 from one read of s0 per tap
+    for (int e = threadIdx.x; e < (Eyp / 4) * Ez * RH; e += blockDim.x) {
+        const int r = e % RH, zz = (e / RH) % Ez, y0 = 4 * (e / (RH * Ez));
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int k = 0; k < Ey; ++k) {
+            const float v = s0[(k * Ez + zz) * RH + r];
+            const f4 t = *reinterpret_cast<const f4*>(tyT + k * Eyp + y0);
+            a0 += t[0] * v;
+            a1 += t[1] * v;
+            a2 += t[2] * v;
+            a3 += t[3] * v;
+        }
+        const float av[4] = {a0, a1, a2, a3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (y0 + i < Ey) s1[((y0 + i) * Ez + zz) * RH + r] = av[i];
     }
     __syncthreads();
+    // z pass, g1[x][y][z][r] = sum_k Tz[z][k] s1[y][k][r]; z = z0 .. z0 + 3 per thread
     float* out = g1 + (wd.grid_off + int64_t(x) * S) * RB + r0;
-    for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
-        const int cell = e / RH, r = e % RH;
-        const int y = cell / Ez, zz = cell % Ez;
-        float acc = 0.f;
-        for (int k = 0; k < Ez; ++k) acc += tz[zz * Ez + k] * s1[(y * Ez + k) * RH + r];
-        out[int64_t(cell) * RB + r] = acc;
+    for (int e = threadIdx.x; e < Ey * (Ezp / 4) * RH; e += blockDim.x) {
+        const int r = e % RH, z0 = 4 * ((e / RH) % (Ezp / 4)), y = e / (RH * (Ezp / 4));
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int k = 0; k < Ez; ++k) {
+            const float v = s1[(y * Ez + k) * RH + r];
+            const f4 t = *reinterpret_cast<const f4*>(tzT + k * Ezp + z0);
+            a0 += t[0] * v;
+            a1 += t[1] * v;
+            a2 += t[2] * v;
+            a3 += t[3] * v;
+        }
+        const float av[4] = {a0, a1, a2, a3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (z0 + i < Ez) out[int64_t(y * Ez + z0 + i) * RB + r] = av[i];
     }
 }
 
 // x pass; block per (y slice, window, rhs half); output h[x][z][y][rhs]
 __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
-                                                   const float* __restrict__ g1, float* __restrict__ h, int RH) {
-    extern __shared__ float smf[];
-    const int l = blockIdx.y;
+                                                   const float* __restrict__ g1, float* __restrict__ h, int RH, int ne,
+                                                   int P) {
+    extern __shared__ __align__(16) float smf[];
+    int y, l, rs;
+    if (!xcd_group(RB / RH, ne, ne * P, y, l, rs)) return;
     const WinDev& wd = wins[l];
-    const int y = blockIdx.x;
-    const int r0 = blockIdx.z * RH;
+    const int r0 = rs * RH;
     if (y >= wd.E[1]) return;
     const int Ex = wd.E[0], Ey = wd.E[1], Ez = wd.E[2];
-    float* sl = smf;                 // [x][z][RH]
-    float* tx = smf + Ex * Ez * RH;
-    for (int e = threadIdx.x; e < Ex * Ex; e += blockDim.x) tx[e] = float(tmat[wd.t_off[0] + e]);
+    const int Exp = (Ex + 3) & ~3;
+    float* txT = smf;                // txT[k][x] = Tx[x][k], rows padded to Exp
+    float* sl = smf + Ex * Exp;      // [x][z][RH]
+    for (int e = threadIdx.x; e < Ex * Exp; e += blockDim.x) {
+        const int k = e / Exp, xx = e % Exp;
+        txT[e] = xx < Ex ? float(tmat[wd.t_off[0] + xx * Ex + k]) : 0.f;
+    }
     for (int e = threadIdx.x; e < Ex * Ez * RH; e += blockDim.x) {
         const int xz = e / RH, r = e % RH;
         const int xx = xz / Ez, zz = xz % Ez;
         sl[e] = g1[(wd.grid_off + (int64_t(xx) * Ey + y) * Ez + zz) * RB + r0 + r];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < Ex * Ez * RH; e += blockDim.x) {
-        const int xz = e / RH, r = e % RH;
-        const int xx = xz / Ez, zz = xz % Ez;
-        float acc = 0.f;
-        for (int k = 0; k < Ex; ++k) acc += tx[xx * Ex + k] * sl[(k * Ez + zz) * RH + r];
-        h[(wd.grid_off + (int64_t(xx) * Ez + zz) * Ey + y) * RB + r0 + r] = acc;
+    // h[x][z][y][r] = sum_k Tx[x][k] g1[k][y][z][r] (k ascending); x = x0 .. x0 + 3 per thread
+    for (int e = threadIdx.x; e < (Exp / 4) * Ez * RH; e += blockDim.x) {
+        const int r = e % RH, zz = (e / RH) % Ez, x0 = 4 * (e / (RH * Ez));
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        for (int k = 0; k < Ex; ++k) {
+            const float v = sl[(k * Ez + zz) * RH + r];
+            const f4 t = *reinterpret_cast<const f4*>(txT + k * Exp + x0);
+            a0 += t[0] * v;
+            a1 += t[1] * v;
+            a2 += t[2] * v;
+            a3 += t[3] * v;
+        }
+        const float av[4] = {a0, a1, a2, a3};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (x0 + i < Ex) h[(wd.grid_off + (int64_t(x0 + i) * Ez + zz) * Ey + y) * RB + r0 + r] = av[i];
     }
 }
 
 // y_r[i] = sum_l eta_l f_l(i, r), windows in order, FP64; 64 points per
-// block, transposed through LDS for coalesced stores
+// block, a thread takes 4 right-hand sides of one point; the windows' rows are
+// loaded 8 at a time, all in flight together; transposed through LDS for
+// coalesced stores
+constexpr int kWsChunk = 8;
 __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ fs, const int32_t* __restrict__ pos,
                                                       const WinDev* __restrict__ wins, int32_t P, int64_t N, int R,
                                                       const ColPtrs cols) {
     __shared__ double s[RB][65];
     const int64_t i0 = int64_t(blockIdx.x) * 64;
+    const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int64_t gi = i0 + i;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (gi < N) {
+        for (int l0 = 0; l0 < P; l0 += kWsChunk) {
+            int32_t pp[kWsChunk];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int e = j * 256 + threadIdx.x;
-        const int i = e / RB, r = e % RB;
-        double acc = 0.0;
-        if (i0 + i < N)
-            for (int l = 0; l < P; ++l)
-                acc += wins[l].eta * double(fs[(int64_t(l) * N + pos[int64_t(l) * N + i0 + i]) * RB + r]);
-        s[r][i] = acc;
+            for (int j = 0; j < kWsChunk; ++j) pp[j] = l0 + j < P ? pos[int64_t(l0 + j) * N + gi] : 0;
+            f4 v[kWsChunk];
+#pragma unroll
+            for (int j = 0; j < kWsChunk; ++j)
+                v[j] = l0 + j < P ? *reinterpret_cast<const f4*>(fs + (int64_t(l0 + j) * N + pp[j]) * RB + 4 * q)
+                                  : f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int j = 0; j < kWsChunk; ++j) {
+                if (l0 + j < P) {
+                    const double eta = wins[l0 + j].eta;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] += eta * double(v[j][c]);
+                }
+            }
+        }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[4 * q + c][i] = acc[c];
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -764,8 +847,9 @@ void ensure_batched_buffers(Plan& pl) {
     // right-hand sides per grid-step block: as many as the LDS budget allows
     const int64_t ex = pl.emax[0], ey = pl.emax[1], ez = pl.emax[2];
     pl.b_rsplit = 1;
-    while (pl.b_rsplit < RB && ((2 * ey * ez * (RB / pl.b_rsplit) + ey * ey + ez * ez) * 4 > 65536 ||
-                                (ex * ez * (RB / pl.b_rsplit) + ex * ex) * 4 > 65536))
+    const int64_t exp = (ex + 3) & ~3, eyp = (ey + 3) & ~3, ezp = (ez + 3) & ~3;
+    while (pl.b_rsplit < RB && ((2 * ey * ez * (RB / pl.b_rsplit) + ey * eyp + ez * ezp) * 4 > 65536 ||
+                                (ex * ez * (RB / pl.b_rsplit) + ex * exp) * 4 > 65536))
         pl.b_rsplit *= 2;
     pl.b_ready = true;
 }
@@ -797,13 +881,16 @@ void batched_pass(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
                            pl.flist.p, pl.fold.p, pl.sbase.p, pl.slabb.p, pl.tgtb.p);
     if (prof) pl.record_stage_event(st);
     const int RH = RB / pl.b_rsplit;
-    const size_t lds_yz =
-        size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pl.emax[1] + pl.emax[2] * pl.emax[2]) * sizeof(float);
-    hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(unsigned(pl.emax[0]), unsigned(pl.P), unsigned(pl.b_rsplit)),
-                       dim3(1024), lds_yz, st, pl.wins_d.p, pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH);
-    const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pl.emax[0]) * sizeof(float);
-    hipLaunchKernelGGL(k_conv_x_b, dim3(unsigned(pl.emax[1]), unsigned(pl.P), unsigned(pl.b_rsplit)), dim3(1024), lds_x,
-                       st, pl.wins_d.p, pl.tmat.p, pl.g1b.p, pl.hb.p, RH);
+    auto pad4 = [](int64_t e) { return (e + 3) & ~int64_t(3); };
+    const size_t lds_yz = size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pad4(pl.emax[1]) +
+                                 pl.emax[2] * pad4(pl.emax[2])) * sizeof(float);
+    // one block per (slice, window, right-hand-side slice), groups padded to a multiple of 8
+    auto xcd_blocks = [&](int64_t ne) { return unsigned((ne * pl.P + 7) / 8 * 8 * pl.b_rsplit); };
+    hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(xcd_blocks(pl.emax[0])), dim3(1024), lds_yz, st, pl.wins_d.p,
+                       pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH, int(pl.emax[0]), int(pl.P));
+    const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pad4(pl.emax[0])) * sizeof(float);
+    hipLaunchKernelGGL(k_conv_x_b, dim3(xcd_blocks(pl.emax[1])), dim3(1024), lds_x, st, pl.wins_d.p, pl.tmat.p,
+                       pl.g1b.p, pl.hb.p, RH, int(pl.emax[1]), int(pl.P));
     if (prof) pl.record_stage_event(st);
     if (pl.nwave[3])
         hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],

@@ -41,6 +41,24 @@ def test_two_passes_with_ragged_tail(dev):
     assert d <= 1e-5
 
 
+@pytest.mark.parametrize("n_bw,sigma", [(24, 0.7), (24, 1.3), (40, 0.9), (16, 2.0), (48, 0.5)])
+def test_bandwidths_and_grid_boxes_of_any_size(dev, n_bw, sigma):
+    # occupied boxes whose sides are not all multiples of the 4 outputs a thread
+    # of the grid-step passes makes: the batched kernels against the one-vector
+    # kernels of the same plan options (same approximation, independent code)
+    p = workloads.gaussian_mixture(seed=9, N=1200, d=9, sigma=sigma, R=16)
+    pl = _plan(p, dev, n_bw=n_bw)
+    y = pl.matvec(to_dev(p.v, dev)).cpu().numpy()
+    y1 = _plan(p, dev, n_bw=n_bw, batch_min_rhs=-1).matvec(to_dev(p.v, dev)).cpu().numpy()
+    ref = oracle.anova_matvec(p.X, p.windows, p.sigma, p.v[:, :2])
+    d = max(rel_l2(y[:, r], y1[:, r]) for r in range(16))
+    e = max(rel_l2(y[:, r], ref[:, r]) for r in range(2))
+    print(f"n_bw={n_bw} sigma={sigma} grid_cells={pl.info()['grid_cells']} batched vs one-vector {d:.2e}, "
+          f"vs oracle {e:.2e}")
+    assert d <= 1e-5
+    assert e <= 1e-2
+
+
 @pytest.mark.parametrize("N,d,sigma,seed,R", [(37, 5, 0.5, 1, 3), (513, 7, 0.25, 2, 16), (1000, 4, 4.0, 3, 2),
                                               (3001, 3, 1.0, 4, 17), (257, 1, 0.3, 5, 5), (800, 2, 0.7, 6, 9)])
 def test_ragged_shapes_and_window_kinds(dev, N, d, sigma, seed, R):
