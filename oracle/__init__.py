@@ -20,6 +20,7 @@ Contents, each following the paper (arXiv 2312.00538):
     by forward substitution; gmres — right-preconditioned GMRES (Section 5).
   * objectives — dual objective (eq. "kernelsvm"), hinge-loss primal and the
     relative duality gap used as the stopping measure.
+  * mi_windows — windows of features by mutual-information ranking (Section 3).
 Readings where the paper is silent are listed in the design notes and repeated
 in the docstrings below.
 """
@@ -482,3 +483,61 @@ def gmres(A, b, apply_pinv, tol, maxit):
             break
     u = V[:, :j] @ np.linalg.solve(np.triu(H[:j, :j]), g[:j])
     return apply_pinv(u), j, hist
+
+
+# ----------------------------------------------------------------------------- windows (Section 3)
+
+def mi_bins(X, bins):
+    """Histogram bin of every entry: equal-width bins over each feature's range,
+    b = floor((x - min) * (bins / (max - min))) clamped to bins - 1 (all entries
+    of a constant feature fall in bin 0)."""
+    X = np.asarray(X, dtype=np.float64)
+    mn, mx = X.min(axis=0), X.max(axis=0)
+    B = np.zeros(X.shape, dtype=np.int64)
+    for f in range(X.shape[1]):
+        if mx[f] > mn[f]:
+            scale = bins / (mx[f] - mn[f])
+            B[:, f] = np.minimum(np.floor((X[:, f] - mn[f]) * scale).astype(np.int64), bins - 1)
+    return B
+
+
+def mutual_information(counts):
+    """Mutual information (nats) of a joint count table n[b][c] (rows: feature
+    bins, columns: classes): sum over n > 0 of (n / N) log(n N / (n_b n_c)),
+    bins in order, classes in order."""
+    counts = np.asarray(counts, dtype=np.int64)
+    Ntot = int(counts.sum())
+    nb = counts.sum(axis=1)
+    nc = counts.sum(axis=0)
+    mi = 0.0
+    for b in range(counts.shape[0]):
+        for c in range(counts.shape[1]):
+            n = int(counts[b, c])
+            if n > 0:
+                mi += (n / Ntot) * np.log(n * Ntot / (int(nb[b]) * int(nc[c])))
+    return mi
+
+
+def mi_windows(X, labels, bins, P):
+    """Windows of features by mutual-information ranking (Section 3 picks the
+    windows from the features' mutual information scores): each feature's
+    mutual information with the labels is estimated from its histogram
+    (mi_bins) against the two classes; features are ranked by it, largest
+    first, ties to the lower index; the windows are consecutive triples of the
+    ranking, the last one taking the remaining 1 or 2 features when 3P > d.
+    Returns (windows P x 3 int32 padded with -1, mi per feature, counts d x bins x 2)."""
+    X = np.asarray(X, dtype=np.float64)
+    y = np.asarray(labels)
+    N, d = X.shape
+    B = mi_bins(X, bins)
+    cls = (y > 0).astype(np.int64)            # class 0: -1, class 1: +1
+    counts = np.zeros((d, bins, 2), dtype=np.int64)
+    for f in range(d):
+        np.add.at(counts[f], (B[:, f], cls), 1)
+    mi = np.array([mutual_information(counts[f]) for f in range(d)])
+    rank = sorted(range(d), key=lambda f: (-mi[f], f))
+    W = np.full((P, 3), -1, dtype=np.int32)
+    for l in range(P):
+        feats = rank[3 * l: min(d, 3 * l + 3)]
+        W[l, :len(feats)] = feats
+    return W, mi, counts

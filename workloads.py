@@ -158,3 +158,23 @@ def cv_grid(seed: int = 0, N: int = 50_000, d: int = 15, folds: int = 5,
     Cs = np.geomspace(C_range[0], C_range[1], n_C)
     p.meta["workload"] = "cv-grid"
     return dict(problem=p, folds=out, sigmas=sigmas, Cs=Cs)
+
+
+def graded_features(seed: int = 0, N: int = 20_000, d: int = 14, order=None) -> Problem:
+    """Balanced +-1 labels and d features of graded relevance: feature f is
+    s_f * y + N(0, 1) with s_f = 2 (1 - rank_f / d), rank_f = order[f] (a
+    permutation of 0..d-1; the identity if None), so that feature order[f] = 0
+    carries the label most strongly and the last rank not at all; then
+    standardize+scale. Windows: consecutive, sigma = 1. The informative order
+    is stored in meta["order"]."""
+    rng = np.random.default_rng(seed)
+    y = np.where(np.arange(N) < N // 2, 1.0, -1.0)
+    y = y[rng.permutation(N)]
+    order = np.arange(d) if order is None else np.asarray(order)
+    s = 2.0 * (1.0 - order / d)
+    X = s[None, :] * y[:, None] + rng.standard_normal((N, d))
+    X = standardize_scale(X)
+    p = Problem(X=X, labels=y, windows=consecutive_windows(d), sigma=1.0)
+    p.meta["workload"] = "graded-features"
+    p.meta["order"] = order
+    return p
