@@ -465,6 +465,28 @@ int anova_autotune(const double* X, int64_t N, int32_t d, int64_t ldx, const int
                    const double* sigma, const double* eta, const anova_tune_opts* t, void* stream,
                    anova_opts* best, anova_tune_candidate* cands, int32_t max_cands, int32_t* n_cands);
 
+/* ------------------------------------------------------------------ windows
+ * Windows of features by mutual-information ranking (Section 3 builds the
+ * windows W_l from the features' mutual-information scores). Each feature's
+ * mutual information with the labels (nats) is estimated from a histogram of
+ * `bins` equal-width bins over the feature's range [min, max] against the two
+ * classes: bin floor((x - min) * (bins / (max - min))), clamped to bins - 1
+ * (a constant feature falls in bin 0), and the estimate is
+ * sum over n > 0 of (n / N) log(n N / (n_bin n_class)). The features are
+ * ranked by it, largest first, ties to the lower index, and window l holds
+ * the ranked features 3l, 3l + 1, 3l + 2 (the last window the remaining 1 or
+ * 2 when 3P > d), so the windows cover the min(3P, d) best features.
+ *   X        device, N x d row-major FP64, leading dimension ldx >= d; finite.
+ *   labels   device, N FP64; a label > 0 is class +1, any other class -1.
+ *   bins     2..1024.
+ *   P        number of windows, 1 <= P <= ceil(d / 3).
+ *   windows  host out, P x 3 int32, -1 padded (the layout anova_plan_create takes).
+ *   mi       host out (may be NULL), d FP64: the estimate per feature.
+ * Synchronises `stream`. Errors: ANOVA_INVALID_ARG (sizes, NaN/Inf in X),
+ * ANOVA_OUT_OF_MEMORY, ANOVA_HIP_ERROR. */
+int anova_mi_windows(const double* X, int64_t N, int32_t d, int64_t ldx, const double* labels, int32_t bins,
+                     int32_t P, int32_t* windows, double* mi, void* stream);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char* anova_last_error(void);
 

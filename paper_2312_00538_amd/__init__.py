@@ -28,7 +28,7 @@ EXPORTED = [
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
     "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
-    "anova_rff_factor",
+    "anova_rff_factor", "anova_mi_windows",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -151,6 +151,7 @@ def load_library(path: str = LIB_PATH):
                                      dbl, P, P], ctypes.c_int),
         "anova_autotune": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(TuneOpts), P, ctypes.POINTER(Opts),
                             ctypes.POINTER(TuneCandidate), i32, ctypes.POINTER(i32)], ctypes.c_int),
+        "anova_mi_windows": ([P, i64, i32, i64, P, i32, i32, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -384,6 +385,28 @@ def decision_function(X, Xnew, windows, sigma, labels, alpha, lam: float, eta=No
                                        ctypes.c_void_p(alpha.data_ptr()), float(lam), ctypes.c_void_p(f.data_ptr()),
                                        _stream(stream)))
     return f
+
+
+def mi_windows(X, labels, bins: int = 32, P: int | None = None, stream=None):
+    """Windows of features by mutual-information ranking (anova_mi_windows).
+    X: device N x d row-major tensor; labels: device N tensor (class by sign).
+    Returns (windows P x 3 int32, -1 padded; mutual-information estimate per
+    feature). P defaults to ceil(d / 3)."""
+    lib = load_library()
+    X = _dev_f64(X, "X")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a 2-D row-major tensor")
+    y = _dev_f64(labels, "labels").contiguous()
+    N, d = int(X.shape[0]), int(X.shape[1])
+    if y.shape != (N,):
+        raise ValueError("labels must have shape (N,)")
+    P = (d + 2) // 3 if P is None else int(P)
+    win = np.full((max(P, 1), 3), -1, dtype=np.int32)
+    mi = np.zeros(d, dtype=np.float64)
+    _check(lib.anova_mi_windows(ctypes.c_void_p(X.data_ptr()), N, d, X.stride(0), ctypes.c_void_p(y.data_ptr()),
+                                int(bins), P, win.ctypes.data_as(ctypes.c_void_p), mi.ctypes.data_as(ctypes.c_void_p),
+                                _stream(stream)))
+    return win[:P], mi
 
 
 def autotune(X, windows, sigma, eta=None, target_rel_err: float = 1e-4, rhs: int = 1,

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libanova_nfft.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["coeffs.cpp", "plan.hip", "matvec.hip", "matvec_batched.hip", "solver.hip", "server.cpp", "tune.hip", "abi.cpp"]
+SOURCES = ["coeffs.cpp", "plan.hip", "matvec.hip", "matvec_batched.hip", "solver.hip", "server.cpp", "tune.hip", "windows.hip", "abi.cpp"]
 ARCH = os.environ.get("ANOVA_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -10,6 +10,7 @@
 #include "server.hpp"
 #include "solver.hpp"
 #include "tune.hpp"
+#include "windows.hpp"
 
 namespace anv {
 static thread_local std::string g_last_error;
@@ -360,6 +361,14 @@ int anova_autotune(const double* X, int64_t N, int32_t d, int64_t ldx, const int
         }
         anv::autotune(X, N, d, ldx, windows, P, sigma, eta, o, static_cast<hipStream_t>(stream), best, cands,
                       max_cands, n_cands);
+        return ANOVA_OK;
+    });
+}
+
+int anova_mi_windows(const double* X, int64_t N, int32_t d, int64_t ldx, const double* labels, int32_t bins,
+                     int32_t P, int32_t* windows, double* mi, void* stream) {
+    return guarded([&] {
+        anv::mi_windows(X, N, d, ldx, labels, bins, P, windows, mi, static_cast<hipStream_t>(stream));
         return ANOVA_OK;
     });
 }
