@@ -59,9 +59,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ipm-small-solves", type=int, default=20)
-    ap.add_argument("--ipm-full-solves", type=int, default=5)
+    ap.add_argument("--ipm-full-solves", type=int, default=20)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
-    ap.add_argument("--ipm-full-gmres-solves", type=int, default=3,
+    ap.add_argument("--ipm-full-gmres-solves", type=int, default=10,
                     help="full-ipm solves with GMRES and the block-triangular preconditioner")
     ap.add_argument("--serving-requests", type=int, default=12,
                     help="requests of the Poisson serving stream (0 = skip)")
