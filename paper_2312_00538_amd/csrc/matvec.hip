@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64) void k_spread_lane(const MvLaunch ML) {
         for (int b = 0; b < WY; ++b) out[int64_t(zr - sg.z0 + c) * WY + b] = acc[b][c];
 }
 
-// Fold, step A: one wavefront per (window, column, layer). Lane (a, b) adds, in
+// Fold, step A for 3-feature windows: one wavefront per (window, column, layer). Lane (a, b) adds, in
 // item order, the slab values that the column's work items wrote for layer L
 // at footprint position (a, b), and stores the sum under its TARGET line
 // (cx + a, cy + b): tgt[window][target x][target y][a, b][layer]. Every
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(256) void k_fold_cols(const MvLaunch ML) {
     const MvJob& J = ML.job[job_of(ML, blk)];
     const WinDev* __restrict__ wins = J.wins;
     const int32_t P = J.P;
-    const int64_t nlist = J.nflist;
+    const int64_t nlist = J.nflist3;  // entries of 3-feature windows
     const int64_t* __restrict__ flist = J.flist;
     const int2* __restrict__ fold = J.fold;
     const int64_t* __restrict__ sbase = J.sbase;
@@ -315,6 +315,56 @@ __global__ __launch_bounds__(256) void k_fold_cols(const MvLaunch ML) {
     if (lane >= wd.lanes) return;
     const int64_t t = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * wd.lanes + pos) * wd.E[2] + L;
     tgt[wd.tgt_off + t] = WT(acc);
+}
+
+// Fold, step A for 1- and 2-feature windows. Their work items are short (one
+// lane each), so a cell gathers hundreds of them: one block per (window,
+// column, layer), thread = (part, footprint position) with 256 / lanes parts
+// taking the items in turn; the parts' sums are added in part order.
+template <class WT>
+__global__ __launch_bounds__(256) void k_fold_cols_wide(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    const int64_t fi = J.nflist3 + blk;
+    if (fi >= J.nflist) return;
+    const WinDev* __restrict__ wins = J.wins;
+    const int64_t* __restrict__ sbase = J.sbase;
+    const WT* __restrict__ slab = static_cast<const WT*>(J.slab);
+    WT* __restrict__ tgt = static_cast<WT*>(J.ca);
+    const int64_t f = J.flist[fi];
+    int l = 0;
+    while (l + 1 < J.P && wins[l + 1].fold_off <= f) ++l;
+    const WinDev& wd = wins[l];
+    const int lanes = wd.lanes, parts = 256 / lanes;
+    const int t = threadIdx.x, pos = t % lanes, part = t / lanes;
+    const int64_t fl = f - wd.fold_off;
+    const int L = int(fl % wd.E[2]);
+    const int2 r = J.fold[f];
+    double acc = 0.0;
+    if (part < parts) {
+        const int64_t row = int64_t(L) * lanes + pos;
+        int s = r.x + part;
+        for (; s + 3 * parts < r.y; s += 4 * parts) {
+            const int64_t o0 = sbase[s], o1 = sbase[s + parts], o2 = sbase[s + 2 * parts], o3 = sbase[s + 3 * parts];
+            const WT v0 = slab[o0 + row], v1 = slab[o1 + row], v2 = slab[o2 + row], v3 = slab[o3 + row];
+            acc += double(v0);
+            acc += double(v1);
+            acc += double(v2);
+            acc += double(v3);
+        }
+        for (; s < r.y; s += parts) acc += double(slab[sbase[s] + row]);
+    }
+    __shared__ double red[256];
+    red[t] = acc;
+    __syncthreads();
+    if (t >= lanes) return;
+    double tot = 0.0;
+    for (int q = 0; q < parts; ++q) tot += red[q * lanes + pos];
+    const int64_t col = fl / wd.E[2];
+    const int cx = int(col / wd.nb[1]), cy = int(col % wd.nb[1]);
+    const int a = pos / wd.Wslot[1], b = pos % wd.Wslot[1];
+    const int64_t tt = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * lanes + pos) * wd.E[2] + L;
+    tgt[wd.tgt_off + tt] = WT(tot);
 }
 
 // Fold step B fused with the y and z passes of the grid convolution. One block
@@ -609,6 +659,7 @@ MvJob make_job(Plan& pl, const double* x, double* y) {
     J.ca = f64 ? static_cast<void*>(pl.c64a.p) : static_cast<void*>(pl.c32a.p);
     J.N = pl.N;
     J.nflist = pl.nflist;
+    J.nflist3 = pl.nflist3;
     for (int k = 0; k < 4; ++k) {
         J.wave_off[k] = pl.wave_off[k];
         J.nwave[k] = pl.nwave[k];
@@ -652,7 +703,8 @@ void run_jobs(MvLaunch& L, Plan* prof, hipStream_t st) {
     launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[2]); }, k_spread_lane<W, W, WT>, 64, 0, st);
     launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[1]); }, k_spread_lane<W, 1, WT>, 64, 0, st);
     ev();
-    launch_jobs(L, [](const MvJob& J) { return (J.nflist + 3) / 4; }, k_fold_cols<WT>, 256, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return (J.nflist3 + 3) / 4; }, k_fold_cols<WT>, 256, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return J.nflist - J.nflist3; }, k_fold_cols_wide<WT>, 256, 0, st);
     ev();
     launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[0]) * J.P; }, k_fold_conv_yz<W, WT>, 1024,
                 size_t(2 * e1 * e2 + e1 * e1 + e2 * e2) * sizeof(double), st);

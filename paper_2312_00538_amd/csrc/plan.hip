@@ -512,7 +512,9 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
         // items alone in their column; fold entries of the other columns; column layer ranges
         std::vector<uint8_t> al(pl->segs_h.size(), 0);
         std::vector<int2> cr(size_t(col_total + 1), int2{1, 0});
-        std::vector<int64_t> fl;
+        // fold entries of 3-feature windows first, then those of 1- and 2-feature
+        // windows (whose cells gather many short items and are folded by blocks)
+        std::vector<int64_t> fl, fl_lane;
         size_t i0 = 0;
         while (i0 < pl->segs_h.size()) {
             size_t i1 = i0;
@@ -529,11 +531,14 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
                 cr[cidx] = int2{s0.z0, s0.z1 + W - 1};
             } else {
                 cr[cidx] = int2{0, wd.E[2] - 1};
-                for (int L = 0; L < wd.E[2]; ++L) fl.push_back(wd.fold_off + int64_t(s0.col) * wd.E[2] + L);
+                for (int L = 0; L < wd.E[2]; ++L)
+                    (dw == 3 ? fl : fl_lane).push_back(wd.fold_off + int64_t(s0.col) * wd.E[2] + L);
             }
             i0 = i1;
         }
         upload(pl->alone, al, st);
+        pl->nflist3 = int64_t(fl.size());
+        fl.insert(fl.end(), fl_lane.begin(), fl_lane.end());
         pl->nflist = int64_t(fl.size());
         if (fl.empty()) fl.push_back(0);
         upload(pl->flist, fl, st);

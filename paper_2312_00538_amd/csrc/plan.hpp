@@ -47,6 +47,7 @@ struct Plan {
     // column the layers holding data in the target-major buffer (x > y = none)
     DevBuf<int64_t> flist;
     int64_t nflist = 0;
+    int64_t nflist3 = 0;        // entries [0, nflist3) belong to 3-feature windows
     DevBuf<int2> crange;
     int64_t wave_off[4] = {0, 0, 0, 0};
     int32_t nwave[4] = {0, 0, 0, 0};
@@ -121,6 +122,7 @@ struct MvJob {
     void* ca;
     int64_t N;
     int64_t nflist;
+    int64_t nflist3;
     int64_t wave_off[4];
     int32_t nwave[4];
     int32_t P;
