@@ -37,17 +37,20 @@ def _problems(g, dev, precision, sigmas=None, folds=None):
     return out
 
 
-def test_grid_equals_direct_solves_fp64(dev):
-    # FP64 plans: shared factor and shared one-vector launches change no bit
+@pytest.mark.parametrize("krylov", ["minres", "gmres"])
+def test_grid_equals_direct_solves_fp64(dev, krylov):
+    # FP64 plans: shared factor and shared one-vector launches change no bit,
+    # with either Krylov method
     import paper_2312_00538_amd as lib
+    kr = lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES
     g = _grid()
     probs = _problems(g, dev, lib.PREC_FP64, sigmas=g["sigmas"][:1], folds=[0, 1])
-    res, launches, matvecs = lib.grid_solve([(pl, y, Cs) for pl, y, Cs, _, _ in probs], max_active=6)
-    print("launches", launches, "matvecs", matvecs)
+    res, launches, matvecs = lib.grid_solve([(pl, y, Cs) for pl, y, Cs, _, _ in probs], max_active=6, krylov=kr)
+    print(krylov, "launches", launches, "matvecs", matvecs)
     assert matvecs > launches
     for (pl, y, Cs, _, _), (alpha, lam, stats) in zip(probs, res):
         for j, C in enumerate(Cs):
-            a_ref, lam_ref, st_ref = pl.solve(y, C, allow_not_converged=True)
+            a_ref, lam_ref, st_ref = pl.solve(y, C, allow_not_converged=True, krylov=kr)
             assert stats[j]["status"] == st_ref["status"] == 0
             assert np.array_equal(alpha[:, j].cpu().numpy(), a_ref.cpu().numpy())
             assert lam[j] == lam_ref
