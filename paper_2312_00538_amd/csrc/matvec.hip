@@ -106,8 +106,12 @@ __global__ __launch_bounds__(64) void k_spread_grp(const MvLaunch ML) {
     WT* __restrict__ tgt = static_cast<WT*>(J.ca);
     constexpr int G = 64 / W;                 // lane groups
     constexpr int REC = rec_stride(W, int(sizeof(WT)));
-    constexpr int CH = 64;                    // staged points
-    constexpr int PADR = 16 / int(sizeof(WT)); // record padding, spreads groups over LDS banks
+    // staged points and record padding (the padding spreads the groups over the
+    // LDS banks); FP64 records of 8 taps per axis are staged 32 at a time, so
+    // that the block's LDS (about 21 KB instead of 33 KB) admits more wavefronts
+    constexpr bool kHalf = sizeof(WT) == 8 && W == 8;
+    constexpr int CH = kHalf ? 32 : 64;
+    constexpr int PADR = (kHalf ? 32 : 16) / int(sizeof(WT));
     constexpr int RS = REC + PADR;
     constexpr int STEP = CH - G;               // chunk c holds points [c*STEP, c*STEP + CH)
     __shared__ WT stw[2][CH * RS];
@@ -491,8 +495,9 @@ __global__ __launch_bounds__(64) void k_gather_grp(const MvLaunch ML) {
     double* __restrict__ fs = J.fs;
     constexpr int G = 64 / W;
     constexpr int REC = rec_stride(W, int(sizeof(WT)));
-    constexpr int CH = 64;
-    constexpr int PADR = 16 / int(sizeof(WT));
+    constexpr bool kHalf = sizeof(WT) == 8 && W == 8;  // as in the spread
+    constexpr int CH = kHalf ? 32 : 64;
+    constexpr int PADR = (kHalf ? 32 : 16) / int(sizeof(WT));
     constexpr int RS = REC + PADR;
     constexpr int STEP = CH - G;
     __shared__ WT stw[2][CH * RS];
