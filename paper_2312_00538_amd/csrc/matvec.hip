@@ -91,9 +91,7 @@ __global__ void k_permute(const MvLaunch ML) {
 // and the wave writes one slab row [a][b]. Point data are staged in LDS in
 // chunks of 64 consecutive points.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_spread_grp(const MvLaunch ML) {
-    int blk = blockIdx.x;
-    const MvJob& J = ML.job[job_of(ML, blk)];
+__device__ __forceinline__ void spread_grp(const MvJob& J, const int blk) {
     const Segment* __restrict__ segs = J.segs;
     const int32_t* __restrict__ lstart = J.lstart;
     const int32_t* __restrict__ lstart_off = J.lstart_off;
@@ -211,9 +209,7 @@ __global__ __launch_bounds__(64) void k_spread_grp(const MvLaunch ML) {
 // 1- and 2-feature windows: one lane per work item; WY = W for two features
 // (y taps in registers), 1 for one feature. Slab layout [layer][b].
 template <int W, int WY, class WT>
-__global__ __launch_bounds__(64) void k_spread_lane(const MvLaunch ML) {
-    int blk = blockIdx.x;
-    const MvJob& J = ML.job[job_of(ML, blk)];
+__device__ __forceinline__ void spread_lane(const MvJob& J, const int blk) {
     const Segment* __restrict__ segs = J.segs;
     const int32_t* __restrict__ zq = J.zq;
     const WT* __restrict__ wts = static_cast<const WT*>(J.wts);
@@ -261,6 +257,22 @@ __global__ __launch_bounds__(64) void k_spread_lane(const MvLaunch ML) {
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int b = 0; b < WY; ++b) out[int64_t(zr - sg.z0 + c) * WY + b] = acc[b][c];
+}
+
+// Spreading of every window of the launch's plans in one launch: the grouped
+// work items of 3-feature windows first (longest first), then the one-lane
+// items of 2- and 1-feature windows, which fill the machine while the last
+// long items finish.
+template <int W, class WT>
+__global__ __launch_bounds__(64) void k_spread(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    if (blk < J.nwave[3])
+        spread_grp<W, WT>(J, blk);
+    else if (blk < J.nwave[3] + J.nwave[2])
+        spread_lane<W, W, WT>(J, blk - J.nwave[3]);
+    else
+        spread_lane<W, 1, WT>(J, blk - J.nwave[3] - J.nwave[2]);
 }
 
 // Fold, step A for 3-feature windows: one wavefront per (window, column, layer). Lane (a, b) adds, in
@@ -482,9 +494,7 @@ __global__ __launch_bounds__(256) void k_conv_x(const MvLaunch ML) {
 // the layer, lane a forms the share of x-tap a and the W lanes add their shares
 // with a fixed xor butterfly.
 template <int W, class WT>
-__global__ __launch_bounds__(64) void k_gather_grp(const MvLaunch ML) {
-    int blk = blockIdx.x;
-    const MvJob& J = ML.job[job_of(ML, blk)];
+__device__ __forceinline__ void gather_grp(const MvJob& J, const int blk) {
     const Segment* __restrict__ segs = J.segs;
     const int32_t* __restrict__ lstart = J.lstart;
     const int32_t* __restrict__ lstart_off = J.lstart_off;
@@ -574,9 +584,7 @@ __global__ __launch_bounds__(64) void k_gather_grp(const MvLaunch ML) {
 
 // 1- and 2-feature windows: one lane per work item.
 template <int W, int WY, class WT>
-__global__ __launch_bounds__(64) void k_gather_lane(const MvLaunch ML) {
-    int blk = blockIdx.x;
-    const MvJob& J = ML.job[job_of(ML, blk)];
+__device__ __forceinline__ void gather_lane(const MvJob& J, const int blk) {
     const Segment* __restrict__ segs = J.segs;
     const WinDev* __restrict__ wins = J.wins;
     const int32_t* __restrict__ zq = J.zq;
@@ -622,6 +630,19 @@ __global__ __launch_bounds__(64) void k_gather_lane(const MvLaunch ML) {
         }
         fs[gi] = double(sy);
     }
+}
+
+// Gathering of every window in one launch, in the order of the spreading
+template <int W, class WT>
+__global__ __launch_bounds__(64) void k_gather(const MvLaunch ML) {
+    int blk = blockIdx.x;
+    const MvJob& J = ML.job[job_of(ML, blk)];
+    if (blk < J.nwave[3])
+        gather_grp<W, WT>(J, blk);
+    else if (blk < J.nwave[3] + J.nwave[2])
+        gather_lane<W, W, WT>(J, blk - J.nwave[3]);
+    else
+        gather_lane<W, 1, WT>(J, blk - J.nwave[3] - J.nwave[2]);
 }
 
 __global__ void k_window_sum(const MvLaunch ML) {
@@ -704,9 +725,8 @@ void run_jobs(MvLaunch& L, Plan* prof, hipStream_t st) {
     ev();
     launch_jobs(L, [](const MvJob& J) { return int64_t(nblocks(J.N * J.P)); }, k_permute, kThreads, 0, st);
     ev();
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]); }, k_spread_grp<W, WT>, 64, 0, st);
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[2]); }, k_spread_lane<W, W, WT>, 64, 0, st);
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[1]); }, k_spread_lane<W, 1, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]) + J.nwave[2] + J.nwave[1]; }, k_spread<W, WT>, 64, 0,
+                st);
     ev();
     launch_jobs(L, [](const MvJob& J) { return (J.nflist3 + 3) / 4; }, k_fold_cols<WT>, 256, 0, st);
     launch_jobs(L, [](const MvJob& J) { return J.nflist - J.nflist3; }, k_fold_cols_wide<WT>, 256, 0, st);
@@ -716,9 +736,8 @@ void run_jobs(MvLaunch& L, Plan* prof, hipStream_t st) {
     launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[1]) * J.P; }, k_conv_x<WT>, 256,
                 size_t(e0 * e2 + e0 * e0) * sizeof(double), st);
     ev();
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]); }, k_gather_grp<W, WT>, 64, 0, st);
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[2]); }, k_gather_lane<W, W, WT>, 64, 0, st);
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[1]); }, k_gather_lane<W, 1, WT>, 64, 0, st);
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.nwave[3]) + J.nwave[2] + J.nwave[1]; }, k_gather<W, WT>, 64, 0,
+                st);
     ev();
     launch_jobs(L, [](const MvJob& J) { return int64_t(nblocks(J.N)); }, k_window_sum, kThreads, 0, st);
     ev();
