@@ -124,3 +124,19 @@ def test_autotune_options_and_argument_checks(L):
     t.version = lib.TuneOpts().version or 1
     t.rhs = 0
     assert L.anova_autotune(*args, ctypes.byref(t), None, ctypes.byref(best), None, 0, None) == lib.INVALID_ARG
+
+
+def test_mi_windows_argument_checks(L):
+    # sizes are checked before any device access: fake device pointers suffice
+    import numpy as np
+    fake = ctypes.c_void_p(0x1000)
+    win = np.zeros((4, 3), dtype=np.int32)
+    w = win.ctypes.data_as(ctypes.c_void_p)
+    ok = dict(N=100, d=9, ldx=9, bins=32, P=3)
+    for bad in (dict(N=0), dict(d=0), dict(ldx=8), dict(bins=1), dict(bins=1025), dict(P=0), dict(P=4)):
+        a = {**ok, **bad}
+        rc = L.anova_mi_windows(fake, a["N"], a["d"], a["ldx"], fake, a["bins"], a["P"], w, None, None)
+        assert rc == lib.INVALID_ARG, bad
+        assert L.anova_last_error()
+    assert L.anova_mi_windows(None, 100, 9, 9, fake, 32, 3, w, None, None) == lib.INVALID_ARG
+    assert L.anova_mi_windows(fake, 100, 9, 9, fake, 32, 3, None, None, None) == lib.INVALID_ARG
