@@ -8,10 +8,13 @@ common module and hold none of the method's arithmetic).
 
 Contents, each following the paper (arXiv 2312.00538):
   * anova_matvec / anova_columns / anova_dense — the ANOVA Gaussian kernel
-    (Section 3), by direct summation (C, `anova_direct.c`) or dense numpy.
+    (Section 3), by direct summation (C, `anova_direct.c`) or dense numpy;
+    anova_cross — the same sum from source points to other target points.
   * ipm_dense — the interior point method of Algorithm 1 (Section 2) with the
     Newton system (Section 2, equation "Newton") solved densely.
-  * pivoted_cholesky — Algorithm 2 (Section 4) on the dense matrix.
+  * pivoted_cholesky — Algorithm 2 (Section 4) on the dense matrix;
+    rp_cholesky — its randomly pivoted variant (Section 4) with given draws.
+  * rff_features — random Fourier features of the ANOVA sum (Section 4).
   * nystrom — the Nystrom approximation (Section 4) with LDL^T and clamping.
   * woodbury_apply — the Sherman-Morrison-Woodbury form of the (1,1)-block
     preconditioner (Section 5).
