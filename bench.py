@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--ipm-small-solves", type=int, default=20)
+    ap.add_argument("--ipm-small-gmres-solves", type=int, default=20,
+                    help="plain-small solves with GMRES and the block-triangular preconditioner")
     ap.add_argument("--ipm-full-solves", type=int, default=20)
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
     ap.add_argument("--ipm-full-gmres-solves", type=int, default=10,
@@ -418,6 +420,11 @@ def main():
                                a.ipm_small_solves, lib.PRECOND_DIAG, 0,
                                "plain-small: N=2000 d=9, 3 windows, sigma=1, C=1; MINRES without a kernel "
                                "preconditioner (barrier diagonal only)"))
+    if a.ipm_small_gmres_solves > 0:
+        ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.small_plain(seed=s, N=2000, d=9, R=0),
+                               a.ipm_small_gmres_solves, lib.PRECOND_DIAG, 0,
+                               "plain-small: N=2000 d=9, 3 windows, sigma=1, C=1; GMRES with the block-triangular "
+                               "preconditioner without a kernel part (barrier diagonal only)", krylov=lib.KRYLOV_GMRES))
     if a.ipm_full_solves > 0:
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
                                a.ipm_full_solves, lib.PRECOND_NYSTROM, 200,
