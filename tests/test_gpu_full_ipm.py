@@ -1,0 +1,69 @@
+"""The IPM at the full benchmark size (N = 500 000, d = 20, 7 windows, 10 %
+label noise, sigma = 0.8, C = 10, Nystrom rank 200: the configuration
+bench.py times), with MINRES and with GMRES.
+
+The dense-KKT oracle cannot run at this size, so the test checks what holds at
+any size, with the margins m_j = y_j ((K Y alpha)_j - lambda) of 512 sampled
+rows computed by the oracle's direct sum over all 500 000 sources:
+  * the GPU solve reports its own relative gap <= 1e-6, 0 < alpha < C and
+    |y^T alpha| <= 1e-6 |y^T alpha^0|;
+  * complementary slackness of the SVM dual (Section 1): free support vectors
+    (0.01 C < alpha_j < 0.99 C) lie on the margin, |m_j - 1| <= 1e-3; rows at
+    the lower bound (alpha_j < 1e-4 C) have m_j >= 1 - 1e-3 and rows at the
+    upper bound (alpha_j > (1 - 1e-4) C) have m_j <= 1 + 1e-3.
+At the final barrier parameter (mu <= 1e-6) the barrier terms move m_j by
+mu / min(alpha_j, C - alpha_j), at most 1e-5 for free support vectors; the
+1e-3 bound leaves room for the inexact Newton steps and the rows near the
+thresholds."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_util import device, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+@pytest.fixture(scope="module")
+def problem():
+    return workloads.full_ipm(seed=0, N=500_000)
+
+
+@pytest.mark.parametrize("krylov", ["minres", "gmres"])
+def test_full_size_solve_satisfies_the_optimality_conditions(dev, problem, krylov):
+    import paper_2312_00538_amd as lib
+    p = problem
+    pl = lib.Plan(to_dev(p.X, dev), p.windows, p.sigma)
+    kr = lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES
+    alpha, lam, st = pl.solve(to_dev(p.labels, dev), p.C, precond=lib.PRECOND_NYSTROM, rank=200, krylov=kr)
+    a = alpha.cpu().numpy()
+    C = p.C
+    print(krylov, {k: st[k] for k in ("ip_iters", "kry_iters_total", "rel_gap", "mu", "xi_alpha_rel")})
+    assert st["status"] == 0 and st["rel_gap"] <= 1e-6 and st["mu"] <= 1e-6
+    assert (a > 0).all() and (a < C).all()
+    assert st["xi_alpha_rel"] <= 1e-6
+    # 512 rows drawn uniformly, and up to 64 more among the free support vectors,
+    # which a uniform sample of this noisy problem rarely hits
+    rng = np.random.default_rng(1)
+    rows = rng.choice(p.X.shape[0], 512, replace=False)
+    free_all = np.flatnonzero((a > 0.01 * C) & (a < 0.99 * C))
+    rows = np.unique(np.concatenate([rows, rng.choice(free_all, min(64, free_all.size), replace=False)]))
+    f = oracle.anova_matvec(p.X, p.windows, p.sigma, p.labels * a, rows=rows) - lam
+    m = p.labels[rows] * f
+    ar = a[rows] / C
+    free, low, up = (ar > 0.01) & (ar < 0.99), ar < 1e-4, ar > 1 - 1e-4
+    print(f"{krylov}: {free_all.size} free support vectors in all; sampled rows: {free.sum()} free,"
+          f" {low.sum()} at 0, {up.sum()} at C of {rows.size};"
+          f" max |m - 1| free {np.max(np.abs(m[free] - 1), initial=0):.2e},"
+          f" min m at 0 {np.min(m[low], initial=np.inf):.6f}, max m at C {np.max(m[up], initial=-np.inf):.6f}")
+    assert free.sum() + low.sum() + up.sum() >= 400          # most rows are clearly classified
+    assert free.sum() >= min(64, free_all.size)
+    assert np.all(np.abs(m[free] - 1.0) <= 1e-3)
+    assert np.all(m[low] >= 1.0 - 1e-3)
+    assert np.all(m[up] <= 1.0 + 1e-3)
