@@ -367,27 +367,48 @@ void syrk_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
 }
 
 // w_part[s][j] = sum over rows of segment s of Z[j N + i] u[i]: one block per
-// (column j, segment s), so that the product of a long column keeps the GPU busy
-__global__ void k_gemv_t_seg(const double* __restrict__ Z, int64_t N, const double* __restrict__ u,
-                             int64_t seg, double* __restrict__ wpart) {
-    const int j = blockIdx.x, sgi = blockIdx.y;
+// (group of kGemvCols columns, segment s), so that the product of long columns
+// keeps the GPU busy and each value of u read serves kGemvCols columns
+constexpr int kGemvCols = 4;
+__global__ __launch_bounds__(kT) void k_gemv_t_seg(const double* __restrict__ Z, int64_t N, int k,
+                                                   const double* __restrict__ u, int64_t seg,
+                                                   double* __restrict__ wpart) {
+    const int j0 = blockIdx.x * kGemvCols, sgi = blockIdx.y;
+    const int nc = min(kGemvCols, k - j0);
     const int64_t r0 = int64_t(sgi) * seg, r1 = std::min<int64_t>(N, r0 + seg);
-    const double* zc = Z + int64_t(j) * N;
-    double a0 = 0.0, a1 = 0.0;
+    double a0[kGemvCols], a1[kGemvCols];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) a0[c] = a1[c] = 0.0;
     int64_t i = r0 + threadIdx.x;
     for (; i + kT < r1; i += 2 * kT) {
-        a0 += zc[i] * u[i];
-        a1 += zc[i + kT] * u[i + kT];
+        const double u0 = u[i], u1 = u[i + kT];
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c) {
+            if (c < nc) {
+                const double* zc = Z + int64_t(j0 + c) * N;
+                a0[c] += zc[i] * u0;
+                a1[c] += zc[i + kT] * u1;
+            }
+        }
     }
-    if (i < r1) a0 += zc[i] * u[i];
-    __shared__ double sh[kT];
-    sh[threadIdx.x] = a0 + a1;
+    if (i < r1) {
+        const double u0 = u[i];
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c)
+            if (c < nc) a0[c] += Z[int64_t(j0 + c) * N + i] * u0;
+    }
+    __shared__ double sh[kGemvCols][kT];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) sh[c][threadIdx.x] = a0[c] + a1[c];
     __syncthreads();
     for (int s = kT / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        if (threadIdx.x < s) {
+#pragma unroll
+            for (int c = 0; c < kGemvCols; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) wpart[int64_t(sgi) * gridDim.x + j] = sh[0];
+    if (threadIdx.x < nc) wpart[int64_t(sgi) * k + j0 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, double diag,
@@ -1094,8 +1115,8 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
     const int64_t N = pl.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
-        hipLaunchKernelGGL(k_gemv_t_seg, dim3(ws.k, ws.nseg), dim3(kT), 0, st, ws.Z, N, ws.tmp.p, ws.seg,
-                           ws.wpart.p);
+        hipLaunchKernelGGL(k_gemv_t_seg, dim3(unsigned((ws.k + kGemvCols - 1) / kGemvCols), unsigned(ws.nseg)),
+                           dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
         hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.wpart.p,
                            ws.nseg, ws.t.p);
     }
@@ -1127,8 +1148,10 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
         ws.status.alloc(1);
         syrk_chunks(N, k, ws.nchunk, ws.chunk);
         ws.Mpart.alloc(size_t(ws.nchunk) * k * k);
-        // segments of Z^T u: about 2048 blocks in all
-        ws.nseg = int(std::max<int64_t>(1, std::min<int64_t>((2048 + k - 1) / k, (N + 4095) / 4096)));
+        // segments of Z^T u: about 1024 blocks in all (fewer partial sums for the
+        // solve to fold, and still four blocks per compute unit)
+        const int64_t ncb = (k + kGemvCols - 1) / kGemvCols;
+        ws.nseg = int(std::max<int64_t>(1, std::min<int64_t>((1024 + ncb - 1) / ncb, (N + 4095) / 4096)));
         ws.seg = (N + ws.nseg - 1) / ws.nseg;
         ws.wpart.alloc(size_t(ws.nseg) * k);
     }
