@@ -94,12 +94,19 @@ def test_ipm_mixture_parity(dev, seed, N, C, sigma):
     _check_solve(p, C, dev)
 
 
-def test_ipm_two_points_closed_form(dev):
+@pytest.mark.parametrize("krylov", ["minres", "gmres"])
+def test_ipm_two_points_closed_form(dev, krylov):
+    # two points: the Newton systems have size 3 and a rank-2 factor makes the
+    # preconditioner's (1,1) block exact, so the preconditioned matrix has two
+    # distinct eigenvalues (Section 5) and GMRES stops within two steps
     import paper_2312_00538_amd as lib
     X = np.array([[0.0, 0.1, 0.0], [0.1, -0.05, 0.2]])
     y = np.array([1.0, -1.0])
     pl = lib.Plan(to_dev(X, dev), np.array([[0, 1, 2]]), 0.3)
-    alpha, lam, st = pl.solve(to_dev(y, dev), 100.0, rank=2)
+    kr = lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES
+    alpha, lam, st = pl.solve(to_dev(y, dev), 100.0, rank=2, krylov=kr)
+    print(krylov, st["ip_iters"], st["kry_iters_total"], st["kry_iters_max"])
+    assert st["kry_iters_max"] <= (2 if krylov == "gmres" else 3)
     K = oracle.anova_dense(X, np.array([[0, 1, 2]]), 0.3)
     a = 1.0 / (K[0, 0] - K[0, 1])
     assert np.allclose(alpha.cpu().numpy(), a, rtol=1e-4)
