@@ -127,6 +127,30 @@ int anova_plan_create(const double* X, int64_t N, int32_t d, int64_t ldx,
 int anova_matvec(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_,
                  double* y, int64_t ldy, void* stream);
 
+/* Allocation-free form of anova_matvec, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc. It computes what anova_matvec computes with R
+ * one-vector passes (bit for bit the same result as anova_matvec for R = 1,
+ * and for any R on plans that do not batch), through the same kernels, but
+ * the passes' scratch arrays (permuted input, slabs, fold target, grids,
+ * gathered values) live in one static array of the library instead of the
+ * plan's buffers. That array holds ANOVA_NOALLOC_SCRATCH_BYTES (64 MiB) per
+ * device; it is part of the loaded library and stays allocated on every
+ * device the library runs on until the process ends. The call allocates no
+ * device memory (no hipMalloc, hipFree or allocating library routine); its
+ * first call on a device looks up that device's copy of the array.
+ * All calls on one device share its array, which keeps the last call's
+ * contents (every pass writes what it reads): calls that overlap in time on
+ * one device, on different streams or threads, race and must be serialised
+ * by the caller; calls in order on one stream are safe.
+ *   plan, x, R, ldx_, y, ldy, stream: as for anova_matvec.
+ * Errors: as for anova_matvec, and ANOVA_INVALID_ARG when the plan's
+ * one-vector scratch exceeds ANOVA_NOALLOC_SCRATCH_BYTES (the message gives
+ * the size it needs). */
+#define ANOVA_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int anova_matvec_noalloc(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_,
+                         double* y, int64_t ldy, void* stream);
+
 /* Release a plan and all device memory it owns (synchronises the device).
  * NULL is accepted. */
 int anova_plan_destroy(anova_plan_t plan);

@@ -28,7 +28,7 @@ EXPORTED = [
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
     "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
-    "anova_rff_factor", "anova_mi_windows",
+    "anova_rff_factor", "anova_mi_windows", "anova_matvec_noalloc",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         "anova_plan_create": ([P, i64, i32, i64, P, i32, P, P, ctypes.POINTER(Opts), P, ctypes.POINTER(P)],
                               ctypes.c_int),
         "anova_matvec": ([P, P, i32, i64, P, i64, P], ctypes.c_int),
+        "anova_matvec_noalloc": ([P, P, i32, i64, P, i64, P], ctypes.c_int),
         "anova_plan_destroy": ([P], ctypes.c_int),
         "anova_plan_info": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
         "anova_ipm_opts_default": ([ctypes.POINTER(IpmOpts)], ctypes.c_int),
@@ -258,6 +259,27 @@ class Plan:
                 raise ValueError("out must be column-contiguous")
         _check(_lib.anova_matvec(self._h, ctypes.c_void_p(xc.data_ptr()), R, self.N,
                                  ctypes.c_void_p(yc.data_ptr()), self.N, _stream(stream)))
+        y = yc.t()
+        return y.reshape(self.N) if vec else y
+
+    def matvec_noalloc(self, x, out=None, stream=None):
+        """y = K x through anova_matvec_noalloc (one-vector passes, scratch in
+        the library's static per-device array; no device allocation in the
+        library call)."""
+        import torch
+        x = _dev_f64(x, "x")
+        vec = x.dim() == 1
+        xm = x.reshape(self.N, 1) if vec else x
+        R = int(xm.shape[1])
+        xc = xm.t().contiguous()
+        if out is None:
+            yc = torch.empty((R, self.N), dtype=torch.float64, device=x.device)
+        else:
+            yc = out.reshape(self.N, R).t() if not vec else out.reshape(1, self.N)
+            if not yc.is_contiguous():
+                raise ValueError("out must be column-contiguous")
+        _check(_lib.anova_matvec_noalloc(self._h, ctypes.c_void_p(xc.data_ptr()), R, self.N,
+                                         ctypes.c_void_p(yc.data_ptr()), self.N, _stream(stream)))
         y = yc.t()
         return y.reshape(self.N) if vec else y
 

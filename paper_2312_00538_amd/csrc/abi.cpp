@@ -87,6 +87,18 @@ int anova_matvec(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_, do
     });
 }
 
+int anova_matvec_noalloc(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_, double* y, int64_t ldy,
+                         void* stream) {
+    return guarded([&] {
+        ANV_CHECK(plan && plan->p, "NULL plan");
+        ANV_CHECK(x && y, "NULL vector");
+        ANV_CHECK(R >= 1, "R < 1");
+        ANV_CHECK(ldx_ >= plan->p->N && ldy >= plan->p->N, "leading dimension < N");
+        anv::enqueue_matvec_noalloc(*plan->p, x, R, ldx_, y, ldy, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
 int anova_plan_destroy(anova_plan_t plan) {
     return guarded([&] {
         if (plan) {

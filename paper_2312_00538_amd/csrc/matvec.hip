@@ -18,6 +18,8 @@
 // kernel adds the slabs that cover a cell in a fixed order, so results are
 // reproducible bit for bit.
 #include <cstring>
+#include <mutex>
+#include <string>
 
 #include "plan.hpp"
 
@@ -802,6 +804,83 @@ void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, in
     for (int r = 0; r < R; ++r) {
         L.job[0] = make_job(pl, x + int64_t(r) * ldx, y + int64_t(r) * ldy);
         run_launch(L, pl.W, pl.precision, &pl, st);
+    }
+}
+
+// ---------------------------------------------------------------- allocation-free matvec
+// Scratch of enqueue_matvec_noalloc: one array per device, allocated with the
+// code object when the library is loaded on the device and held until the
+// process ends. Host code never passes `scratch` itself to a kernel (in host
+// code the name is a host-side stand-in, not a device address): it uses the
+// device address that hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on the first call
+// on the device, with that device current).
+unsigned char* noalloc_scratch() {
+    int dev = 0;
+    ANV_HIP(hipGetDevice(&dev));
+    ANV_CHECK(dev >= 0 && dev < kMaxDevices, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        ANV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        ANV_CHECK(p != nullptr, "no device address for the scratch array");
+        g_scratch_ptr[dev] = static_cast<unsigned char*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Byte offsets of the one-vector matvec's scratch arrays inside the scratch
+// region (each 256-byte aligned): vs, fs, slab, g, h, fold target; [6] = total.
+void noalloc_layout(const Plan& pl, size_t (&off)[7]) {
+    const size_t elem = pl.precision == ANOVA_PREC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t np = size_t(pl.N) * size_t(pl.P);
+    const size_t bytes[6] = {(np + 2) * sizeof(double), np * sizeof(double), size_t(std::max<int64_t>(pl.slab_total, 1)) * elem,
+                             size_t(pl.grid_total) * elem, size_t(pl.grid_total) * elem,
+                             size_t(std::max<int64_t>(pl.tgt_total, 1)) * elem};
+    size_t o = 0;
+    for (int k = 0; k < 6; ++k) {
+        off[k] = o;
+        o += (bytes[k] + 255) & ~size_t(255);
+    }
+    off[6] = o;
+}
+
+}  // namespace
+
+size_t noalloc_scratch_bytes(const Plan& pl) {
+    size_t off[7];
+    noalloc_layout(pl, off);
+    return off[6];
+}
+
+void enqueue_matvec_noalloc(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
+    size_t off[7];
+    noalloc_layout(pl, off);
+    if (off[6] > kNoAllocScratchBytes)
+        throw Error(ANOVA_INVALID_ARG, "plan needs " + std::to_string(off[6]) +
+                                           " bytes of matvec scratch, more than the allocation-free maximum of " +
+                                           std::to_string(kNoAllocScratchBytes) + " bytes");
+    unsigned char* base = noalloc_scratch();
+    MvLaunch L;
+    L.njobs = 1;
+    for (int r = 0; r < R; ++r) {
+        MvJob J = make_job(pl, x + int64_t(r) * ldx, y + int64_t(r) * ldy);
+        J.vs = reinterpret_cast<double*>(base + off[0]);
+        J.fs = reinterpret_cast<double*>(base + off[1]);
+        J.slab = base + off[2];
+        J.g = base + off[3];
+        J.h = base + off[4];
+        J.ca = base + off[5];
+        L.job[0] = J;
+        run_launch(L, pl.W, pl.precision, nullptr, st);
     }
 }
 

@@ -145,6 +145,17 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
 void enqueue_matvec(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                     hipStream_t stream);
 
+// y[:, r] = K x[:, r] one vector at a time, with every scratch array of the
+// pass placed in a static per-device array of kNoAllocScratchBytes instead of
+// the plan's buffers: no device memory is allocated. Plans whose one-vector
+// scratch (noalloc_scratch_bytes) exceeds the maximum are rejected
+// (ANOVA_INVALID_ARG). All calls on a device share its array, so calls that
+// overlap on one device race.
+constexpr size_t kNoAllocScratchBytes = size_t(ANOVA_NOALLOC_SCRATCH_BYTES);
+size_t noalloc_scratch_bytes(const Plan& pl);
+void enqueue_matvec_noalloc(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
+                            hipStream_t stream);
+
 // The 16-wide batched kernels (matvec_batched.hip): used by enqueue_matvec for
 // R >= batch_min_rhs when batched_supported(pl).
 bool batched_supported(const Plan& pl);
