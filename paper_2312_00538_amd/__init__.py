@@ -8,6 +8,7 @@ otherwise (there is no CPU fallback).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -175,6 +176,27 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+@contextlib.contextmanager
+def _on_stream(stream, *inputs):
+    """Runs the binding's own copies and allocations on the stream that the
+    library call gets, and yields that stream's handle. With an explicit
+    `stream` other than torch's current one, `stream` first waits for the
+    current stream (which produced the inputs), and the inputs are recorded on
+    it so that the caching allocator keeps their memory until the library's
+    asynchronous reads on `stream` are done."""
+    import torch
+    cur = torch.cuda.current_stream()
+    if stream is None or stream == cur:
+        yield ctypes.c_void_p(cur.cuda_stream)
+        return
+    stream.wait_stream(cur)
+    for t in inputs:
+        if t is not None:
+            t.record_stream(stream)
+    with torch.cuda.stream(stream):
+        yield ctypes.c_void_p(stream.cuda_stream)
+
+
 def _dev_f64(t, name):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
@@ -245,41 +267,29 @@ class Plan:
 
     def matvec(self, x, out=None, stream=None):
         """y = K x for x of shape (N,) or (N, R) (R columns, column-major: x.T contiguous)."""
-        import torch
-        x = _dev_f64(x, "x")
-        vec = x.dim() == 1
-        xm = x.reshape(self.N, 1) if vec else x
-        R = int(xm.shape[1])
-        xc = xm.t().contiguous()               # R x N, column r contiguous
-        if out is None:
-            yc = torch.empty((R, self.N), dtype=torch.float64, device=x.device)
-        else:
-            yc = out.reshape(self.N, R).t() if not vec else out.reshape(1, self.N)
-            if not yc.is_contiguous():
-                raise ValueError("out must be column-contiguous")
-        _check(_lib.anova_matvec(self._h, ctypes.c_void_p(xc.data_ptr()), R, self.N,
-                                 ctypes.c_void_p(yc.data_ptr()), self.N, _stream(stream)))
-        y = yc.t()
-        return y.reshape(self.N) if vec else y
+        return self._matvec(_lib.anova_matvec, x, out, stream)
 
     def matvec_noalloc(self, x, out=None, stream=None):
         """y = K x through anova_matvec_noalloc (one-vector passes, scratch in
         the library's static per-device array; no device allocation in the
         library call)."""
+        return self._matvec(_lib.anova_matvec_noalloc, x, out, stream)
+
+    def _matvec(self, fn, x, out, stream):
         import torch
         x = _dev_f64(x, "x")
         vec = x.dim() == 1
-        xm = x.reshape(self.N, 1) if vec else x
-        R = int(xm.shape[1])
-        xc = xm.t().contiguous()
-        if out is None:
-            yc = torch.empty((R, self.N), dtype=torch.float64, device=x.device)
-        else:
-            yc = out.reshape(self.N, R).t() if not vec else out.reshape(1, self.N)
-            if not yc.is_contiguous():
-                raise ValueError("out must be column-contiguous")
-        _check(_lib.anova_matvec_noalloc(self._h, ctypes.c_void_p(xc.data_ptr()), R, self.N,
-                                         ctypes.c_void_p(yc.data_ptr()), self.N, _stream(stream)))
+        with _on_stream(stream, x, out) as s:
+            xm = x.reshape(self.N, 1) if vec else x
+            R = int(xm.shape[1])
+            xc = xm.t().contiguous()               # R x N, column r contiguous
+            if out is None:
+                yc = torch.empty((R, self.N), dtype=torch.float64, device=x.device)
+            else:
+                yc = out.reshape(self.N, R).t() if not vec else out.reshape(1, self.N)
+                if not yc.is_contiguous():
+                    raise ValueError("out must be column-contiguous")
+            _check(fn(self._h, ctypes.c_void_p(xc.data_ptr()), R, self.N, ctypes.c_void_p(yc.data_ptr()), self.N, s))
         y = yc.t()
         return y.reshape(self.N) if vec else y
 
@@ -300,26 +310,27 @@ class Plan:
               **kw):
         """Interior point SVM training; returns (alpha, lambda, stats dict)."""
         import torch
-        labels = _dev_f64(labels, "labels").contiguous()
+        labels = _dev_f64(labels, "labels")
         if opts is None:
             opts = default_ipm_opts(**kw)
-        alpha = torch.empty(self.N, dtype=torch.float64, device=labels.device)
-        lam = ctypes.c_double(0.0)
-        st = IpmStats()
-        rc = _lib.svm_ipm_solve(self._h, ctypes.c_void_p(labels.data_ptr()), float(C), ctypes.byref(opts),
-                                ctypes.c_void_p(alpha.data_ptr()), ctypes.byref(lam), ctypes.byref(st),
-                                _stream(stream))
+        with _on_stream(stream, labels) as s:
+            labels = labels.contiguous()
+            alpha = torch.empty(self.N, dtype=torch.float64, device=labels.device)
+            lam = ctypes.c_double(0.0)
+            st = IpmStats()
+            rc = _lib.svm_ipm_solve(self._h, ctypes.c_void_p(labels.data_ptr()), float(C), ctypes.byref(opts),
+                                    ctypes.c_void_p(alpha.data_ptr()), ctypes.byref(lam), ctypes.byref(st), s)
         _check(rc, allow=(OK, NOT_CONVERGED) if allow_not_converged else (OK,))
         return alpha, lam.value, st.as_dict()
 
     def pivoted_cholesky(self, rank: int, err_tol: float = 0.0, stream=None):
         import torch
-        L = torch.empty((rank, self.N), dtype=torch.float64, device=self.device)
         piv = np.zeros(rank, dtype=np.int64)
         used = ctypes.c_int32(0)
-        _check(_lib.anova_pivoted_cholesky(self._h, rank, float(err_tol), ctypes.c_void_p(L.data_ptr()),
-                                           self.N, piv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(used),
-                                           _stream(stream)))
+        with _on_stream(stream) as s:
+            L = torch.empty((rank, self.N), dtype=torch.float64, device=self.device)
+            _check(_lib.anova_pivoted_cholesky(self._h, rank, float(err_tol), ctypes.c_void_p(L.data_ptr()),
+                                               self.N, piv.ctypes.data_as(ctypes.c_void_p), ctypes.byref(used), s))
         r = used.value
         return L[:r].t(), piv[:r]
 
@@ -328,12 +339,13 @@ class Plan:
         import torch
         u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1))
         rank = int(u.shape[0])
-        L = torch.empty((rank, self.N), dtype=torch.float64, device=self.device)
         piv = np.zeros(rank, dtype=np.int64)
         used = ctypes.c_int32(0)
-        _check(_lib.anova_rp_cholesky(self._h, rank, float(err_tol), u.ctypes.data_as(ctypes.c_void_p),
-                                      ctypes.c_void_p(L.data_ptr()), self.N, piv.ctypes.data_as(ctypes.c_void_p),
-                                      ctypes.byref(used), _stream(stream)))
+        with _on_stream(stream) as s:
+            L = torch.empty((rank, self.N), dtype=torch.float64, device=self.device)
+            _check(_lib.anova_rp_cholesky(self._h, rank, float(err_tol), u.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.c_void_p(L.data_ptr()), self.N, piv.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(used), s))
         r = used.value
         return L[:r].t(), piv[:r]
 
@@ -343,19 +355,21 @@ class Plan:
         w = np.ascontiguousarray(np.asarray(w, dtype=np.float64).reshape(-1, 3))
         b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
         k = int(b.shape[0])
-        Z = torch.empty((k, self.N), dtype=torch.float64, device=self.device)
-        _check(_lib.anova_rff_factor(self._h, k, w.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p),
-                                     ctypes.c_void_p(Z.data_ptr()), self.N, _stream(stream)))
+        with _on_stream(stream) as s:
+            Z = torch.empty((k, self.N), dtype=torch.float64, device=self.device)
+            _check(_lib.anova_rff_factor(self._h, k, w.ctypes.data_as(ctypes.c_void_p),
+                                         b.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(Z.data_ptr()), self.N, s))
         return Z.t()
 
     def nystrom(self, G, stream=None):
         import torch
         G = _dev_f64(G, "G")
         k = int(G.shape[1])
-        Gc = G.t().contiguous()
-        Z = torch.empty((k, self.N), dtype=torch.float64, device=G.device)
-        _check(_lib.anova_nystrom(self._h, ctypes.c_void_p(Gc.data_ptr()), k, self.N,
-                                  ctypes.c_void_p(Z.data_ptr()), self.N, _stream(stream)))
+        with _on_stream(stream, G) as s:
+            Gc = G.t().contiguous()
+            Z = torch.empty((k, self.N), dtype=torch.float64, device=G.device)
+            _check(_lib.anova_nystrom(self._h, ctypes.c_void_p(Gc.data_ptr()), k, self.N,
+                                      ctypes.c_void_p(Z.data_ptr()), self.N, s))
         return Z.t()
 
     def close(self):
@@ -389,8 +403,8 @@ def decision_function(X, Xnew, windows, sigma, labels, alpha, lam: float, eta=No
     Xn = _dev_f64(Xnew, "Xnew")
     if X.dim() != 2 or Xn.dim() != 2 or X.stride(1) != 1 or Xn.stride(1) != 1 or X.shape[1] != Xn.shape[1]:
         raise ValueError("X and Xnew must be 2-D row-major tensors with the same number of columns")
-    labels = _dev_f64(labels, "labels").contiguous()
-    alpha = _dev_f64(alpha, "alpha").contiguous()
+    labels = _dev_f64(labels, "labels")
+    alpha = _dev_f64(alpha, "alpha")
     win = np.ascontiguousarray(np.asarray(windows, dtype=np.int32).reshape(-1, 3))
     Pw = int(win.shape[0])
     sig = np.ascontiguousarray(np.broadcast_to(np.asarray(sigma, dtype=np.float64), (Pw,)))
@@ -398,14 +412,18 @@ def decision_function(X, Xnew, windows, sigma, labels, alpha, lam: float, eta=No
     if opts is None:
         opts = default_opts(**opt_kw)
     M = int(Xn.shape[0])
-    f = torch.empty(M, dtype=torch.float64, device=Xn.device)
-    _check(lib.anova_decision_function(ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), X.stride(0),
-                                       ctypes.c_void_p(Xn.data_ptr()), M, Xn.stride(0), int(X.shape[1]),
-                                       win.ctypes.data_as(ctypes.c_void_p), Pw, sig.ctypes.data_as(ctypes.c_void_p),
-                                       et.ctypes.data_as(ctypes.c_void_p) if et is not None else None,
-                                       ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()),
-                                       ctypes.c_void_p(alpha.data_ptr()), float(lam), ctypes.c_void_p(f.data_ptr()),
-                                       _stream(stream)))
+    with _on_stream(stream, X, Xn, labels, alpha) as s:
+        labels = labels.contiguous()
+        alpha = alpha.contiguous()
+        f = torch.empty(M, dtype=torch.float64, device=Xn.device)
+        _check(lib.anova_decision_function(ctypes.c_void_p(X.data_ptr()), int(X.shape[0]), X.stride(0),
+                                           ctypes.c_void_p(Xn.data_ptr()), M, Xn.stride(0), int(X.shape[1]),
+                                           win.ctypes.data_as(ctypes.c_void_p), Pw,
+                                           sig.ctypes.data_as(ctypes.c_void_p),
+                                           et.ctypes.data_as(ctypes.c_void_p) if et is not None else None,
+                                           ctypes.byref(opts), ctypes.c_void_p(labels.data_ptr()),
+                                           ctypes.c_void_p(alpha.data_ptr()), float(lam),
+                                           ctypes.c_void_p(f.data_ptr()), s))
     return f
 
 
@@ -418,16 +436,18 @@ def mi_windows(X, labels, bins: int = 32, P: int | None = None, stream=None):
     X = _dev_f64(X, "X")
     if X.dim() != 2 or X.stride(1) != 1:
         raise ValueError("X must be a 2-D row-major tensor")
-    y = _dev_f64(labels, "labels").contiguous()
+    y = _dev_f64(labels, "labels")
     N, d = int(X.shape[0]), int(X.shape[1])
     if y.shape != (N,):
         raise ValueError("labels must have shape (N,)")
     P = (d + 2) // 3 if P is None else int(P)
     win = np.full((max(P, 1), 3), -1, dtype=np.int32)
     mi = np.zeros(d, dtype=np.float64)
-    _check(lib.anova_mi_windows(ctypes.c_void_p(X.data_ptr()), N, d, X.stride(0), ctypes.c_void_p(y.data_ptr()),
-                                int(bins), P, win.ctypes.data_as(ctypes.c_void_p), mi.ctypes.data_as(ctypes.c_void_p),
-                                _stream(stream)))
+    with _on_stream(stream, X, y) as s:
+        y = y.contiguous()
+        _check(lib.anova_mi_windows(ctypes.c_void_p(X.data_ptr()), N, d, X.stride(0), ctypes.c_void_p(y.data_ptr()),
+                                    int(bins), P, win.ctypes.data_as(ctypes.c_void_p),
+                                    mi.ctypes.data_as(ctypes.c_void_p), s))
     return win[:P], mi
 
 
