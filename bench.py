@@ -7,13 +7,15 @@ stand-in for the paper's HIGGS-sized problems), 10 windows of 3 consecutive
 features, sigma = 1, NFFT bandwidth 32 per axis, oversampling 2,
 Kaiser-Bessel cutoff m = 4, 16 right-hand sides. One step = one full matvec
 Y = sum_l K_l X over all windows for the 16 right-hand sides, inputs and
-outputs resident in HBM (column-major FP64). Headline: the batched
-mixed-precision path (FP32 weights, grids and matrix-core contractions, FP64
-window sums). The FP64 and mixed one-vector forms on the same GPU are reported
-beside it. Accuracy: every run compares all rows and right-hand sides with
-the FP64 one-vector path on the GPU, and the oracle leg (the cpu_baseline
-measurement) checks the first right-hand side on the rows it samples; a run
-above relative l2 error 1e-4 reports value 0.
+outputs resident in HBM (column-major FP64). Headline: the batched FP64 path
+(FP64 records, grids, matrix-core contractions on v_mfma_f64_16x16x4f64 and
+window sums: the paper's precision). Beside it: the batched mixed-precision
+form (FP32 records and grids, FP32 matrix-core spread, split-bf16 matrix-core
+gather, FP64 window sums) and the FP64 and mixed one-vector forms on the same
+GPU. Accuracy: every run compares all rows and right-hand sides with the FP64
+one-vector path on the GPU, and the oracle leg (the cpu_baseline measurement)
+checks the first right-hand side on the rows it samples; a run above relative
+l2 error 1e-4 reports value 0.
 
 Also reported: IPM solve latency p50/p99 for the small plain problem and the
 full N = 500000 problem (MINRES, and GMRES with the block-triangular
@@ -42,7 +44,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6     # FP64 vector and FP64 MFMA
 FP32_PEAK_TFLOPS = 157.3    # FP32 vector and FP32 MFMA (dense)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batched_matvec_scaling_r16_hbm_traffic.md")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
+                 ("batched_matvec_scaling_r16_fp64_hbm_traffic.md", "batched_matvec_scaling_r16_hbm_traffic.md")]
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2312_00538_amd", "csrc", "matvec_batched.hip")
 
 
@@ -52,7 +55,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rhs", type=int, default=16)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-other-precision", dest="other_precision", action="store_false",
+                    help="skip the batched form in the other precision")
     ap.add_argument("--N", type=int, default=100_000)
     ap.add_argument("--reference-steps", type=int, default=30,
                     help="timed steps of the one-vector FP64 and mixed forms (0 = skip)")
@@ -111,17 +116,26 @@ def rel_err_cols(y, ref):
 
 def traffic_record():
     """HBM bytes per launch of the batched kernels, from the committed rocprofv3
-    counter summary, if that summary was taken from the current kernel source."""
-    try:
-        txt = open(TRAFFIC_FILE).read()
-    except OSError:
-        return None
-    m = re.search(r"traffic-data:\s*(\{.*\})", txt)
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
+    counter summaries that were taken from the current kernel source (one
+    record per summary, merged; kernel name -> bytes)."""
     sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-    return rec if rec.get("source_sha256") == sha else None
+    out = None
+    for path in TRAFFIC_FILES:
+        try:
+            txt = open(path).read()
+        except OSError:
+            continue
+        m = re.search(r"traffic-data:\s*(\{.*\})", txt)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("source_sha256") != sha:
+            continue
+        if out is None:
+            out = dict(rec)
+        elif rec.get("N") == out.get("N") and rec.get("rhs") == out.get("rhs"):
+            out.update({k: v for k, v in rec.items() if k.startswith("k_")})
+    return out
 
 
 def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
@@ -244,6 +258,72 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves):
     return out
 
 
+def matvec_form(lib, torch, p, X, xb, R, prec, steps, warmup, y_ref):
+    """One batched (or one-vector) form of the matvec workload: plan, timed
+    steps, stage times, accuracy against the FP64 one-vector path, and the
+    roofline of its dominant kernel."""
+    N, P = p.X.shape[0], p.windows.shape[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = lib.Plan(X, p.windows, p.sigma, precision=prec)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    yb = torch.empty((R, N), dtype=torch.float64, device=X.device)
+    plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
+    torch.cuda.synchronize()
+    y = yb.cpu().numpy().T.copy()               # N x R
+    rel_err = rel_err_cols(y, y_ref)
+    t_step, stages, passes = time_matvec(lib, torch, plan, xb, yb, N, R, steps, warmup)
+    f64 = prec == lib.PREC_FP64
+    batched = R >= 2 and info["cutoff_m"] == 4
+    rb = 16 if batched else 1               # right-hand sides per pass
+    per_pass = dict(stages)
+    # Roofline of the dominant kernel. Spread and gather each apply (2m)^3
+    # taps per point-window per right-hand side, 2 flops per tap (the
+    # algorithmic count; weights are evaluated once per plan). The batched
+    # path runs them as matrix-core contractions (FP64, or FP32 for the
+    # spread and split bf16 for the gather of the mixed form), the one-vector
+    # path on the vector ALUs. The grid step is bounded by its grid traffic.
+    W = 2 * info["cutoff_m"]
+    pw = N * P
+    dom = max(("spread", "gather", "fold", "convolve"), key=lambda s: per_pass[s])
+    t_dom = per_pass[dom] * 1e-3
+    if dom in ("spread", "gather"):
+        flops = 2.0 * W ** 3 * pw * rb
+        achieved = flops / t_dom / 1e12
+        peak = FP64_PEAK_TFLOPS if f64 else FP32_PEAK_TFLOPS
+        kname = ("k_%s_mfma%s" % (dom, "64" if f64 else "")) if batched else dom
+        roof = {"bound": "mfma" if batched else "alu", "kernel": kname,
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "algorithmic_flops_per_launch": flops,
+                "launch_ms": per_pass[dom]}
+        rec = traffic_record() if batched else None
+        if rec is not None and rec.get("N") == N and rec.get("rhs") == rb and kname in rec:
+            roof["traffic"] = rec[kname]
+            roof["traffic_unit"] = "bytes per launch"
+            roof["traffic_note"] = rec["note"]
+    else:
+        wb = 8 if f64 else 4
+        nbytes = 2.0 * info["grid_cells"] * wb * rb
+        achieved = nbytes / t_dom / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launch_ms": per_pass[dom]}
+    if f64:
+        precision = "fp64 (FP64 records, grids, matrix-core contractions and window sums)"
+    else:
+        precision = ("mixed (FP32 records and grids; spread on FP32 matrix cores, gather on bf16x3 split-precision "
+                     "matrix cores with FP32 sums; FP64 window sums)")
+    res = {"value": N * P * R / t_step, "unit": "points*windows/s", "ms_per_step": 1e3 * t_step,
+           "precision": precision, "path": "batched 16-wide" if batched else "one vector per pass",
+           "rel_err_vs_fp64_path": rel_err, "stage_ms_per_pass": per_pass, "passes_per_step": -(-R // rb),
+           "plan_ms": 1e3 * t_plan,
+           "plan": {k: info[k] for k in ("n_segments", "grid_cells", "device_bytes", "max_kernel_err")},
+           "roofline": roof, "y": y}
+    del plan, yb
+    return res
+
+
 def cpu_baseline(p, seconds):
     """The oracle (FP64 direct sum, C + OpenMP) on a bounded sample of target
     rows of the same workload (one right-hand side), scaled to
@@ -286,70 +366,27 @@ def main():
     P = p.windows.shape[0]
     prec = lib.PREC_FP64 if a.precision == "fp64" else lib.PREC_MIXED
     X = torch.as_tensor(p.X, device=dev)
-    t0 = time.perf_counter()
-    plan = lib.Plan(X, p.windows, p.sigma, precision=prec)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
-    info = plan.info()
     xb = colmajor(torch, p.v[:, :R], dev)
-    yb = torch.empty((R, N), dtype=torch.float64, device=dev)
-    plan.matvec_raw(xb.data_ptr(), R, N, yb.data_ptr(), N)
-    torch.cuda.synchronize()
-    y_head = yb.cpu().numpy().T.copy()          # N x R, checked below
-    # accuracy against the FP64 GPU path (one vector per pass, all rows and
-    # columns); the FP64 path's own accuracy against the oracle is what the
-    # parity tests establish, and the oracle leg below checks a sample again
+    # the FP64 one-vector path on all rows and columns: the accuracy reference
+    # of every batched form (the FP64 path's own accuracy against the oracle is
+    # what the parity tests establish; the oracle leg below checks a sample again)
     plr = lib.Plan(X, p.windows, p.sigma, precision=lib.PREC_FP64, batch_min_rhs=-1)
     yr = torch.empty((R, N), dtype=torch.float64, device=dev)
     plr.matvec_raw(xb.data_ptr(), R, N, yr.data_ptr(), N)
     torch.cuda.synchronize()
-    rel_err = rel_err_cols(y_head, yr.cpu().numpy().T)
+    y_fp64_1 = yr.cpu().numpy().T.copy()
     del plr, yr
 
-    t_step, stages, passes = time_matvec(lib, torch, plan, xb, yb, N, R, a.steps, a.warmup)
-    value = N * P * R / t_step
-    batched = prec == lib.PREC_MIXED and R >= 2 and info["cutoff_m"] == 4
-    rb = 16 if batched else 1               # right-hand sides per pass
-    npass = -(-R // rb)
-    per_pass = {k: v for k, v in stages.items()}
-
-    # Roofline of the dominant kernel. Spread and gather each apply (2m)^3
-    # taps per point-window per right-hand side, 2 flops per tap (the
-    # algorithmic count; weights are evaluated once per plan). The batched
-    # path runs them as FP32 matrix-core contractions, the one-vector path on
-    # the vector ALUs. The grid step is bounded by its grid traffic.
-    W = 2 * info["cutoff_m"]
-    pw = N * P
-    dom = max(("spread", "gather", "fold", "convolve"), key=lambda s: per_pass[s])
-    t_dom = per_pass[dom] * 1e-3
-    if dom in ("spread", "gather"):
-        flops = 2.0 * W ** 3 * pw * rb
-        achieved = flops / t_dom / 1e12
-        peak = FP64_PEAK_TFLOPS if prec == lib.PREC_FP64 else FP32_PEAK_TFLOPS
-        roof = {"bound": "mfma" if batched else "alu", "kernel": ("k_%s_mfma" % dom) if batched else dom,
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "algorithmic_flops_per_launch": flops,
-                "launch_ms": per_pass[dom]}
-        rec = traffic_record() if batched else None
-        if rec is not None and rec.get("N") == N and rec.get("rhs") == rb and roof["kernel"] in rec:
-            roof["traffic"] = rec[roof["kernel"]]
-            roof["traffic_unit"] = "bytes per launch"
-            roof["traffic_note"] = rec["note"]
-    else:
-        wb = 8 if prec == lib.PREC_FP64 else 4
-        nbytes = 2.0 * info["grid_cells"] * wb * rb
-        achieved = nbytes / t_dom / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launch_ms": per_pass[dom]}
-
+    head = matvec_form(lib, torch, p, X, xb, R, prec, a.steps, a.warmup, y_fp64_1)
+    y_head = head.pop("y")
     out = {
         "metric": "ANOVA-NFFT matvec points*windows/s at rel.err<=1e-4; IPM solve p50/p99 ms",
-        "value": value,
+        "value": head["value"],
         "unit": "points*windows/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * t_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -357,20 +394,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"matvec-scaling: N={N} d={d} two-class Gaussian mixture, {P} windows x 3 "
                                f"features, sigma=1, bandwidth 32, oversampling 2, m=4, {R} right-hand sides",
-                   "N": N, "d": d, "windows": P, "rhs": R,
-                   "precision": "mixed (FP32 spread/grid/gather, FP64 window sums)" if prec else "fp64",
-                   "path": "batched 16-wide" if batched else "one vector per pass"},
-        "rel_err_vs_fp64_path": rel_err,
-        "stage_ms_per_pass": per_pass,
-        "passes_per_step": npass,
-        "plan_ms": 1e3 * t_plan,
-        "plan": {k: info[k] for k in ("n_segments", "grid_cells", "device_bytes", "max_kernel_err")},
-        "roofline": roof,
+                   "N": N, "d": d, "windows": P, "rhs": R, "precision": head["precision"], "path": head["path"]},
+        "rel_err_vs_fp64_path": head["rel_err_vs_fp64_path"],
+        "stage_ms_per_pass": head["stage_ms_per_pass"],
+        "passes_per_step": head["passes_per_step"],
+        "plan_ms": head["plan_ms"],
+        "plan": head["plan"],
+        "roofline": head["roofline"],
     }
-    if rel_err > 1e-4:
+    if head["rel_err_vs_fp64_path"] > 1e-4:
         out["value"] = 0.0
-        out["error"] = f"accuracy bar missed: rel_err {rel_err:.3e} > 1e-4 against the FP64 path"
-    del plan, xb, yb
+        out["error"] = f"accuracy bar missed: rel_err {head['rel_err_vs_fp64_path']:.3e} > 1e-4 against the FP64 path"
+    # the other precision's batched form on the same workload and right-hand sides
+    if a.other_precision and R >= 2:
+        other = lib.PREC_MIXED if prec == lib.PREC_FP64 else lib.PREC_FP64
+        o = matvec_form(lib, torch, p, X, xb, R, other, a.steps, a.warmup, y_fp64_1)
+        o.pop("y")
+        out["mixed_16rhs" if other == lib.PREC_MIXED else "fp64_16rhs"] = o
+    del xb
 
     # the one-vector forms on the same GPU at the same accuracy bar
     one_vec = {}

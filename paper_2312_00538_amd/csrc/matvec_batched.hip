@@ -23,6 +23,11 @@ constexpr int kT = 256;
 inline unsigned nblk(int64_t n, int t = kT) { return unsigned(std::max<int64_t>(1, (n + t - 1) / t)); }
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+// four consecutive values of the element type, moved as one vector access
+template <class T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <class T> using v4 = typename Vec4<T>::type;
 
 __device__ inline void wait_vmem_b() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
@@ -38,19 +43,20 @@ struct ColPtrs {
     double* y[RB];
 };
 
-// xt[i][r] = x_r[i] in FP32 (zero for r >= R); 64 points per block, transposed
-// through LDS so that both the reads and the writes are coalesced. Also resets
-// the spread and gather work queues of the pass.
-__global__ __launch_bounds__(256) void k_transpose_in(const ColPtrs cols, int R, int64_t N, float* __restrict__ xt,
+// xt[i][r] = x_r[i] in the pass's element type (zero for r >= R); 64 points per
+// block, transposed through LDS so that both the reads and the writes are
+// coalesced. Also resets the spread and gather work queues of the pass.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose_in(const ColPtrs cols, int R, int64_t N, T* __restrict__ xt,
                                                       int32_t* __restrict__ queues) {
-    __shared__ float s[RB][65];
+    __shared__ T s[RB][65];
     if (blockIdx.x == 0 && threadIdx.x < 2) queues[threadIdx.x] = 0;  // work queues of this pass
     const int64_t i0 = int64_t(blockIdx.x) * 64;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int e = j * 256 + threadIdx.x;
         const int r = e / 64, i = e % 64;  // r is uniform across a wavefront
-        s[r][i] = (r < R && i0 + i < N) ? float(cols.x[r][i0 + i]) : 0.0f;
+        s[r][i] = (r < R && i0 + i < N) ? T(cols.x[r][i0 + i]) : T(0);
     }
     __syncthreads();
 #pragma unroll
@@ -424,15 +430,349 @@ __global__ __launch_bounds__(64, 2) void k_gather_mfma(const int32_t* __restrict
     }
 }
 
+// ---------------------------------------------------------------- FP64 spread and gather (3 features, MFMA)
+// The FP64 path runs the same contractions on v_mfma_f64_16x16x4f64 with FP64
+// records, inputs, grids and sums. Its accumulators and grid tiles take twice
+// the registers of the FP32 ones, so a wavefront takes one half of the 16
+// right-hand sides (work item = (segment, half)): M = 8 x taps x 8 rhs.
+// Operand layouts as for the FP32 instruction (A: lane (i, k), B: lane (k, j)),
+// but the result row of register v in lane (j, g) is g + 4 v (not 4 g + v).
+// Row i of m-block mb is therefore (x tap a = mb + 4 (i & 1), rhs
+// r8 = 4 ((i >> 1) & 1) + (i >> 2)), so that a lane's four results are four
+// consecutive right-hand sides of one x tap (lane group g: a = mb + 4 (g & 1),
+// r8 = 4 (g >> 1) + v) and the four x taps of a lane's A operands are four
+// consecutive doubles of the record.
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+constexpr int RHW = 8;      // right-hand sides per wavefront in the FP64 contractions
+__device__ inline int row_rhs64(int i) { return 4 * ((i >> 1) & 1) + (i >> 2); }
+constexpr int REC64 = 24;   // doubles per FP64 point record: x, y and z taps
+
+// CHB records as stored (24 doubles each, 6 KB): 1 KB slot j, lane l moves bytes
+// 1024 j + 16 l of the chunk (one 16-byte piece of record (1024 j + 16 l) / 192).
+__device__ inline void stage_records64(double* lrec, const double* __restrict__ wts, int64_t base, int cstart,
+                                       int count, int lane) {
+    const int last = count - 1 - cstart;
+#pragma unroll
+    for (int j = 0; j < CHB * REC64 * 8 / 1024; ++j) {
+        const int o = j * 1024 + lane * 16;
+        dma16(wts + (base + cstart + min(o / (REC64 * 8), last)) * REC64 + (o % (REC64 * 8)) / 8, lrec + j * 128);
+    }
+}
+
+// CHB records with the z taps repeated (32 doubles each, 8 KB), so that any 8
+// cyclically consecutive z taps are 8 consecutive doubles: 4 records per slot.
+__device__ inline void stage_records64_ring(double* lrec, const double* __restrict__ wts, int64_t base, int cstart,
+                                            int count, int lane) {
+    const int last = count - 1 - cstart;
+    const int e = (lane % 16) * 2;
+#pragma unroll
+    for (int j = 0; j < CHB / 4; ++j)
+        dma16(wts + (base + cstart + min(j * 4 + lane / 16, last)) * REC64 + (e < 24 ? e : e - 8), lrec + j * 128);
+}
+
+// This wavefront's 8 right-hand sides of two value rows (16 rows per slot,
+// 64 bytes each: four lanes per row).
+__device__ inline void stage_values64(double* lval, const double* __restrict__ xt, const int32_t (&pr)[2], int half,
+                                      int lane) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) dma16(xt + int64_t(pr[j]) * RB + RHW * half + (lane % 4) * 2, lval + j * 128);
+}
+
+__device__ inline void lds_spread_operands64(uint32_t ax, uint32_t ay, uint32_t az, uint32_t av, d2& wx01, d2& wx23,
+                                             d2& wy01, d2& wy23, double& wz, double& v) {
+    asm volatile(
+        "ds_read_b128 %0, %6\n\t"
+        "ds_read_b128 %1, %6 offset:16\n\t"
+        "ds_read_b128 %2, %7\n\t"
+        "ds_read_b128 %3, %7 offset:16\n\t"
+        "ds_read_b64 %4, %8\n\t"
+        "ds_read_b64 %5, %9\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx01), "=&v"(wx23), "=&v"(wy01), "=&v"(wy23), "=&v"(wz), "=&v"(v)
+        : "v"(ax), "v"(ay), "v"(az), "v"(av)
+        : "memory");
+}
+
+__device__ inline void lds_gather_operands64(uint32_t ax, uint32_t ay, uint32_t az, d2& wx01, d2& wx23, double& wy0,
+                                             double& wy1, double (&wz)[8]) {
+    asm volatile(
+        "ds_read_b128 %0, %12\n\t"
+        "ds_read_b128 %1, %12 offset:16\n\t"
+        "ds_read_b64 %2, %13\n\t"
+        "ds_read_b64 %3, %13 offset:32\n\t"
+        "ds_read_b64 %4, %14\n\t"
+        "ds_read_b64 %5, %14 offset:8\n\t"
+        "ds_read_b64 %6, %14 offset:16\n\t"
+        "ds_read_b64 %7, %14 offset:24\n\t"
+        "ds_read_b64 %8, %14 offset:32\n\t"
+        "ds_read_b64 %9, %14 offset:40\n\t"
+        "ds_read_b64 %10, %14 offset:48\n\t"
+        "ds_read_b64 %11, %14 offset:56\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx01), "=&v"(wx23), "=&v"(wy0), "=&v"(wy1), "=&v"(wz[0]), "=&v"(wz[1]), "=&v"(wz[2]), "=&v"(wz[3]),
+          "=&v"(wz[4]), "=&v"(wz[5]), "=&v"(wz[6]), "=&v"(wz[7])
+        : "v"(ax), "v"(ay), "v"(az)
+        : "memory");
+}
+
+__device__ inline void lds_store_d2(uint32_t addr, d2 v) {
+    asm volatile("ds_write_b128 %0, %1" : : "v"(addr), "v"(v) : "memory");
+}
+
+__device__ inline d2 lds_load_d2(uint32_t addr) {
+    d2 v;
+    asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr) : "memory");
+    return v;
+}
+
+// Spread, FP64. Accumulator tile (mb, nb) of 16 x 16: rows as above, columns
+// n = lr -> (y tap b = nb + 4 (lr >> 3), physical z column lr & 7); the lane
+// (lr, lk) holds x tap mb + 4 (lk & 1) and right-hand sides 4 (lk >> 1) .. + 3
+// of its half, in column lr. A step takes 4 points.
+__global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
+                                                         int32_t* __restrict__ queue,
+                                                         const Segment* __restrict__ segs,
+                                                         const int32_t* __restrict__ lstart,
+                                                         const int32_t* __restrict__ lstart_off,
+                                                         const WinDev* __restrict__ wins,
+                                                         const uint8_t* __restrict__ alone,
+                                                         const double* __restrict__ wts,
+                                                         const int32_t* __restrict__ perm,
+                                                         const double* __restrict__ xt, int64_t N,
+                                                         double* __restrict__ slab, double* __restrict__ tgt) {
+    constexpr int STEP = CHB - 4;
+    __shared__ __align__(16) double srec[2][CHB * REC64];
+    __shared__ __align__(16) double sval[2][CHB * RHW];
+    __shared__ __align__(16) double stg[64 * RHW];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(queue, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= nwork) break;
+        const int sid = wave_items[it >> 1];
+        const int half = it & 1;
+        const Segment sg = segs[sid];
+        const WinDev& wd = wins[sg.win];
+        const int lr = lane & 15, lk = lane >> 4;
+        const int64_t base = int64_t(sg.win) * N + sg.start;
+        const int32_t* ls = lstart + lstart_off[sid];
+        const bool direct = alone[sid] != 0;
+        const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+        const int E1 = wd.E[1], E2 = wd.E[2];
+        // output addressing as in k_spread_mfma
+        const int64_t SA = direct ? int64_t(64 * E1 + 8) * E2 : 8;
+        const int64_t SB = direct ? int64_t(65) * E2 : 1;
+        const int64_t U0 = direct ? wd.tgt_off + (int64_t(cx) * E1 + cy) * 64 * E2 : sg.off - int64_t(sg.z0) * 64;
+        const int64_t UL = direct ? 1 : 64;
+        double* const outp = direct ? tgt : slab;
+        d4 acc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        // Write z cell `layer` of this half and clear it: rows [8 a + b][8 rhs]
+        // through LDS, then four lanes per 64-byte half row.
+        const uint32_t stg0 = lds_addr(&stg[0]);
+        auto flush = [&](int layer) __attribute__((always_inline)) {
+            if ((lr & 7) == (layer & 7)) {
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb) {
+                        const int ab = (mb + 4 * (lk & 1)) * 8 + nb + 4 * (lr >> 3);
+                        const uint32_t ad = stg0 + uint32_t(ab * RHW + 4 * (lk >> 1)) * 8;
+                        const d4 a = acc[mb * 4 + nb];
+                        lds_store_d2(ad, d2{a[0], a[1]});
+                        lds_store_d2(ad + 16, d2{a[2], a[3]});
+                        acc[mb * 4 + nb] = d4{0.0, 0.0, 0.0, 0.0};
+                    }
+            }
+            lds_wait();
+            __syncthreads();
+            double* const row = outp + (U0 + int64_t(layer) * UL) * RB + RHW * half + 2 * (lane & 3);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ab = 16 * j + (lane >> 2);
+                const d2 v = lds_load_d2(stg0 + uint32_t(ab * RHW + 2 * (lane & 3)) * 8);
+                *reinterpret_cast<d2*>(row + ((ab >> 3) * SA + (ab & 7) * SB) * RB) = v;
+            }
+        };
+        const uint32_t rec0 = lds_addr(&srec[0][0]), val0 = lds_addr(&sval[0][0]);
+        constexpr uint32_t RECB = CHB * REC64 * 8, VALB = CHB * RHW * 8;  // bytes per buffer
+        int cc = -1;
+        int32_t prow[2];
+        stage_records64(srec[0], wts, base, 0, sg.count, lane);
+        value_rows(perm, base, 0, sg.count, lane, prow);
+        stage_values64(sval[0], xt, prow, half, lane);
+        if (STEP < sg.count) value_rows(perm, base, STEP, sg.count, lane, prow);
+        for (int z = sg.z0; z <= sg.z1; ++z) {
+            const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+            for (int k = p; k < q; k += 4) {
+                const int c = k / STEP;
+                if (c > cc) {  // chunk c has landed (and earlier stores have drained); prefetch c + 1
+                    wait_vmem_b();
+                    __syncthreads();
+                    cc = c;
+                    if ((c + 1) * STEP < sg.count) {
+                        stage_records64(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                        stage_values64(sval[(c + 1) & 1], xt, prow, half, lane);
+                        if ((c + 2) * STEP < sg.count) value_rows(perm, base, (c + 2) * STEP, sg.count, lane, prow);
+                    }
+                }
+                const int pt = k + lk;
+                const uint32_t slot = uint32_t(pt - c * STEP);
+                const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + slot * (REC64 * 8);
+                d2 wx01, wx23, wy01, wy23;
+                double wz, v;
+                lds_spread_operands64(rb + 32 * uint32_t(lr & 1), rb + 64 + 32 * uint32_t(lr >> 3),
+                                      rb + 128 + 8 * uint32_t((lr - z) & 7),
+                                      val0 + uint32_t(c & 1) * VALB + (slot * RHW + row_rhs64(lr)) * 8, wx01, wx23,
+                                      wy01, wy23, wz, v);
+                v = pt < q ? v : 0.0;
+                const double av[4] = {v * wx01[0], v * wx01[1], v * wx23[0], v * wx23[1]};
+                const double bv[4] = {wy01[0] * wz, wy01[1] * wz, wy23[0] * wz, wy23[1] * wz};
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 4; ++nb)
+                        acc[mb * 4 + nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mb], bv[nb], acc[mb * 4 + nb], 0, 0, 0);
+            }
+            flush(z);
+        }
+        for (int j = 1; j < 8; ++j) flush(sg.z1 + j);
+    }
+}
+
+// Gather, FP64: S[(a, r)][p] = sum_K H[(a, r)][K] B[K][p] over the 64 taps, in
+// 16 k-steps ks of 4: k-index lk of step ks is tap (y tap b = 4 (ks >> 3) + lk,
+// ring column c = ks & 7), so a lane holds one tap of each ring column per
+// y-tap group and refilling column c after a layer touches H[.][c] and
+// H[.][c + 8] in every lane. D[mb] holds, in lane (point lr, lk), the rows
+// (x tap mb + 4 (lk & 1), rhs 4 (lk >> 1) .. + 3); f sums the x taps of
+// a < 4 in the lanes with even lk, adds those of a >= 4 from lane + 16, and
+// stores.
+__global__ __launch_bounds__(64, 2) void k_gather_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
+                                                         int32_t* __restrict__ queue,
+                                                         const Segment* __restrict__ segs,
+                                                         const int32_t* __restrict__ lstart,
+                                                         const int32_t* __restrict__ lstart_off,
+                                                         const WinDev* __restrict__ wins,
+                                                         const double* __restrict__ wts,
+                                                         const double* __restrict__ h, int64_t N,
+                                                         double* __restrict__ fs) {
+    constexpr int STEP = CHB - 16;
+    constexpr int RPD = 32;  // doubles per staged record (z taps repeated)
+    __shared__ __align__(16) double srec[2][CHB * RPD];
+    const int lane = threadIdx.x;
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(queue, 1);
+        it = __builtin_amdgcn_readfirstlane(it);
+        if (it >= nwork) break;
+        const int sid = wave_items[it >> 1];
+        const int half = it & 1;
+        const Segment sg = segs[sid];
+        const WinDev& wd = wins[sg.win];
+        const int lr = lane & 15, lk = lane >> 4;
+        const int64_t base = int64_t(sg.win) * N + sg.start;
+        const int32_t* ls = lstart + lstart_off[sid];
+        const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
+        const int Ey = wd.E[1], Ez = wd.E[2];
+        // h[x][z][y][r]: rows of this lane are x = cx + mb + 4 (lr & 1), rhs 8 half + row_rhs64(lr)
+        const double* hp = h + (wd.grid_off + int64_t(cx + 4 * (lr & 1)) * Ez * Ey + cy + lk) * RB + RHW * half +
+                           row_rhs64(lr);
+        double H[4][16];
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int layer = sg.z0 + (((ks & 7) - sg.z0) & 7);
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb) H[mb][ks] = hp[((int64_t(mb) * Ez + layer) * Ey + 4 * (ks >> 3)) * RB];
+        }
+        double pre[4][2];
+        if (sg.z0 < sg.z1) {
+#pragma unroll
+            for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                for (int k2 = 0; k2 < 2; ++k2) pre[mb][k2] = hp[((int64_t(mb) * Ez + sg.z0 + 8) * Ey + 4 * k2) * RB];
+        }
+        const uint32_t rec0 = lds_addr(&srec[0][0]);
+        constexpr uint32_t RECB = CHB * RPD * 8;
+        int cc = -1;
+        stage_records64_ring(srec[0], wts, base, 0, sg.count, lane);
+        for (int z = sg.z0; z <= sg.z1; ++z) {
+            const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+            for (int k = p; k < q; k += 16) {
+                const int c = k / STEP;
+                if (c > cc) {
+                    wait_vmem_b();
+                    __syncthreads();
+                    cc = c;
+                    if ((c + 1) * STEP < sg.count)
+                        stage_records64_ring(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                }
+                const int pt = k + lr;
+                const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + uint32_t(pt - c * STEP) * (RPD * 8);
+                d2 wx01, wx23;
+                double wy0, wy1, wz[8];  // wz[c]: z tap of ring column c, (c - z) & 7
+                lds_gather_operands64(rb + 32 * uint32_t(lk & 1), rb + 64 + 8 * uint32_t(lk),
+                                      rb + 128 + 8 * uint32_t((-z) & 7), wx01, wx23, wy0, wy1, wz);
+                double B[16];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    B[j] = wy0 * wz[j];
+                    B[8 + j] = wy1 * wz[j];
+                }
+                d4 D[4];
+#pragma unroll
+                for (int mb = 0; mb < 4; ++mb) D[mb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < 16; ++ks)
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb) D[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(H[mb][ks], B[ks], D[mb], 0, 0, 0);
+                d4 f = wx01[0] * D[0];
+                f += wx01[1] * D[1];
+                f += wx23[0] * D[2];
+                f += wx23[1] * D[3];
+                d4 o;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) o[i] = __shfl_xor(f[i], 16);
+                if ((lk & 1) == 0 && pt < q)
+                    *reinterpret_cast<d4*>(fs + (base + pt) * RB + RHW * half + 4 * (lk >> 1)) = f + o;
+            }
+            if (z < sg.z1) {  // column z mod 8 takes layer z + 8; load layer z + 9 for the next column
+                switch (z & 7) {
+#define ANV_REFILL64(J)                                  \
+    case J:                                              \
+        _Pragma("unroll") for (int mb = 0; mb < 4; ++mb) { \
+            H[mb][J] = pre[mb][0];                       \
+            H[mb][J + 8] = pre[mb][1];                   \
+        }                                                \
+        break;
+                    ANV_REFILL64(0) ANV_REFILL64(1) ANV_REFILL64(2) ANV_REFILL64(3)
+                    ANV_REFILL64(4) ANV_REFILL64(5) ANV_REFILL64(6) ANV_REFILL64(7)
+#undef ANV_REFILL64
+                }
+                if (z + 1 < sg.z1) {
+#pragma unroll
+                    for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+                        for (int k2 = 0; k2 < 2; ++k2)
+                            pre[mb][k2] = hp[((int64_t(mb) * Ez + z + 9) * Ey + 4 * k2) * RB];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- 1 and 2 features: one lane per (item, rhs)
-template <int W, int WY>
+template <int W, int WY, class T>
 __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict__ items, int nitems,
                                                       const Segment* __restrict__ segs,
                                                       const int32_t* __restrict__ zq,
-                                                      const float* __restrict__ wts,
+                                                      const T* __restrict__ wts,
                                                       const int32_t* __restrict__ perm,
-                                                      const float* __restrict__ xt, int64_t N,
-                                                      float* __restrict__ slab) {
+                                                      const T* __restrict__ xt, int64_t N,
+                                                      T* __restrict__ slab) {
     const int64_t t = blockIdx.x * int64_t(64) + threadIdx.x;
     if (t >= int64_t(nitems) * RB) return;
     const int sid = items[t / RB];
@@ -440,12 +780,12 @@ __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict_
     if (sid < 0) return;
     const Segment sg = segs[sid];
     const int64_t base = int64_t(sg.win) * N + sg.start;
-    constexpr int REC = rec_stride(W, 4);
-    float acc[WY][W];
+    constexpr int REC = rec_stride(W, int(sizeof(T)));
+    T acc[WY][W];
 #pragma unroll
     for (int b = 0; b < WY; ++b)
 #pragma unroll
-        for (int c = 0; c < W; ++c) acc[b][c] = 0.f;
+        for (int c = 0; c < W; ++c) acc[b][c] = T(0);
     int zr = sg.z0;
     for (int k = 0; k < sg.count; ++k) {
         const int64_t gi = base + k;
@@ -457,15 +797,15 @@ __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict_
             for (int b = 0; b < WY; ++b) {
 #pragma unroll
                 for (int c = 0; c < W - 1; ++c) acc[b][c] = acc[b][c + 1];
-                acc[b][W - 1] = 0.f;
+                acc[b][W - 1] = T(0);
             }
             ++zr;
         }
-        const float* w = wts + gi * REC;
-        const float v = xt[int64_t(perm[gi]) * RB + r];
+        const T* w = wts + gi * REC;
+        const T v = xt[int64_t(perm[gi]) * RB + r];
 #pragma unroll
         for (int b = 0; b < WY; ++b) {
-            const float cb = v * w[W + b];
+            const T cb = v * w[W + b];
 #pragma unroll
             for (int c = 0; c < W; ++c) acc[b][c] += cb * w[2 * W + c];
         }
@@ -476,14 +816,14 @@ __global__ __launch_bounds__(64) void k_spread_lane_b(const int32_t* __restrict_
         for (int b = 0; b < WY; ++b) slab[(sg.off + int64_t(zr - sg.z0 + c) * WY + b) * RB + r] = acc[b][c];
 }
 
-template <int W, int WY>
+template <int W, int WY, class T>
 __global__ __launch_bounds__(64) void k_gather_lane_b(const int32_t* __restrict__ items, int nitems,
                                                       const Segment* __restrict__ segs,
                                                       const WinDev* __restrict__ wins,
                                                       const int32_t* __restrict__ zq,
-                                                      const float* __restrict__ wts,
-                                                      const float* __restrict__ h, int64_t N,
-                                                      float* __restrict__ fs) {
+                                                      const T* __restrict__ wts,
+                                                      const T* __restrict__ h, int64_t N,
+                                                      T* __restrict__ fs) {
     const int64_t t = blockIdx.x * int64_t(64) + threadIdx.x;
     if (t >= int64_t(nitems) * RB) return;
     const int sid = items[t / RB];
@@ -493,10 +833,10 @@ __global__ __launch_bounds__(64) void k_gather_lane_b(const int32_t* __restrict_
     const WinDev& wd = wins[sg.win];
     const int cx = sg.col / wd.nb[1], cy = sg.col % wd.nb[1];
     const int Ey = wd.E[1];
-    const float* hp = h + (wd.grid_off + int64_t(cx) * wd.E[2] * Ey + cy) * RB + r;
+    const T* hp = h + (wd.grid_off + int64_t(cx) * wd.E[2] * Ey + cy) * RB + r;
     const int64_t base = int64_t(sg.win) * N + sg.start;
-    constexpr int REC = rec_stride(W, 4);
-    float hr[WY][W];
+    constexpr int REC = rec_stride(W, int(sizeof(T)));
+    T hr[WY][W];
     int zr = sg.z0;
 #pragma unroll
     for (int c = 0; c < W; ++c)
@@ -514,11 +854,11 @@ __global__ __launch_bounds__(64) void k_gather_lane_b(const int32_t* __restrict_
             }
             ++zr;
         }
-        const float* w = wts + gi * REC;
-        float sy = 0.f;
+        const T* w = wts + gi * REC;
+        T sy = T(0);
 #pragma unroll
         for (int b = 0; b < WY; ++b) {
-            float s = 0.f;
+            T s = T(0);
 #pragma unroll
             for (int c = 0; c < W; ++c) s += w[2 * W + c] * hr[b][c];
             sy += w[W + b] * s;
@@ -528,10 +868,11 @@ __global__ __launch_bounds__(64) void k_gather_lane_b(const int32_t* __restrict_
 }
 
 // ---------------------------------------------------------------- fold and grid step, 16 rhs innermost
+template <class T>
 __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ wins, int32_t P, int64_t nlist,
                                                      const int64_t* __restrict__ flist, const int2* __restrict__ fold,
-                                                     const int64_t* __restrict__ sbase, const float* __restrict__ slab,
-                                                     float* __restrict__ tgt) {
+                                                     const int64_t* __restrict__ sbase, const T* __restrict__ slab,
+                                                     T* __restrict__ tgt) {
     __shared__ double red[256][4];
     const int64_t fi = blockIdx.x;
     if (fi >= nlist) return;
@@ -553,7 +894,7 @@ __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ 
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     if (part < parts) {
         for (int s = rr.x + part; s < rr.y; s += parts) {
-            const f4 v = *reinterpret_cast<const f4*>(slab + (sbase[s] + int64_t(L) * lanes + pos) * RB + 4 * q4);
+            const v4<T> v = *reinterpret_cast<const v4<T>*>(slab + (sbase[s] + int64_t(L) * lanes + pos) * RB + 4 * q4);
             s0 += v[0];
             s1 += v[1];
             s2 += v[2];
@@ -571,8 +912,7 @@ __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[i] += red[(q * lanes + pos) * 4 + q4][i];
     const int64_t tt = ((int64_t(cx + a) * wd.E[1] + (cy + b)) * lanes + pos) * wd.E[2] + L;
-    *reinterpret_cast<f4*>(tgt + (wd.tgt_off + tt) * RB + 4 * q4) =
-        f4{float(o[0]), float(o[1]), float(o[2]), float(o[3])};
+    *reinterpret_cast<v4<T>*>(tgt + (wd.tgt_off + tt) * RB + 4 * q4) = v4<T>{T(o[0]), T(o[1]), T(o[2]), T(o[3])};
 }
 
 // Blocks are dealt to the 8 XCDs in turn (block i to XCD i mod 8). The nrs
@@ -590,13 +930,14 @@ __device__ inline bool xcd_group(int nrs, int ne, int ngroups, int& slice, int& 
 }
 
 // fold step B + y and z passes; block per (x slice, window, slice of the rhs)
-template <int W>
+template <int W, class T>
 __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restrict__ wins,
                                                          const double* __restrict__ tmat,
                                                          const int2* __restrict__ crange,
-                                                         const float* __restrict__ tgt, float* __restrict__ g1,
+                                                         const T* __restrict__ tgt, T* __restrict__ g1,
                                                          int RH, int ne, int P) {
-    extern __shared__ __align__(16) float smf[];
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    T* const smf = reinterpret_cast<T*>(sm_raw);
     int x, l, rs;
     if (!xcd_group(RB / RH, ne, ne * P, x, l, rs)) return;
     const WinDev& wd = wins[l];
@@ -608,17 +949,17 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
     // Toeplitz matrices transposed, rows padded to a multiple of 4 with zeros:
     // tyT[k][y] = Ty[y][k], so that 4 consecutive outputs read their 4
     // coefficients of tap k in one 16-byte access
-    float* tyT = smf;
-    float* tzT = tyT + Ey * Eyp;
-    float* s0 = tzT + Ez * Ezp;  // [y][z][RH]
-    float* s1 = s0 + S * RH;
+    T* tyT = smf;
+    T* tzT = tyT + Ey * Eyp;
+    T* s0 = tzT + Ez * Ezp;  // [y][z][RH]
+    T* s1 = s0 + S * RH;
     for (int e = threadIdx.x; e < Ey * Eyp; e += blockDim.x) {
         const int k = e / Eyp, y = e % Eyp;
-        tyT[e] = y < Ey ? float(tmat[wd.t_off[1] + y * Ey + k]) : 0.f;
+        tyT[e] = y < Ey ? T(tmat[wd.t_off[1] + y * Ey + k]) : T(0);
     }
     for (int e = threadIdx.x; e < Ez * Ezp; e += blockDim.x) {
         const int k = e / Ezp, z = e % Ezp;
-        tzT[e] = z < Ez ? float(tmat[wd.t_off[2] + z * Ez + k]) : 0.f;
+        tzT[e] = z < Ez ? T(tmat[wd.t_off[2] + z * Ez + k]) : T(0);
     }
     __shared__ int2 rng[W][65];
     const int wx = wd.Wslot[0], wy = wd.Wslot[1], nby = wd.nb[1];
@@ -633,8 +974,8 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
     for (int e = threadIdx.x; e < S * RH; e += blockDim.x) {
         const int cell = e / RH, r = e % RH;
         const int y = cell / Ez, zz = cell % Ez;
-        const float* tl = tgt + (wd.tgt_off + (int64_t(x) * Ey + y) * wd.lanes * Ez + zz) * RB + r0 + r;
-        float acc = 0.f;
+        const T* tl = tgt + (wd.tgt_off + (int64_t(x) * Ey + y) * wd.lanes * Ez + zz) * RB + r0 + r;
+        T acc = T(0);
 #pragma unroll
         for (int a = 0; a < W; ++a)
 #pragma unroll
@@ -645,8 +986,8 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
                 // no points reaching layer z; every lane loads (a valid address) so
                 // that all 64 loads are in flight at once, and the select drops it
                 const bool ok = zz >= rr.x && zz <= rr.y;
-                const float v = tl[ok ? int64_t(a * wy + b) * Ez * RB : 0];
-                acc += ok ? v : 0.f;
+                const T v = tl[ok ? int64_t(a * wy + b) * Ez * RB : 0];
+                acc += ok ? v : T(0);
             }
         s0[e] = acc;
     }
@@ -655,35 +996,35 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
     // makes y = y0 .. y0 + 3 from one read of s0 per tap
     for (int e = threadIdx.x; e < (Eyp / 4) * Ez * RH; e += blockDim.x) {
         const int r = e % RH, zz = (e / RH) % Ez, y0 = 4 * (e / (RH * Ez));
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
         for (int k = 0; k < Ey; ++k) {
-            const float v = s0[(k * Ez + zz) * RH + r];
-            const f4 t = *reinterpret_cast<const f4*>(tyT + k * Eyp + y0);
+            const T v = s0[(k * Ez + zz) * RH + r];
+            const v4<T> t = *reinterpret_cast<const v4<T>*>(tyT + k * Eyp + y0);
             a0 += t[0] * v;
             a1 += t[1] * v;
             a2 += t[2] * v;
             a3 += t[3] * v;
         }
-        const float av[4] = {a0, a1, a2, a3};
+        const T av[4] = {a0, a1, a2, a3};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (y0 + i < Ey) s1[((y0 + i) * Ez + zz) * RH + r] = av[i];
     }
     __syncthreads();
     // z pass, g1[x][y][z][r] = sum_k Tz[z][k] s1[y][k][r]; z = z0 .. z0 + 3 per thread
-    float* out = g1 + (wd.grid_off + int64_t(x) * S) * RB + r0;
+    T* out = g1 + (wd.grid_off + int64_t(x) * S) * RB + r0;
     for (int e = threadIdx.x; e < Ey * (Ezp / 4) * RH; e += blockDim.x) {
         const int r = e % RH, z0 = 4 * ((e / RH) % (Ezp / 4)), y = e / (RH * (Ezp / 4));
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
         for (int k = 0; k < Ez; ++k) {
-            const float v = s1[(y * Ez + k) * RH + r];
-            const f4 t = *reinterpret_cast<const f4*>(tzT + k * Ezp + z0);
+            const T v = s1[(y * Ez + k) * RH + r];
+            const v4<T> t = *reinterpret_cast<const v4<T>*>(tzT + k * Ezp + z0);
             a0 += t[0] * v;
             a1 += t[1] * v;
             a2 += t[2] * v;
             a3 += t[3] * v;
         }
-        const float av[4] = {a0, a1, a2, a3};
+        const T av[4] = {a0, a1, a2, a3};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (z0 + i < Ez) out[int64_t(y * Ez + z0 + i) * RB + r] = av[i];
@@ -691,10 +1032,12 @@ __global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restric
 }
 
 // x pass; block per (y slice, window, rhs half); output h[x][z][y][rhs]
+template <class T>
 __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wins, const double* __restrict__ tmat,
-                                                   const float* __restrict__ g1, float* __restrict__ h, int RH, int ne,
+                                                   const T* __restrict__ g1, T* __restrict__ h, int RH, int ne,
                                                    int P) {
-    extern __shared__ __align__(16) float smf[];
+    extern __shared__ __align__(16) unsigned char sm_raw[];
+    T* const smf = reinterpret_cast<T*>(sm_raw);
     int y, l, rs;
     if (!xcd_group(RB / RH, ne, ne * P, y, l, rs)) return;
     const WinDev& wd = wins[l];
@@ -702,11 +1045,11 @@ __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wi
     if (y >= wd.E[1]) return;
     const int Ex = wd.E[0], Ey = wd.E[1], Ez = wd.E[2];
     const int Exp = (Ex + 3) & ~3;
-    float* txT = smf;                // txT[k][x] = Tx[x][k], rows padded to Exp
-    float* sl = smf + Ex * Exp;      // [x][z][RH]
+    T* txT = smf;                // txT[k][x] = Tx[x][k], rows padded to Exp
+    T* sl = smf + Ex * Exp;      // [x][z][RH]
     for (int e = threadIdx.x; e < Ex * Exp; e += blockDim.x) {
         const int k = e / Exp, xx = e % Exp;
-        txT[e] = xx < Ex ? float(tmat[wd.t_off[0] + xx * Ex + k]) : 0.f;
+        txT[e] = xx < Ex ? T(tmat[wd.t_off[0] + xx * Ex + k]) : T(0);
     }
     for (int e = threadIdx.x; e < Ex * Ez * RH; e += blockDim.x) {
         const int xz = e / RH, r = e % RH;
@@ -717,16 +1060,16 @@ __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wi
     // h[x][z][y][r] = sum_k Tx[x][k] g1[k][y][z][r] (k ascending); x = x0 .. x0 + 3 per thread
     for (int e = threadIdx.x; e < (Exp / 4) * Ez * RH; e += blockDim.x) {
         const int r = e % RH, zz = (e / RH) % Ez, x0 = 4 * (e / (RH * Ez));
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+        T a0 = T(0), a1 = T(0), a2 = T(0), a3 = T(0);
         for (int k = 0; k < Ex; ++k) {
-            const float v = sl[(k * Ez + zz) * RH + r];
-            const f4 t = *reinterpret_cast<const f4*>(txT + k * Exp + x0);
+            const T v = sl[(k * Ez + zz) * RH + r];
+            const v4<T> t = *reinterpret_cast<const v4<T>*>(txT + k * Exp + x0);
             a0 += t[0] * v;
             a1 += t[1] * v;
             a2 += t[2] * v;
             a3 += t[3] * v;
         }
-        const float av[4] = {a0, a1, a2, a3};
+        const T av[4] = {a0, a1, a2, a3};
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             if (x0 + i < Ex) h[(wd.grid_off + (int64_t(x0 + i) * Ez + zz) * Ey + y) * RB + r0 + r] = av[i];
@@ -738,7 +1081,8 @@ __global__ __launch_bounds__(1024) void k_conv_x_b(const WinDev* __restrict__ wi
 // loaded 8 at a time, all in flight together; transposed through LDS for
 // coalesced stores
 constexpr int kWsChunk = 8;
-__global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ fs, const int32_t* __restrict__ pos,
+template <class T>
+__global__ __launch_bounds__(256) void k_window_sum_b(const T* __restrict__ fs, const int32_t* __restrict__ pos,
                                                       const WinDev* __restrict__ wins, int32_t P, int64_t N, int R,
                                                       const ColPtrs cols) {
     __shared__ double s[RB][65];
@@ -751,11 +1095,11 @@ __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ 
             int32_t pp[kWsChunk];
 #pragma unroll
             for (int j = 0; j < kWsChunk; ++j) pp[j] = l0 + j < P ? pos[int64_t(l0 + j) * N + gi] : 0;
-            f4 v[kWsChunk];
+            v4<T> v[kWsChunk];
 #pragma unroll
             for (int j = 0; j < kWsChunk; ++j)
-                v[j] = l0 + j < P ? *reinterpret_cast<const f4*>(fs + (int64_t(l0 + j) * N + pp[j]) * RB + 4 * q)
-                                  : f4{0.f, 0.f, 0.f, 0.f};
+                v[j] = l0 + j < P ? *reinterpret_cast<const v4<T>*>(fs + (int64_t(l0 + j) * N + pp[j]) * RB + 4 * q)
+                                  : v4<T>{T(0), T(0), T(0), T(0)};
 #pragma unroll
             for (int j = 0; j < kWsChunk; ++j) {
                 if (l0 + j < P) {
@@ -779,45 +1123,36 @@ __global__ __launch_bounds__(256) void k_window_sum_b(const float* __restrict__ 
 
 }  // namespace
 
-bool batched_supported(const Plan& pl) { return pl.precision == ANOVA_PREC_MIXED && pl.W == 8; }
+bool batched_supported(const Plan& pl) {
+    return (pl.precision == ANOVA_PREC_MIXED || pl.precision == ANOVA_PREC_FP64) && pl.W == 8;
+}
 
 namespace {
-__global__ void k_to_f32(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
-    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
-    if (i < n) b[i] = float(a[i]);
+template <class T>
+T* buf_as(DevBuf<double>& b) {
+    return reinterpret_cast<T*>(b.p);
 }
+// a batched buffer of n elements of elem bytes (storage in whole doubles)
+void alloc_elems(DevBuf<double>& b, size_t n, size_t elem) { b.alloc((n * elem + 7) / 8); }
 }  // namespace
 
-void enqueue_matvec_sketch(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy, hipStream_t st) {
-    if (pl.W != 8 || R < 2) {
-        enqueue_matvec(pl, x, R, ldx, y, ldy, st);
-        return;
-    }
-    if (pl.precision == ANOVA_PREC_FP64 && pl.wts32.n == 0) {
-        static_assert(rec_stride(8, 8) == rec_stride(8, 4), "FP64 and FP32 records hold the same elements");
-        pl.wts32.alloc(pl.wts64.n);
-        hipLaunchKernelGGL(k_to_f32, dim3(nblk(int64_t(pl.wts64.n))), dim3(kT), 0, st, pl.wts64.p,
-                           int64_t(pl.wts64.n), pl.wts32.p);
-    }
-    enqueue_matvec_batched(pl, x, R, ldx, y, ldy, st);
-}
-
 void release_batched_buffers(Plan& pl) {
-    for (DevBuf<float>* b : {&pl.xtb, &pl.fsb, &pl.slabb, &pl.tgtb, &pl.g1b, &pl.hb}) b->release();
+    for (DevBuf<double>* b : {&pl.xtb, &pl.fsb, &pl.slabb, &pl.tgtb, &pl.g1b, &pl.hb}) b->release();
     pl.b_items.release();
     pl.b_queue.release();
-    if (pl.precision == ANOVA_PREC_FP64) pl.wts32.release();
     pl.b_ready = false;
 }
 
 void ensure_batched_buffers(Plan& pl) {
     if (pl.b_ready) return;
-    pl.xtb.alloc(size_t(pl.N) * RB);
-    pl.fsb.alloc(size_t(pl.N) * pl.P * RB);
-    pl.slabb.alloc(size_t(pl.slab_total) * RB + RB);
-    pl.tgtb.alloc(size_t(pl.tgt_total) * RB);
-    pl.g1b.alloc(size_t(pl.grid_total) * RB);
-    pl.hb.alloc(size_t(pl.grid_total) * RB);
+    const bool f64 = pl.precision == ANOVA_PREC_FP64;
+    const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    alloc_elems(pl.xtb, size_t(pl.N) * RB, elem);
+    alloc_elems(pl.fsb, size_t(pl.N) * pl.P * RB, elem);
+    alloc_elems(pl.slabb, size_t(pl.slab_total) * RB + RB, elem);
+    alloc_elems(pl.tgtb, size_t(pl.tgt_total) * RB, elem);
+    alloc_elems(pl.g1b, size_t(pl.grid_total) * RB, elem);
+    alloc_elems(pl.hb, size_t(pl.grid_total) * RB, elem);
     // items of 1- and 2-feature windows as flat lists (lane kernels take (item, rhs) per lane)
     std::vector<int32_t> it2, it1;
     for (size_t i = 0; i < pl.segs_h.size(); ++i) {
@@ -833,82 +1168,115 @@ void ensure_batched_buffers(Plan& pl) {
     if (it2.empty()) it2.push_back(-1);
     pl.b_items.alloc(it2.size());
     ANV_HIP(hipMemcpy(pl.b_items.p, it2.data(), it2.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    // persistent grids of the matrix-core kernels: as many wavefronts as fit at once
+    // persistent grids of the matrix-core kernels: as many wavefronts as fit at
+    // once (the FP64 kernels take a work item per half of the right-hand sides)
     pl.b_queue.alloc(2);
     {
         int dev = 0, ncu = 0, bs = 0, bg = 0;
         ANV_HIP(hipGetDevice(&dev));
         ANV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-        ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma, 64, 0));
-        ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma, 64, 0));
-        pl.b_grid[0] = std::max(1, std::min(pl.nwave[3], std::max(1, bs) * ncu));
-        pl.b_grid[1] = std::max(1, std::min(pl.nwave[3], std::max(1, bg) * ncu));
+        if (f64) {
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma64, 64, 0));
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma64, 64, 0));
+        } else {
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma, 64, 0));
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma, 64, 0));
+        }
+        const int work = pl.nwave[3] * (f64 ? 2 : 1);
+        pl.b_grid[0] = std::max(1, std::min(work, std::max(1, bs) * ncu));
+        pl.b_grid[1] = std::max(1, std::min(work, std::max(1, bg) * ncu));
     }
     // right-hand sides per grid-step block: as many as the LDS budget allows
     const int64_t ex = pl.emax[0], ey = pl.emax[1], ez = pl.emax[2];
     pl.b_rsplit = 1;
     const int64_t exp = (ex + 3) & ~3, eyp = (ey + 3) & ~3, ezp = (ez + 3) & ~3;
-    while (pl.b_rsplit < RB && ((2 * ey * ez * (RB / pl.b_rsplit) + ey * eyp + ez * ezp) * 4 > 65536 ||
-                                (ex * ez * (RB / pl.b_rsplit) + ex * exp) * 4 > 65536))
+    const int64_t el = int64_t(elem);
+    while (pl.b_rsplit < RB && ((2 * ey * ez * (RB / pl.b_rsplit) + ey * eyp + ez * ezp) * el > 65536 ||
+                                (ex * ez * (RB / pl.b_rsplit) + ex * exp) * el > 65536))
         pl.b_rsplit *= 2;
     pl.b_ready = true;
 }
 
 namespace {
 
-// one pass of up to RB right-hand sides
-void batched_pass(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
+// one pass of up to RB right-hand sides; T = float (mixed precision: FP32
+// MFMA spread, split-bf16 MFMA gather) or double (FP64 throughout)
+template <class T>
+void batched_pass_t(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
+    constexpr bool f64 = sizeof(T) == sizeof(double);
     const int64_t N = pl.N;
     const bool prof = pl.profiling;
+    const T* wts = f64 ? reinterpret_cast<const T*>(pl.wts64.p) : reinterpret_cast<const T*>(pl.wts32.p);
+    T* xt = buf_as<T>(pl.xtb);
+    T* fsb = buf_as<T>(pl.fsb);
+    T* slab = buf_as<T>(pl.slabb);
+    T* tgt = buf_as<T>(pl.tgtb);
+    T* g1 = buf_as<T>(pl.g1b);
+    T* hb = buf_as<T>(pl.hb);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_transpose_in, dim3(nblk(N, 64)), dim3(256), 0, st, cols, rn, N, pl.xtb.p, pl.b_queue.p);
+    hipLaunchKernelGGL(k_transpose_in<T>, dim3(nblk(N, 64)), dim3(256), 0, st, cols, rn, N, xt, pl.b_queue.p);
     if (prof) pl.record_stage_event(st);
-    if (pl.nwave[3])
-        hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                           pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p, pl.alone.p,
-                           pl.wts32.p, pl.perm.p, pl.xtb.p, N, pl.slabb.p, pl.tgtb.p);
+    if (pl.nwave[3]) {
+        if constexpr (f64)
+            hipLaunchKernelGGL(k_spread_mfma64, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               2 * pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
+                               pl.alone.p, pl.wts64.p, pl.perm.p, xt, N, slab, tgt);
+        else
+            hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
+                               pl.alone.p, pl.wts32.p, pl.perm.p, xt, N, slab, tgt);
+    }
     if (pl.nb_items2)
-        hipLaunchKernelGGL((k_spread_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
-                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p, pl.xtb.p, N,
-                           pl.slabb.p);
+        hipLaunchKernelGGL((k_spread_lane_b<8, 8, T>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.zq.p, wts, pl.perm.p, xt, N, slab);
     if (pl.nb_items1)
-        hipLaunchKernelGGL((k_spread_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
-                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, pl.wts32.p, pl.perm.p,
-                           pl.xtb.p, N, pl.slabb.p);
+        hipLaunchKernelGGL((k_spread_lane_b<8, 1, T>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.zq.p, wts, pl.perm.p, xt, N, slab);
     if (prof) pl.record_stage_event(st);
     if (pl.nflist)
-        hipLaunchKernelGGL(k_fold_cols_b, dim3(unsigned(pl.nflist)), dim3(256), 0, st, pl.wins_d.p, pl.P, pl.nflist,
-                           pl.flist.p, pl.fold.p, pl.sbase.p, pl.slabb.p, pl.tgtb.p);
+        hipLaunchKernelGGL(k_fold_cols_b<T>, dim3(unsigned(pl.nflist)), dim3(256), 0, st, pl.wins_d.p, pl.P,
+                           pl.nflist, pl.flist.p, pl.fold.p, pl.sbase.p, slab, tgt);
     if (prof) pl.record_stage_event(st);
     const int RH = RB / pl.b_rsplit;
     auto pad4 = [](int64_t e) { return (e + 3) & ~int64_t(3); };
     const size_t lds_yz = size_t(2 * pl.emax[1] * pl.emax[2] * RH + pl.emax[1] * pad4(pl.emax[1]) +
-                                 pl.emax[2] * pad4(pl.emax[2])) * sizeof(float);
+                                 pl.emax[2] * pad4(pl.emax[2])) * sizeof(T);
     // one block per (slice, window, right-hand-side slice), groups padded to a multiple of 8
     auto xcd_blocks = [&](int64_t ne) { return unsigned((ne * pl.P + 7) / 8 * 8 * pl.b_rsplit); };
-    hipLaunchKernelGGL((k_fold_conv_yz_b<8>), dim3(xcd_blocks(pl.emax[0])), dim3(1024), lds_yz, st, pl.wins_d.p,
-                       pl.tmat.p, pl.crange.p, pl.tgtb.p, pl.g1b.p, RH, int(pl.emax[0]), int(pl.P));
-    const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pad4(pl.emax[0])) * sizeof(float);
-    hipLaunchKernelGGL(k_conv_x_b, dim3(xcd_blocks(pl.emax[1])), dim3(1024), lds_x, st, pl.wins_d.p, pl.tmat.p,
-                       pl.g1b.p, pl.hb.p, RH, int(pl.emax[1]), int(pl.P));
+    hipLaunchKernelGGL((k_fold_conv_yz_b<8, T>), dim3(xcd_blocks(pl.emax[0])), dim3(1024), lds_yz, st, pl.wins_d.p,
+                       pl.tmat.p, pl.crange.p, tgt, g1, RH, int(pl.emax[0]), int(pl.P));
+    const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pad4(pl.emax[0])) * sizeof(T);
+    hipLaunchKernelGGL(k_conv_x_b<T>, dim3(xcd_blocks(pl.emax[1])), dim3(1024), lds_x, st, pl.wins_d.p, pl.tmat.p,
+                       g1, hb, RH, int(pl.emax[1]), int(pl.P));
     if (prof) pl.record_stage_event(st);
-    if (pl.nwave[3])
-        hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                           pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
-                           pl.wts32.p, pl.hb.p, N, pl.fsb.p);
+    if (pl.nwave[3]) {
+        if constexpr (f64)
+            hipLaunchKernelGGL(k_gather_mfma64, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               2 * pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p,
+                               pl.wins_d.p, pl.wts64.p, hb, N, fsb);
+        else
+            hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
+                               pl.wts32.p, hb, N, fsb);
+    }
     if (pl.nb_items2)
-        hipLaunchKernelGGL((k_gather_lane_b<8, 8>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
-                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p, pl.hb.p, N,
-                           pl.fsb.p);
+        hipLaunchKernelGGL((k_gather_lane_b<8, 8, T>), dim3(nblk(int64_t(pl.nb_items2) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p, pl.nb_items2, pl.segs.p, pl.wins_d.p, pl.zq.p, wts, hb, N, fsb);
     if (pl.nb_items1)
-        hipLaunchKernelGGL((k_gather_lane_b<8, 1>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
-                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.wins_d.p, pl.zq.p, pl.wts32.p,
-                           pl.hb.p, N, pl.fsb.p);
+        hipLaunchKernelGGL((k_gather_lane_b<8, 1, T>), dim3(nblk(int64_t(pl.nb_items1) * RB, 64)), dim3(64), 0, st,
+                           pl.b_items.p + pl.nb_items2, pl.nb_items1, pl.segs.p, pl.wins_d.p, pl.zq.p, wts, hb, N, fsb);
     if (prof) pl.record_stage_event(st);
-    hipLaunchKernelGGL(k_window_sum_b, dim3(nblk(N, 64)), dim3(256), 0, st, pl.fsb.p, pl.pos.p, pl.wins_d.p, pl.P, N,
+    hipLaunchKernelGGL(k_window_sum_b<T>, dim3(nblk(N, 64)), dim3(256), 0, st, fsb, pl.pos.p, pl.wins_d.p, pl.P, N,
                        rn, cols);
     if (prof) pl.record_stage_event(st);
     ANV_HIP(hipGetLastError());
+}
+
+void batched_pass(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
+    if (pl.precision == ANOVA_PREC_FP64)
+        batched_pass_t<double>(pl, cols, rn, st);
+    else
+        batched_pass_t<float>(pl, cols, rn, st);
 }
 
 }  // namespace
@@ -939,6 +1307,11 @@ void enqueue_matvec_batched_cols(Plan& pl, const double* const* x, double* const
     }
 }
 
+// Shared launches batch the vectors of mixed-precision plans only: FP64 plans
+// keep the one-vector kernels there, so that a served or grid solve on an FP64
+// plan rounds exactly as the direct solve does.
+static bool grouped_batching(const Plan& pl) { return pl.precision == ANOVA_PREC_MIXED && pl.W == 8; }
+
 void enqueue_matvec_grouped(Plan* const* plans, const double* const* x, double* const* y, int n, hipStream_t st) {
     // same-plan vectors of batched plans: one batched pass per 16 of them;
     // the rest: shared one-vector launches
@@ -948,7 +1321,7 @@ void enqueue_matvec_grouped(Plan* const* plans, const double* const* x, double* 
     std::vector<double*> ry;
     for (int i = 0; i < n; ++i) {
         if (taken[i]) continue;
-        if (!batched_supported(*plans[i])) {
+        if (!grouped_batching(*plans[i])) {
             rp.push_back(plans[i]);
             rx.push_back(x[i]);
             ry.push_back(y[i]);

@@ -70,13 +70,14 @@ struct Plan {
     DevBuf<double> slab64;
     DevBuf<float> slab32;
 
-    // batched path (16 right-hand sides per pass, mixed precision), allocated on
-    // first use: inputs [N][16] (point order), slabs, fold targets, grids and
-    // gathered values, each with the 16 right-hand sides innermost
+    // batched path (16 right-hand sides per pass; FP32 elements for mixed
+    // precision, FP64 for FP64 plans), allocated on first use: inputs [N][16]
+    // (point order), slabs, fold targets, grids and gathered values, each with
+    // the 16 right-hand sides innermost (storage in doubles, either element type)
     int32_t batch_min_rhs = 2;
     bool b_ready = false;
     int32_t b_rsplit = 2;       // grid-step blocks per slice (right-hand sides split for LDS)
-    DevBuf<float> xtb, fsb, slabb, tgtb, g1b, hb;
+    DevBuf<double> xtb, fsb, slabb, tgtb, g1b, hb;
     DevBuf<int32_t> b_items;    // work items of 2-feature then 1-feature windows
     DevBuf<int32_t> b_queue;    // work-queue counters of the matrix-core spread and gather
     int32_t b_grid[2] = {1, 1}; // their persistent grid sizes
@@ -161,11 +162,6 @@ void enqueue_matvec_noalloc(Plan& pl, const double* x, int R, int64_t ldx, doubl
 bool batched_supported(const Plan& pl);
 void enqueue_matvec_batched(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
                             hipStream_t stream);
-// A matvec of R right-hand sides at FP32 accuracy, for random sketches that only
-// need an approximation of K: the batched kernels (an FP64 plan converts its
-// weights to FP32 on first use) when the cutoff allows, else enqueue_matvec.
-void enqueue_matvec_sketch(Plan& pl, const double* x, int R, int64_t ldx, double* y, int64_t ldy,
-                           hipStream_t stream);
 // frees the batched path's buffers (and the FP32 weights of an FP64 plan)
 void release_batched_buffers(Plan& pl);
 
