@@ -200,7 +200,10 @@ typedef struct {
     int32_t max_ip;      /* IPM iteration cap (Table 1: 50)                      */
     int32_t max_kry;     /* Krylov iterations per Newton solve (Table 1: 100)    */
     int32_t precond;     /* ANOVA_PRECOND_*                                      */
-    double  tol;         /* on mu, |y^T a|/|y^T a0| and the relative duality gap */
+    double  tol;         /* on mu, |y^T a|/|y^T a0| and the relative duality gap;
+                            the gap, measured with the plan's fast-summation
+                            operator, must fall to tol / 2 (the other half
+                            covers its difference from the exact kernel's gap) */
     double  tol_inf;     /* on ||xi_lambda||/||xi_lambda^0|| (Table 1: 1e-1)    */
     double  tol_kry;     /* upper bound of the Krylov relative tolerance (1e-3)  */
     double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */

@@ -60,6 +60,11 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
+// largest per-axis error of a request's trigonometric kernel approximation
+// (absolute, the Gaussian's maximum being 1) that the server accepts: the
+// matvec accuracy bar
+constexpr double kMaxKernelErr = 1e-4;
+
 double ms_between(clk::time_point a, clk::time_point b) {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
@@ -213,7 +218,8 @@ struct Server::Impl {
     std::condition_variable cv;
     std::list<std::unique_ptr<Request>> queue;
     std::map<int64_t, Result> results;
-    std::list<std::thread> workers;
+    std::map<int64_t, std::thread> workers;  // by ticket
+    std::vector<int64_t> finished;           // tickets whose worker has returned (joined by the scheduler)
     int active = 0;
     int64_t used = 0;
     int64_t next_ticket = 1;
@@ -224,8 +230,10 @@ struct Server::Impl {
         (void)hipSetDevice(device);
         std::unique_lock<std::mutex> lk(m);
         for (;;) {
-            cv.wait(lk, [&] { return stop || (!queue.empty() && active < opts.max_active); });
+            cv.wait(lk, [&] { return stop || !finished.empty() || (!queue.empty() && active < opts.max_active); });
+            reap_finished(lk);
             if (stop && queue.empty()) return;
+            if (queue.empty()) continue;  // woken only to join finished workers
             // first fit in arrival order
             bool admitted = false;
             for (auto it = queue.begin(); it != queue.end() && active < opts.max_active; ++it) {
@@ -236,12 +244,29 @@ struct Server::Impl {
                 used += r->footprint;
                 ++active;
                 Request* raw = r.release();
-                workers.emplace_back([this, raw] { run_request(std::unique_ptr<Request>(raw)); });
+                const int64_t tk = raw->ticket;
+                workers.emplace(tk, std::thread([this, raw] { run_request(std::unique_ptr<Request>(raw)); }));
                 admitted = true;
                 break;
             }
             if (!admitted) cv.wait(lk);  // nothing fits: wait for a solve to finish
         }
+    }
+
+    // joins the threads of requests that have finished (called with m held;
+    // the joins wait at most for the threads' last few instructions)
+    void reap_finished(std::unique_lock<std::mutex>& lk) {
+        std::vector<std::thread> done;
+        for (int64_t tk : finished) {
+            auto it = workers.find(tk);
+            if (it == workers.end()) continue;
+            done.push_back(std::move(it->second));
+            workers.erase(it);
+        }
+        finished.clear();
+        lk.unlock();
+        for (auto& t : done) t.join();
+        lk.lock();
     }
 
     void run_request(std::unique_ptr<Request> r) {
@@ -255,20 +280,30 @@ struct Server::Impl {
         hipStream_t stream = nullptr;
         hipEvent_t ev_ready = nullptr, ev_done = nullptr;
         bool joined = false;
+        // device state of the request; released only after its stream has
+        // drained (also when the solve ends in an error)
+        DevBuf<double> Xd, yd, ad;
+        std::unique_ptr<Plan> pl;
         try {
             ANV_HIP(hipSetDevice(device));
             ANV_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
             ANV_HIP(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
             ANV_HIP(hipEventCreateWithFlags(&ev_done, hipEventDisableTiming));
-            DevBuf<double> Xd, yd, ad;
             Xd.alloc(r->X.size());
             yd.alloc(size_t(r->N));
             ad.alloc(size_t(r->N));
             ANV_HIP(hipMemcpyAsync(Xd.p, r->X.data(), r->X.size() * sizeof(double), hipMemcpyHostToDevice, stream));
             ANV_HIP(hipMemcpyAsync(yd.p, r->labels.data(), r->labels.size() * sizeof(double),
                                    hipMemcpyHostToDevice, stream));
-            std::unique_ptr<Plan> pl(create_plan(Xd.p, r->N, r->d, r->d, r->windows.data(), r->P, r->sigma.data(),
-                                                 nullptr, &r->nfft, stream));
+            pl.reset(create_plan(Xd.p, r->N, r->d, r->d, r->windows.data(), r->P, r->sigma.data(), nullptr, &r->nfft,
+                                 stream));
+            // the plan's kernel approximation must meet the matvec accuracy the
+            // solve relies on (data outside the scale the bandwidth resolves
+            // would otherwise be solved with a far worse kernel)
+            if (!(pl->max_kerr <= kMaxKernelErr))
+                throw Error(ANOVA_INVALID_ARG, "kernel approximation error " + std::to_string(pl->max_kerr) +
+                                                   " exceeds " + std::to_string(kMaxKernelErr) +
+                                                   ": scale the features or raise the bandwidth");
             Plan* plp = pl.get();
             MatvecHook hook = [this, plp, ev_ready, ev_done, &joined](const double* x, double* y, hipStream_t s) {
                 comb->matvec(*plp, x, y, s, ev_ready, ev_done, joined);
@@ -286,10 +321,12 @@ struct Server::Impl {
             err = e.what();
         }
         if (comb) comb->solver_leave(joined);
-        if (stream) {
-            (void)hipStreamSynchronize(stream);
-            (void)hipStreamDestroy(stream);
-        }
+        if (stream) (void)hipStreamSynchronize(stream);
+        pl.reset();
+        Xd.release();
+        yd.release();
+        ad.release();
+        if (stream) (void)hipStreamDestroy(stream);
         if (ev_ready) (void)hipEventDestroy(ev_ready);
         if (ev_done) (void)hipEventDestroy(ev_done);
         const auto t_end = clk::now();
@@ -310,6 +347,7 @@ struct Server::Impl {
             results[r->ticket] = std::move(out);
             used -= r->footprint;
             --active;
+            finished.push_back(r->ticket);
         }
         cv.notify_all();
     }
@@ -353,7 +391,7 @@ Server::~Server() {
     }
     impl_->cv.notify_all();
     impl_->scheduler.join();
-    for (auto& t : impl_->workers) t.join();
+    for (auto& t : impl_->workers) t.second.join();
     impl_->comb.reset();
 }
 
@@ -401,9 +439,16 @@ int Server::wait(int64_t ticket, double* alpha, anova_result* res) {
     std::unique_lock<std::mutex> lk(impl_->m);
     auto it = impl_->results.find(ticket);
     ANV_CHECK(it != impl_->results.end(), "unknown or already collected ticket");
-    impl_->cv.wait(lk, [&] { return impl_->results[ticket].done; });
-    Result r = std::move(impl_->results[ticket]);
-    impl_->results.erase(ticket);
+    // a second waiter on the same ticket finds the entry gone once the first
+    // has collected it, and reports that instead of waiting for ever
+    impl_->cv.wait(lk, [&] {
+        auto f = impl_->results.find(ticket);
+        return f == impl_->results.end() || f->second.done;
+    });
+    it = impl_->results.find(ticket);
+    ANV_CHECK(it != impl_->results.end(), "ticket collected by another waiter");
+    Result r = std::move(it->second);
+    impl_->results.erase(it);
     lk.unlock();
     if (alpha) std::memcpy(alpha, r.alpha.data(), r.alpha.size() * sizeof(double));
     if (res) *res = r.res;

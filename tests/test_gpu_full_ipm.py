@@ -67,3 +67,25 @@ def test_full_size_solve_satisfies_the_optimality_conditions(dev, problem, krylo
     assert np.all(np.abs(m[free] - 1.0) <= 1e-3)
     assert np.all(m[low] >= 1.0 - 1e-3)
     assert np.all(m[up] <= 1.0 + 1e-3)
+
+
+@pytest.mark.parametrize("krylov", ["minres", "gmres"])
+def test_full_ipm_shape_at_40000_meets_the_exact_gap(dev, krylov):
+    # the full-IPM workload's shape (d = 20, 7 windows, 10 % label noise,
+    # sigma = 0.8, C = 10, Nystrom rank 200) at N = 40 000, where one oracle
+    # direct sum K (Y alpha) over all pairs (1.1e10 pair-windows) evaluates the
+    # GPU solution in the exact QP of Algorithm 1 (eq. "kernelsvm"): relative
+    # duality gap G_exact <= 1e-6 and y^T alpha ~ 0
+    import paper_2312_00538_amd as lib
+    p = workloads.full_ipm(seed=0, N=40_000)
+    pl = lib.Plan(to_dev(p.X, dev), p.windows, p.sigma)
+    kr = lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES
+    alpha, lam, st = pl.solve(to_dev(p.labels, dev), p.C, precond=lib.PRECOND_NYSTROM, rank=200, krylov=kr)
+    a = alpha.cpu().numpy()
+    assert st["status"] == 0 and st["rel_gap"] <= 1e-6
+    kya = oracle.anova_matvec(p.X, p.windows, p.sigma, p.labels * a)
+    D, Pr, G = oracle.objectives_from_kya(kya, p.labels, a, lam, p.C)
+    print(f"{krylov}: ip {st['ip_iters']} krylov {st['kry_iters_total']}, GPU gap {st['rel_gap']:.2e}, "
+          f"G_exact {G:.2e}, dual {D:.12g}, primal {Pr:.12g}, |y^T a| {abs(p.labels @ a):.1e}")
+    assert G <= 1e-6
+    assert abs(p.labels @ a) <= 1e-6 * p.C * p.X.shape[0] / 4

@@ -5,6 +5,7 @@ launches, and bad requests are reported to their caller."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads
 from gpu_util import device, to_dev
 
@@ -104,3 +105,27 @@ def test_bad_request_is_reported_at_wait(dev):
     with pytest.raises(lib.AnovaError):
         srv.submit(p.X, p.labels, p.windows, p.sigma, -1.0)
     srv.close()
+
+
+def test_served_results_meet_the_exact_qp_bar(dev):
+    # every request of the mix, served concurrently with shared launches, is
+    # evaluated in the exact QP of Algorithm 1 (eq. "kernelsvm") with a dense K:
+    # relative duality gap G_exact <= 1e-6, and the dual objective within 1e-6
+    # (relative) of the dense-KKT oracle's optimum
+    import paper_2312_00538_amd as lib
+    probs = [_problem(*m) for m in MIX]
+    srv = lib.Server(max_active=4, share_launches=True)
+    tickets = [srv.submit(p.X, p.labels, p.windows, p.sigma, p.C) for p in probs]
+    served = [srv.wait(t) for t in tickets]
+    srv.close()
+    for p, (a, res) in zip(probs, served):
+        assert res["status"] == 0
+        K = oracle.anova_dense(p.X, p.windows, p.sigma)
+        ref = oracle.ipm_dense(K, p.labels, p.C)
+        assert ref["converged"]
+        D, Pr, G = oracle.objectives_from_kya(K @ (p.labels * a), p.labels, a, res["lambda"], p.C)
+        rel_d = abs(D - ref["D"]) / abs(ref["D"])
+        print(f"N={p.X.shape[0]} d={p.X.shape[1]} C={p.C}: G_exact {G:.2e}, dual {D:.10g} vs oracle "
+              f"{ref['D']:.10g} (rel {rel_d:.2e}), |y^T a| {abs(p.labels @ a):.1e}")
+        assert G <= 1e-6
+        assert rel_d <= 1e-6
