@@ -151,6 +151,42 @@ int anova_matvec(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_,
 int anova_matvec_noalloc(anova_plan_t plan, const double* x, int32_t R, int64_t ldx_,
                          double* y, int64_t ldy, void* stream);
 
+/* The Kaiser-Bessel window of the plans' NFFT (Section 3 names the window
+ * parameter m; the window is the Kaiser-Bessel pair of the NFFT literature it
+ * cites), for checking it outside a plan. Host only: no device work.
+ *   opts     as for anova_plan_create (NULL: defaults); uses n_bw, oversample
+ *            (FFT length n = oversample * n_bw) and cutoff_m.
+ *   u, nu    host, nu offsets in grid cells, |u| <= cutoff_m.
+ *   phi      host, nu outputs: phi(u) / phi(0) with
+ *            phi(u) = sinh(b sqrt(m^2 - u^2)) / (pi sqrt(m^2 - u^2)),
+ *            b = pi (2 - n_bw / n).
+ *   phi_hat  host, n/2 + 1 outputs or NULL: for k = 0 .. n/2 the transform
+ *            (1/n) I0(m sqrt(b^2 - (2 pi k / n)^2)) / phi(0) (J0 of the
+ *            imaginary argument past b), i.e. the integral of
+ *            phi(u) e^{-2 pi i k u / n} du divided by n phi(0).
+ * Errors: ANOVA_INVALID_ARG (bad options, NULL pointers, |u| > m). */
+int anova_kaiser_bessel(const anova_opts* opts, const double* u, int32_t nu, double* phi, double* phi_hat);
+
+/* The one-axis coefficients a plan builds for a feature with data range
+ * [lo, hi] and kernel width sigma (Section 3: the kernel replaced by a
+ * trigonometric polynomial, evaluated by an adjoint and a forward NFFT), for
+ * checking them outside a plan. Host only: no device work.
+ *   opts   as for anova_plan_create (NULL: defaults).
+ *   bk     host, n_bw outputs or NULL: b_k for k = -n_bw/2 .. n_bw/2 - 1 (index
+ *          k + n_bw/2), the trigonometric interpolation coefficients of the
+ *          1-periodic regularised Gaussian exp(-t^2 / sigma_a^2) in torus units.
+ *   circ   host, n = oversample * n_bw outputs or NULL: first column of the real
+ *          symmetric circulant that the grid step applies along this axis
+ *          (forward FFT, times B_k = b_k / (n phi_hat(k))^2, inverse FFT; the
+ *          unpaired frequency -n_bw/2 split evenly between +-n_bw/2).
+ *   axis   host, 4 outputs or NULL: center and scale of the torus map
+ *          u = (x - center) * scale, sigma_a = sigma * scale, and the largest
+ *          |trigonometric interpolant - Gaussian| on the box |t| <= 1/2 - eps_b.
+ *   reg_p  host or NULL: smoothness p of the regularisation chosen.
+ * Errors: ANOVA_INVALID_ARG (bad options, lo > hi, sigma <= 0, NaN). */
+int anova_axis_coefficients(double lo, double hi, double sigma, const anova_opts* opts, double* bk, double* circ,
+                            double* axis, int32_t* reg_p);
+
 /* Release a plan and all device memory it owns (synchronises the device).
  * NULL is accepted. */
 int anova_plan_destroy(anova_plan_t plan);

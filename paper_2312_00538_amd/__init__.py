@@ -29,7 +29,8 @@ EXPORTED = [
     "anova_server_opts_default", "anova_server_create", "anova_server_submit", "anova_server_wait",
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
     "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
-    "anova_rff_factor", "anova_mi_windows", "anova_matvec_noalloc",
+    "anova_rff_factor", "anova_mi_windows", "anova_matvec_noalloc", "anova_kaiser_bessel",
+    "anova_axis_coefficients",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -126,6 +127,8 @@ def load_library(path: str = LIB_PATH):
                               ctypes.c_int),
         "anova_matvec": ([P, P, i32, i64, P, i64, P], ctypes.c_int),
         "anova_matvec_noalloc": ([P, P, i32, i64, P, i64, P], ctypes.c_int),
+        "anova_kaiser_bessel": ([ctypes.POINTER(Opts), P, i32, P, P], ctypes.c_int),
+        "anova_axis_coefficients": ([dbl, dbl, dbl, ctypes.POINTER(Opts), P, P, P, ctypes.POINTER(i32)], ctypes.c_int),
         "anova_plan_destroy": ([P], ctypes.c_int),
         "anova_plan_info": ([P, ctypes.POINTER(PlanInfo)], ctypes.c_int),
         "anova_ipm_opts_default": ([ctypes.POINTER(IpmOpts)], ctypes.c_int),
@@ -382,6 +385,35 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def kaiser_bessel(u, opts: Opts | None = None):
+    """(phi(u) / phi(0), phi_hat(k) for k = 0..n/2) of the plans' Kaiser-Bessel
+    window (anova_kaiser_bessel); host only."""
+    lib = load_library()
+    o = opts if opts is not None else default_opts()
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))
+    phi = np.zeros(u.shape[0])
+    ph = np.zeros(o.oversample * o.n_bw // 2 + 1)
+    _check(lib.anova_kaiser_bessel(ctypes.byref(o), u.ctypes.data_as(ctypes.c_void_p), int(u.shape[0]),
+                                   phi.ctypes.data_as(ctypes.c_void_p), ph.ctypes.data_as(ctypes.c_void_p)))
+    return phi, ph
+
+
+def axis_coefficients(lo: float, hi: float, sigma: float, opts: Opts | None = None):
+    """Per-axis coefficients a plan builds (anova_axis_coefficients); host only.
+    Returns dict(bk (k = -n_bw/2 .. n_bw/2 - 1), circ, center, scale, sigma_a,
+    kerr, reg_p)."""
+    lib = load_library()
+    o = opts if opts is not None else default_opts()
+    bk = np.zeros(o.n_bw)
+    circ = np.zeros(o.oversample * o.n_bw)
+    ax = np.zeros(4)
+    rp = ctypes.c_int32(0)
+    _check(lib.anova_axis_coefficients(float(lo), float(hi), float(sigma), ctypes.byref(o),
+                                       bk.ctypes.data_as(ctypes.c_void_p), circ.ctypes.data_as(ctypes.c_void_p),
+                                       ax.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rp)))
+    return dict(bk=bk, circ=circ, center=ax[0], scale=ax[1], sigma_a=ax[2], kerr=ax[3], reg_p=rp.value)
 
 
 def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: IpmOpts | None = None) -> int:

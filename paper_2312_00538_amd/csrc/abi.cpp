@@ -1,5 +1,6 @@
 // extern "C" entry points: argument checks, exception-to-status translation
 // and the thread-local error message.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -95,6 +96,57 @@ int anova_matvec_noalloc(anova_plan_t plan, const double* x, int32_t R, int64_t 
         ANV_CHECK(R >= 1, "R < 1");
         ANV_CHECK(ldx_ >= plan->p->N && ldy >= plan->p->N, "leading dimension < N");
         anv::enqueue_matvec_noalloc(*plan->p, x, R, ldx_, y, ldy, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
+int anova_kaiser_bessel(const anova_opts* opts, const double* u, int32_t nu, double* phi, double* phi_hat) {
+    return guarded([&] {
+        anova_opts o;
+        anova_opts_default(&o);
+        if (opts) o = *opts;
+        ANV_CHECK(o.version == ANOVA_OPTS_VERSION, "anova_opts.version mismatch");
+        ANV_CHECK(o.n_bw >= 4 && o.n_bw % 2 == 0 && o.oversample >= 2 && o.cutoff_m >= 1, "bad options");
+        ANV_CHECK(nu >= 0 && (nu == 0 || (u && phi)), "NULL argument");
+        const int n = o.oversample * o.n_bw, m = o.cutoff_m;
+        const double b = M_PI * (2.0 - double(o.n_bw) / n);
+        for (int32_t i = 0; i < nu; ++i) {
+            ANV_CHECK(std::fabs(u[i]) <= double(m), "|u| > m");
+            phi[i] = anv::kb_window(u[i], m, b);
+        }
+        if (phi_hat)
+            for (int k = 0; k <= n / 2; ++k) phi_hat[k] = anv::kb_hat(k, n, m, b);
+        return ANOVA_OK;
+    });
+}
+
+int anova_axis_coefficients(double lo, double hi, double sigma, const anova_opts* opts, double* bk, double* circ,
+                            double* axis, int32_t* reg_p) {
+    return guarded([&] {
+        anova_opts o;
+        anova_opts_default(&o);
+        if (opts) o = *opts;
+        ANV_CHECK(o.version == ANOVA_OPTS_VERSION, "anova_opts.version mismatch");
+        ANV_CHECK(o.n_bw >= 4 && o.n_bw % 2 == 0 && o.oversample >= 2 && o.cutoff_m >= 1, "bad options");
+        ANV_CHECK(o.eps_b > 0.0 && o.eps_b < 0.5, "eps_b must be in (0, 1/2)");
+        ANV_CHECK(std::isfinite(lo) && std::isfinite(hi) && lo <= hi, "need finite lo <= hi");
+        ANV_CHECK(std::isfinite(sigma) && sigma > 0.0, "sigma must be > 0");
+        anv::NfftParams prm;
+        prm.n_bw = o.n_bw;
+        prm.n_os = o.oversample * o.n_bw;
+        prm.m = o.cutoff_m;
+        prm.eps_b = o.eps_b;
+        prm.reg_p = o.reg_p;
+        const anv::AxisCoef ax = anv::build_axis(lo, hi, sigma, prm);
+        if (bk) std::copy(ax.bk.begin(), ax.bk.end(), bk);
+        if (circ) std::copy(ax.circ.begin(), ax.circ.end(), circ);
+        if (axis) {
+            axis[0] = ax.center;
+            axis[1] = ax.scale;
+            axis[2] = ax.sigma_a;
+            axis[3] = ax.kerr;
+        }
+        if (reg_p) *reg_p = ax.reg_p;
         return ANOVA_OK;
     });
 }

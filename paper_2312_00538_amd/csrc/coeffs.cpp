@@ -164,6 +164,7 @@ AxisCoef build_axis(double lo, double hi, double sigma, const NfftParams& prm) {
         double ph = double(n) * kb_hat(k, n, m, b);
         Bk[k] = bkv / (ph * ph);
     }
+    ax.bk = bk;
     ax.circ.assign(n, 0.0);
     for (int dlt = 0; dlt < n; ++dlt) {
         double acc = Bk[0];

@@ -79,6 +79,7 @@ struct AxisCoef {
     int reg_p = 0;                // smoothness of the regularisation used
     double kerr = 0;              // max |trig interpolant - Gaussian| on the box
     std::vector<double> circ;     // circ[delta], delta = 0..n_os-1
+    std::vector<double> bk;       // b_k, k = -n_bw/2 .. n_bw/2 - 1 (index k + n_bw/2)
 };
 
 struct NfftParams {
