@@ -49,6 +49,11 @@ TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f) for f in
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2312_00538_amd", "csrc", "matvec_batched.hip")
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,8 +75,13 @@ def parse():
     ap.add_argument("--ipm-full-N", type=int, default=500_000)
     ap.add_argument("--ipm-full-gmres-solves", type=int, default=10,
                     help="full-ipm solves with GMRES and the block-triangular preconditioner")
-    ap.add_argument("--serving-requests", type=int, default=12,
+    ap.add_argument("--serving-requests", type=int, default=100,
                     help="requests of the Poisson serving stream (0 = skip)")
+    ap.add_argument("--serving-reference-requests", type=int, default=100,
+                    help="requests of the same stream served one at a time (0 = skip)")
+    ap.add_argument("--save-alpha", default=None,
+                    help="write the first full-ipm solve's alpha and lambda to this .npz file")
+    ap.add_argument("--grid-max-ip", type=int, default=200)
     ap.add_argument("--serving-rate", type=float, default=2.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuned form of the matvec workload")
@@ -138,9 +148,10 @@ def traffic_record():
     return out
 
 
-def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
+def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0, oversample=2, save_alpha=None):
     """Wall-clock per svm_ipm_solve call (API call to return, preconditioner
-    build included) over seeds 0..n-1; plan creation timed separately."""
+    build included) over seeds 0..n-1; plan creation timed separately. With
+    save_alpha, the first solve's alpha and lambda are written there (.npz)."""
     t_solve, t_plan, stats = [], [], []
     for seed in range(n):
         p = make(seed)
@@ -148,7 +159,7 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
         y = torch.as_tensor(p.labels, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = lib.Plan(X, p.windows, p.sigma)
+        plan = lib.Plan(X, p.windows, p.sigma, oversample=oversample)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         alpha, lam, st = plan.solve(y, p.C, precond=precond, rank=rank, krylov=krylov, allow_not_converged=True)
@@ -157,6 +168,8 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
         t_plan.append(1e3 * (t1 - t0))
         t_solve.append(1e3 * (t2 - t1))
         stats.append(st)
+        if save_alpha and seed == 0:
+            np.savez(save_alpha, alpha=alpha.cpu().numpy(), lam=lam, seed=seed, N=p.X.shape[0])
         del plan
     ts = np.array(t_solve)
     return {"workload": label, "solves": n, "p50_ms": float(np.percentile(ts, 50)),
@@ -168,7 +181,7 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0):
             "kry_iters_p50": float(np.percentile([s["kry_iters_total"] for s in stats], 50)),
             "rel_gap_max": float(max(s["rel_gap"] for s in stats)),
             "rank": rank, "precond": {1: "pivoted-cholesky", 2: "nystrom", 3: "barrier-diagonal"}[precond],
-            "krylov": ("minres", "gmres")[krylov], "precision": "fp64"}
+            "krylov": ("minres", "gmres")[krylov], "precision": "fp64", "oversampling": oversample}
 
 
 def serving(lib, workloads, n, rate, max_active, share):
@@ -197,6 +210,8 @@ def serving(lib, workloads, n, rate, max_active, share):
         while tickets[i] is None:
             time.sleep(0.001)
         res.append(srv.wait(tickets[i])[1])
+        if (i + 1) % 20 == 0:
+            progress(f"serving (max_active {max_active}): {i + 1} of {n} requests done")
     t_end = time.perf_counter()
     th.join()
     launches, matvecs = srv.counters()
@@ -208,17 +223,19 @@ def serving(lib, workloads, n, rate, max_active, share):
             "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile([r["queue_ms"] for r in res], 50)),
             "solves_per_s": n / span, "converged": int(sum(r["status"] == 0 for r in res)),
             "matvecs_in_shared_launches": matvecs, "shared_launch_count": launches,
+            "matvecs_per_shared_launch": matvecs / launches if launches else None,
+            "p90_ms": float(np.percentile(lat, 90)), "max_ms": float(lat.max()),
             "N_max": int(max(r["N"] for r in stream)), "N_median": int(np.median([r["N"] for r in stream]))}
 
 
-def grid(lib, torch, workloads, dev, folds, max_active, ref_solves):
+def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip):
     """Hyperparameter grid over cross-validation folds: 8 sigma x 8 C per fold,
     mixed-precision plans, solves of a plan sharing its pivoted-Cholesky
     factor, matvecs of concurrent solves in shared launches."""
     g = workloads.cv_grid(seed=0)
     p = g["problem"]
     folds = min(folds, len(g["folds"]))
-    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0)
+    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0, max_ip=max_ip)
     t0 = time.perf_counter()
     probs, data = [], []
     for tr, _ in g["folds"][:folds]:
@@ -238,9 +255,10 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves):
     out = {"workload": f"cross-validation grid: N=50000, d=15 (5 windows of 3), {folds} of 5 folds (class-balanced "
                        "training parts of 39874..39982 points), sigma 8 log-spaced in 0.25..4, C 8 log-spaced in "
                        "0.1..1000; mixed-precision plans, pivoted-Cholesky rank 200 shared per plan, automatic "
-                       "initial barrier parameter, at most 100 iterations",
+                       f"initial barrier parameter, at most {max_ip} iterations",
            "solves": len(st), "plans": len(probs), "plan_s": t1 - t0, "wall_s": t2 - t1,
            "solves_per_s": len(st) / (t2 - t1), "status_counts": status,
+           "converged": status.get("0", 0), "converged_per_s": status.get("0", 0) / (t2 - t1),
            "ip_iters_mean": float(np.mean([x["ip_iters"] for x in st])),
            "shared_launches": launches, "matvecs": matvecs, "max_active": max_active}
     if ref_solves > 0:
@@ -379,6 +397,7 @@ def main():
 
     head = matvec_form(lib, torch, p, X, xb, R, prec, a.steps, a.warmup, y_fp64_1)
     y_head = head.pop("y")
+    progress(f"headline matvec: {head['value']:.4g} point-windows/s, {head['ms_per_step']:.3f} ms")
     out = {
         "metric": "ANOVA-NFFT matvec points*windows/s at rel.err<=1e-4; IPM solve p50/p99 ms",
         "value": head["value"],
@@ -411,6 +430,7 @@ def main():
         o = matvec_form(lib, torch, p, X, xb, R, other, a.steps, a.warmup, y_fp64_1)
         o.pop("y")
         out["mixed_16rhs" if other == lib.PREC_MIXED else "fp64_16rhs"] = o
+        progress(f"other-precision matvec: {o['value']:.4g} point-windows/s")
     del xb
 
     # the one-vector forms on the same GPU at the same accuracy bar
@@ -428,6 +448,7 @@ def main():
             refs[name] = {"value": N * P / t1, "ms_per_step": 1e3 * t1, "stage_ms": st1}
             del pl
         out["reference"] = refs
+        progress("one-vector forms done")
 
     # the same workload with the options the autotuner picks for a 1e-4 target
     if not a.no_autotune:
@@ -454,6 +475,7 @@ def main():
             "note": "same workload and right-hand sides; bandwidth, cutoff, precision and work-item size chosen by "
                     "anova_autotune for relative error <= 1e-4 (the headline keeps bandwidth 32 and m = 4)"}
         del pl, plr, xt, yt, yr
+        progress("autotuned form done")
 
     ipm = []
     if a.ipm_small_solves > 0:
@@ -470,23 +492,31 @@ def main():
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
                                a.ipm_full_solves, lib.PRECOND_NYSTROM, 200,
                                f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
-                               "Nystrom rank 200"))
+                               "Nystrom rank 200; NFFT oversampling 3 (matvec error ~7e-8, so that the duality gap "
+                               "in the exact kernel meets 1e-6)", oversample=3, save_alpha=a.save_alpha))
     if a.ipm_full_gmres_solves > 0:
         ipm.append(ipm_latency(lib, torch, dev, lambda s: workloads.full_ipm(seed=s, N=a.ipm_full_N),
                                a.ipm_full_gmres_solves, lib.PRECOND_NYSTROM, 200,
                                f"full-ipm: N={a.ipm_full_N} d=20, 7 windows, 10% label noise, sigma=0.8, C=10, "
-                               "Nystrom rank 200; GMRES with the block-triangular preconditioner",
-                               krylov=lib.KRYLOV_GMRES))
+                               "Nystrom rank 200, NFFT oversampling 3; GMRES with the block-triangular preconditioner",
+                               krylov=lib.KRYLOV_GMRES, oversample=3))
     out["ipm"] = ipm
+    progress("IPM legs done: " + ", ".join(f"{r['p50_ms']:.0f}" for r in ipm) + " ms p50")
     if a.serving_requests > 0:
         label = (f"serving: Poisson stream, rate {a.serving_rate}/s, N log-uniform 5e3..1e6, d uniform 6..60 "
                  "(3-feature windows), sigma log-uniform 0.5..2, C log-uniform 0.1..100; FP64 IPM, "
                  "pivoted-Cholesky rank 200, automatic initial barrier parameter, at most 200 iterations")
         cont = serving(lib, workloads, a.serving_requests, a.serving_rate, a.serving_max_active, True)
-        one = serving(lib, workloads, a.serving_requests, a.serving_rate, 1, False)
-        out["serving"] = {"workload": label, "continuous_batching": cont, "one_at_a_time": one}
+        progress(f"serving, continuous batching: p50 {cont['p50_ms']:.0f} ms p99 {cont['p99_ms']:.0f} ms")
+        out["serving"] = {"workload": label, "continuous_batching": cont}
+        if a.serving_reference_requests > 0:
+            out["serving"]["one_at_a_time"] = serving(lib, workloads, a.serving_reference_requests, a.serving_rate, 1,
+                                                      False)
+            progress("serving, one at a time done")
     if a.grid_folds > 0:
-        out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves)
+        out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves,
+                           a.grid_max_ip)
+        progress(f"grid: {out['grid']['solves_per_s']:.2f} solves/s, {out['grid']['converged']} converged")
     if not a.no_cpu_baseline:
         rec, rows, ref = cpu_baseline(p, a.cpu_seconds)
         out["cpu_baseline"] = rec

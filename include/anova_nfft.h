@@ -62,7 +62,7 @@ extern "C" {
                                   ANOVA_PRECOND_NONE, P = I. HIP graphs unused.   */
 
 #define ANOVA_OPTS_VERSION 1
-#define ANOVA_IPM_OPTS_VERSION 2
+#define ANOVA_IPM_OPTS_VERSION 3
 
 typedef struct anova_plan_s* anova_plan_t;
 
@@ -237,9 +237,10 @@ typedef struct {
     int32_t max_kry;     /* Krylov iterations per Newton solve (Table 1: 100)    */
     int32_t precond;     /* ANOVA_PRECOND_*                                      */
     double  tol;         /* on mu, |y^T a|/|y^T a0| and the relative duality gap;
-                            the gap, measured with the plan's fast-summation
-                            operator, must fall to tol / 2 (the other half
-                            covers its difference from the exact kernel's gap) */
+                            on FP64 plans the gap, measured with the plan's
+                            fast-summation operator, must fall to tol / 2 (the
+                            other half covers its difference from the exact
+                            kernel's gap); mixed-precision plans stop at tol   */
     double  tol_inf;     /* on ||xi_lambda||/||xi_lambda^0|| (Table 1: 1e-1)    */
     double  tol_kry;     /* upper bound of the Krylov relative tolerance (1e-3)  */
     double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */
@@ -256,6 +257,15 @@ typedef struct {
                             graph and replayed (solves outside a server or grid);
                             0: launched kernel by kernel. Same arithmetic.       */
     int32_t krylov;      /* ANOVA_KRYLOV_MINRES (0) or ANOVA_KRYLOV_GMRES (1)    */
+    int32_t factor_fp32; /* 1: the low-rank factor is built in FP64 and its N x k
+                            products (capacitance Gram matrix, Z^T u, Z t) read
+                            an FP32 copy of it, half the bytes, with FP64
+                            multiplies and sums: the preconditioner is then
+                            exactly that of the rounded factor, still SPD (FP32
+                            arithmetic in the Woodbury form, whose two terms
+                            cancel where theta is small, can make it
+                            indefinite); 0: the FP64 factor. Only the
+                            preconditioner changes, not the Newton systems.     */
 } anova_ipm_opts;
 
 typedef struct {
@@ -279,7 +289,7 @@ typedef struct {
  * max_kry = 100, tol_kry = 1e-3, sigma_bar = 0.6, gamma0 = 0.99995,
  * mu0 = 1, err_tol = 1e-5), tol = 1e-6, tol_inf = 1e-1, precond = PCHOL,
  * rank = 200, mu_rule = 0 (step-scaled reduction), seed = 0, graphs = 1,
- * krylov = MINRES. */
+ * krylov = MINRES, factor_fp32 = 1. */
 int anova_ipm_opts_default(anova_ipm_opts* o);
 
 /* Train: alpha (device, N FP64 out), lambda (host, 1 FP64 out; the bias of

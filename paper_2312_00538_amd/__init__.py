@@ -60,7 +60,7 @@ class IpmOpts(ctypes.Structure):
                 ("tol_kry", ctypes.c_double), ("sigma_bar", ctypes.c_double), ("gamma0", ctypes.c_double),
                 ("mu0", ctypes.c_double), ("rank", ctypes.c_int32), ("mu_rule", ctypes.c_int32),
                 ("err_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("graphs", ctypes.c_int32),
-                ("krylov", ctypes.c_int32)]
+                ("krylov", ctypes.c_int32), ("factor_fp32", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):

@@ -201,6 +201,7 @@ int anova_ipm_opts_default(anova_ipm_opts* o) {
     if (!o) return ANOVA_INVALID_ARG;
     std::memset(o, 0, sizeof(*o));
     o->version = ANOVA_IPM_OPTS_VERSION;
+    o->factor_fp32 = 1;
     o->max_ip = 100;
     o->max_kry = 100;
     o->precond = ANOVA_PRECOND_PCHOL;

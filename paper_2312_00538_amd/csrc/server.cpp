@@ -365,6 +365,7 @@ int64_t request_footprint(int64_t N, int32_t d, int32_t P, const anova_opts& nff
     const int64_t k = (ipm.precond == ANOVA_PRECOND_PCHOL || ipm.precond == ANOVA_PRECOND_NYSTROM ||
                        ipm.precond == ANOVA_PRECOND_RPCHOL || ipm.precond == ANOVA_PRECOND_RFF) ? ipm.rank : 0;
     b += (ipm.precond == ANOVA_PRECOND_NYSTROM ? 4 : 2) * N * k * 8;  // factor and its build
+    if (ipm.factor_fp32) b += N * k * 4;                             // FP32 copy for the products
     b += 260 * k * k * 8;                                            // capacitance partial sums
     if (ipm.krylov == ANOVA_KRYLOV_GMRES)                            // Arnoldi basis and P^{-1} v
         b += (int64_t(std::min(ipm.max_kry, 100)) + 2) * ((N + 1 + 31) / 32 * 32) * 8;
@@ -543,7 +544,10 @@ void grid_solve(const GridProblem* probs, int nprob, const anova_ipm_opts& o, in
             st.status = status;
             g.lambda[c] = lam;
             g.stats[c] = st;
-            if (--P.left == 0) P.f.Z.release();  // the problem's last solve has finished
+            if (--P.left == 0) {  // the problem's last solve has finished
+                P.f.Z.release();
+                P.f.Z32.release();
+            }
         }
         if (stream) {
             (void)hipStreamSynchronize(stream);

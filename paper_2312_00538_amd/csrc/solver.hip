@@ -259,7 +259,10 @@ __global__ void k_gram_partial(const double* __restrict__ Z, const double* __res
     if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc;
 }
 
-// Weighted Gram matrix on the FP64 matrix cores (v_mfma_f64_16x16x4f64):
+// Weighted Gram matrix on the FP64 matrix cores (v_mfma_f64_16x16x4f64), the
+// factor stored in FP64 or as its FP32 copy (read as FP32, multiplied and
+// summed in FP64, so that the matrix is exactly the Gram matrix of the stored
+// values up to FP64 rounding, as the Woodbury applies that use it assume):
 // part[c][a][b] = sum_{i in chunk c} Z_a(i) Z_b(i) / theta_i for a >= b (the
 // upper triangle is filled only inside diagonal super-tiles). Block = 4 waves on
 // one pair (sa >= sb) of 128-column super-tiles and one row chunk; wave w owns
@@ -269,7 +272,8 @@ __global__ void k_gram_partial(const double* __restrict__ Z, const double* __res
 // the result is D[l / 16 + 4 e][l % 16].
 constexpr int kST = 128;   // super-tile columns
 constexpr int kSP = 16;    // panel rows
-__global__ __launch_bounds__(256) void k_syrk_mfma(const double* __restrict__ Z, int64_t N, int k,
+template <class ZT>
+__global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int64_t N, int k,
                                                    const double* __restrict__ theta, int64_t chunk,
                                                    double* __restrict__ part) {
     typedef double d4 __attribute__((ext_vector_type(4)));
@@ -294,8 +298,8 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const double* __restrict__ Z,
             const int e = t + 256 * q, col = e / kSP, r = e % kSP;
             const int64_t i = ib0 + r;
             const int ga = sa * kST + col, gb = sb * kST + col;
-            ra[q] = (ga < k && i < i1) ? Z[int64_t(ga) * N + i] : 0.0;
-            rb[q] = (gb < k && i < i1) ? Z[int64_t(gb) * N + i] : 0.0;
+            ra[q] = (ga < k && i < i1) ? double(Z[int64_t(ga) * N + i]) : 0.0;
+            rb[q] = (gb < k && i < i1) ? double(Z[int64_t(gb) * N + i]) : 0.0;
         }
         if (t < kSP) {
             const int64_t i = ib0 + t;
@@ -371,7 +375,8 @@ void syrk_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
 // (group of kGemvCols columns, segment s), so that the product of long columns
 // keeps the GPU busy and each value of u read serves kGemvCols columns
 constexpr int kGemvCols = 4;
-__global__ __launch_bounds__(kT) void k_gemv_t_seg(const double* __restrict__ Z, int64_t N, int k,
+template <class ZT>
+__global__ __launch_bounds__(kT) void k_gemv_t_seg(const ZT* __restrict__ Z, int64_t N, int k,
                                                    const double* __restrict__ u, int64_t seg,
                                                    double* __restrict__ wpart) {
     const int j0 = blockIdx.x * kGemvCols, sgi = blockIdx.y;
@@ -386,9 +391,9 @@ __global__ __launch_bounds__(kT) void k_gemv_t_seg(const double* __restrict__ Z,
 #pragma unroll
         for (int c = 0; c < kGemvCols; ++c) {
             if (c < nc) {
-                const double* zc = Z + int64_t(j0 + c) * N;
-                a0[c] += zc[i] * u0;
-                a1[c] += zc[i + kT] * u1;
+                const ZT* zc = Z + int64_t(j0 + c) * N;
+                a0[c] += double(zc[i]) * u0;
+                a1[c] += double(zc[i + kT]) * u1;
             }
         }
     }
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(kT) void k_gemv_t_seg(const double* __restrict__ Z,
         const double u0 = u[i];
 #pragma unroll
         for (int c = 0; c < kGemvCols; ++c)
-            if (c < nc) a0[c] += Z[int64_t(j0 + c) * N + i] * u0;
+            if (c < nc) a0[c] += double(Z[int64_t(j0 + c) * N + i]) * u0;
     }
     __shared__ double sh[kGemvCols][kT];
 #pragma unroll
@@ -966,8 +971,9 @@ __global__ void k_wb_in(const double* __restrict__ y, const double* __restrict__
 }
 
 // second half: out = r / theta - (y / theta) * (Z t); out[N] = r[N] / s
+template <class ZT>
 __global__ void k_wb_out(const double* __restrict__ y, const double* __restrict__ th,
-                         const double* __restrict__ r, const double* __restrict__ Z, int64_t N, int k,
+                         const double* __restrict__ r, const ZT* __restrict__ Z, int64_t N, int k,
                          const double* __restrict__ t, const double* __restrict__ inv_s, int has_last,
                          double* __restrict__ out) {
     __shared__ double ts[1024];
@@ -976,12 +982,17 @@ __global__ void k_wb_out(const double* __restrict__ y, const double* __restrict_
     int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
     if (i < N) {
         double zt = 0.0;
-        for (int j = 0; j < k; ++j) zt += Z[int64_t(j) * N + i] * ts[j];
+        for (int j = 0; j < k; ++j) zt += double(Z[int64_t(j) * N + i]) * ts[j];
         double ti = 1.0 / th[i];
         out[i] = r[i] * ti - y[i] * ti * zt;
     } else if (i == N && has_last) {
         out[N] = r[N] * *inv_s;
     }
+}
+
+__global__ void k_narrow(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+    const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (i < n) b[i] = float(a[i]);
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -1103,6 +1114,7 @@ struct Workspace {
     Workspace(const Workspace&) = delete;
     Workspace& operator=(const Workspace&) = delete;
     const double* Z = nullptr;            // N x k column-major low-rank factor Z^T
+    const float* Z32 = nullptr;           // its FP32 copy, when the N x k products run in FP32
     DevBuf<double> M, Mpart, t;           // capacitance (its factor in place), partials, M^{-1} w
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
@@ -1127,21 +1139,31 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
     const int64_t N = pl.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
-        hipLaunchKernelGGL(k_gemv_t_seg, dim3(unsigned((ws.k + kGemvCols - 1) / kGemvCols), unsigned(ws.nseg)),
-                           dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
+        const dim3 g(unsigned((ws.k + kGemvCols - 1) / kGemvCols), unsigned(ws.nseg));
+        if (ws.Z32)
+            hipLaunchKernelGGL(k_gemv_t_seg<float>, g, dim3(kT), 0, st, ws.Z32, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
+        else
+            hipLaunchKernelGGL(k_gemv_t_seg<double>, g, dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
         hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.wpart.p,
                            ws.nseg, ws.t.p);
     }
-    hipLaunchKernelGGL(k_wb_out, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p, inv_s,
-                       has_last ? 1 : 0, out);
+    if (ws.Z32)
+        hipLaunchKernelGGL(k_wb_out<float>, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z32, N, ws.k, ws.t.p,
+                           inv_s, has_last ? 1 : 0, out);
+    else
+        hipLaunchKernelGGL(k_wb_out<double>, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z, N, ws.k, ws.t.p,
+                           inv_s, has_last ? 1 : 0, out);
 }
 
 void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t st) {
     if (ws.k == 0) return;
     const int k = ws.k;
     const int ns = (k + kST - 1) / kST;
-    hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st, ws.Z,
-                       pl.N, k, th, ws.chunk, ws.Mpart.p);
+    const dim3 g(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk));
+    if (ws.Z32)
+        hipLaunchKernelGGL(k_syrk_mfma<float>, g, dim3(256), 0, st, ws.Z32, pl.N, k, th, ws.chunk, ws.Mpart.p);
+    else
+        hipLaunchKernelGGL(k_syrk_mfma<double>, g, dim3(256), 0, st, ws.Z, pl.N, k, th, ws.chunk, ws.Mpart.p);
     hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
@@ -1293,7 +1315,7 @@ struct Gram {
     std::vector<double> run(const double* A, const double* B, int64_t N, int k, hipStream_t st) {
         if (A == B) {
             const int ns = (k + kST - 1) / kST;
-            hipLaunchKernelGGL(k_syrk_mfma, dim3(unsigned(ns * (ns + 1) / 2), unsigned(nchunk_s)), dim3(256), 0, st, A,
+            hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(nchunk_s)), dim3(256), 0, st, A,
                                N, k, (const double*)nullptr, chunk_s, part.p);
             hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, part.p, nchunk_s, k, 0.0,
                                M.p);
@@ -1526,6 +1548,11 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
         enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
         nystrom_core(pl, Y, o.rank, f.Z.p, st);
     }
+    if (o.factor_fp32 && f.rank > 0) {  // FP64 factor, FP32 copy for the products
+        f.Z32.alloc(size_t(N) * f.rank);
+        hipLaunchKernelGGL(k_narrow, dim3(nblk(N * f.rank)), dim3(kT), 0, st, f.Z.p, N * f.rank, f.Z32.p);
+        ANV_HIP(hipGetLastError());
+    }
     host_wait(st);
     f.t_setup_ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count();
 }
@@ -1613,6 +1640,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     }
     const int rank_used = factor->rank;
     ws.Z = factor->Z.p;
+    ws.Z32 = (o.factor_fp32 && factor->Z32.n >= size_t(N) * factor->rank) ? factor->Z32.p : nullptr;
     setup_factor_storage(ws, N, low_rank_precond(o.precond) ? rank_used : 0);
     const double t_setup_ms = factor->t_setup_ms;
 
@@ -1703,15 +1731,18 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
     int it = 0, kry_total = 0, kry_max = 0;
     int status = ANOVA_NOT_CONVERGED;
     double s_prev = 1.0;
+    const double gap_stop = (pl.precision == ANOVA_PREC_FP64 ? kGapMargin : 1.0) * o.tol;
     for (;;) {
         if (!(std::isfinite(mu) && std::isfinite(G) && std::isfinite(xl))) {
             status = ANOVA_NUMERICAL;
             break;
         }
         // the gap is measured with the fast-summation kernel, which differs from
-        // the exact one by the matvec error (~1e-7 relative at m = 4); stopping
-        // at half the tolerance keeps the gap in the exact kernel below it
-        if (mu <= o.tol && xa / xa0 <= o.tol && xl / xl0 <= o.tol_inf && G <= kGapMargin * o.tol) {
+        // the exact one by the matvec error (~1e-7 relative for FP64 plans);
+        // stopping at half the tolerance keeps the gap in the exact kernel below
+        // it. Mixed-precision plans (matvec error ~5e-7, above the tolerance's
+        // reach) stop at the tolerance itself.
+        if (mu <= o.tol && xa / xa0 <= o.tol && xl / xl0 <= o.tol_inf && G <= gap_stop) {
             status = ANOVA_OK;
             break;
         }

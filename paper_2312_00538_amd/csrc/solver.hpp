@@ -16,6 +16,7 @@ struct LowRankFactor {
     int precond = ANOVA_PRECOND_NONE;
     int rank = 0;             // columns used
     DevBuf<double> Z;
+    DevBuf<float> Z32;        // FP32 copy for the N x k products (anova_ipm_opts.factor_fp32)
     double t_setup_ms = 0.0;
 };
 

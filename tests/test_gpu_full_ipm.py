@@ -69,23 +69,28 @@ def test_full_size_solve_satisfies_the_optimality_conditions(dev, problem, krylo
     assert np.all(m[up] <= 1.0 + 1e-3)
 
 
-@pytest.mark.parametrize("krylov", ["minres", "gmres"])
-def test_full_ipm_shape_at_40000_meets_the_exact_gap(dev, krylov):
+@pytest.mark.parametrize("krylov,fp32", [("minres", 1), ("gmres", 1), ("minres", 0)])
+def test_full_ipm_shape_at_40000_meets_the_exact_gap(dev, krylov, fp32):
     # the full-IPM workload's shape (d = 20, 7 windows, 10 % label noise,
     # sigma = 0.8, C = 10, Nystrom rank 200) at N = 40 000, where one oracle
     # direct sum K (Y alpha) over all pairs (1.1e10 pair-windows) evaluates the
     # GPU solution in the exact QP of Algorithm 1 (eq. "kernelsvm"): relative
-    # duality gap G_exact <= 1e-6 and y^T alpha ~ 0
+    # duality gap G_exact <= 1e-6 and y^T alpha ~ 0. NFFT oversampling 3 (matvec
+    # error ~7e-8; at oversampling 2, ~4e-7, the exact gap sits near 1e-6). The
+    # factor's N x k products in FP32 (the default) or FP64: only the
+    # preconditioner differs, so both meet the bar, with similar Krylov counts.
     import paper_2312_00538_amd as lib
     p = workloads.full_ipm(seed=0, N=40_000)
-    pl = lib.Plan(to_dev(p.X, dev), p.windows, p.sigma)
+    pl = lib.Plan(to_dev(p.X, dev), p.windows, p.sigma, oversample=3)
     kr = lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES
-    alpha, lam, st = pl.solve(to_dev(p.labels, dev), p.C, precond=lib.PRECOND_NYSTROM, rank=200, krylov=kr)
+    alpha, lam, st = pl.solve(to_dev(p.labels, dev), p.C, precond=lib.PRECOND_NYSTROM, rank=200, krylov=kr,
+                              factor_fp32=fp32)
     a = alpha.cpu().numpy()
     assert st["status"] == 0 and st["rel_gap"] <= 1e-6
     kya = oracle.anova_matvec(p.X, p.windows, p.sigma, p.labels * a)
     D, Pr, G = oracle.objectives_from_kya(kya, p.labels, a, lam, p.C)
-    print(f"{krylov}: ip {st['ip_iters']} krylov {st['kry_iters_total']}, GPU gap {st['rel_gap']:.2e}, "
-          f"G_exact {G:.2e}, dual {D:.12g}, primal {Pr:.12g}, |y^T a| {abs(p.labels @ a):.1e}")
+    print(f"{krylov} fp32 products {fp32}: ip {st['ip_iters']} krylov {st['kry_iters_total']} (max "
+          f"{st['kry_iters_max']}), GPU gap {st['rel_gap']:.2e}, G_exact {G:.2e}, dual {D:.12g}, "
+          f"primal {Pr:.12g}, |y^T a| {abs(p.labels @ a):.1e}, {st['t_solve_ms']:.0f} ms")
     assert G <= 1e-6
     assert abs(p.labels @ a) <= 1e-6 * p.C * p.X.shape[0] / 4
