@@ -81,7 +81,7 @@ def parse():
                     help="requests of the same stream served one at a time (0 = skip)")
     ap.add_argument("--save-alpha", default=None,
                     help="write the first full-ipm solve's alpha and lambda to this .npz file")
-    ap.add_argument("--grid-max-ip", type=int, default=200)
+    ap.add_argument("--grid-max-ip", type=int, default=100)
     ap.add_argument("--serving-rate", type=float, default=2.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuned form of the matvec workload")

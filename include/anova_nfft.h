@@ -257,14 +257,15 @@ typedef struct {
                             graph and replayed (solves outside a server or grid);
                             0: launched kernel by kernel. Same arithmetic.       */
     int32_t krylov;      /* ANOVA_KRYLOV_MINRES (0) or ANOVA_KRYLOV_GMRES (1)    */
-    int32_t factor_fp32; /* 1: the low-rank factor is built in FP64 and its N x k
-                            products (capacitance Gram matrix, Z^T u, Z t) read
-                            an FP32 copy of it, half the bytes, with FP64
-                            multiplies and sums: the preconditioner is then
-                            exactly that of the rounded factor, still SPD (FP32
-                            arithmetic in the Woodbury form, whose two terms
-                            cancel where theta is small, can make it
-                            indefinite); 0: the FP64 factor. Only the
+    int32_t factor_fp32; /* 1: the low-rank factor is built in FP64 and rounded
+                            to FP32 values; Z^T u and Z t read an FP32 copy
+                            (half the bytes) and the capacitance Gram matrix the
+                            FP64 copy of the same values, all with FP64
+                            multiplies and sums, so the preconditioner is
+                            exactly that of the rounded factor and stays SPD
+                            (FP32 arithmetic in the Woodbury form, whose two
+                            terms cancel where theta is small, can make it
+                            indefinite); 0: the unrounded FP64 factor. Only the
                             preconditioner changes, not the Newton systems.     */
 } anova_ipm_opts;
 

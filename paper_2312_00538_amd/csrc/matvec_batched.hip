@@ -434,7 +434,10 @@ __global__ __launch_bounds__(64, 2) void k_gather_mfma(const int32_t* __restrict
 // The FP64 path runs the same contractions on v_mfma_f64_16x16x4f64 with FP64
 // records, inputs, grids and sums. Its accumulators and grid tiles take twice
 // the registers of the FP32 ones, so a wavefront takes one half of the 16
-// right-hand sides (work item = (segment, half)): M = 8 x taps x 8 rhs.
+// right-hand sides: M = 8 x taps x 8 rhs. A work item (segment) goes to a block
+// of two wavefronts, one per half, which stage each chunk of point records into
+// LDS once for both (each wavefront moves half of the chunk's DMA slots) and
+// run the same loops in step, so that the block barriers line up.
 // Operand layouts as for the FP32 instruction (A: lane (i, k), B: lane (k, j)),
 // but the result row of register v in lane (j, g) is g + 4 v (not 4 g + v).
 // Row i of m-block mb is therefore (x tap a = mb + 4 (i & 1), rhs
@@ -450,11 +453,13 @@ constexpr int REC64 = 24;   // doubles per FP64 point record: x, y and z taps
 
 // CHB records as stored (24 doubles each, 6 KB): 1 KB slot j, lane l moves bytes
 // 1024 j + 16 l of the chunk (one 16-byte piece of record (1024 j + 16 l) / 192).
+// Wavefront `w` of the block moves slots w, w + 2, ...
 __device__ inline void stage_records64(double* lrec, const double* __restrict__ wts, int64_t base, int cstart,
-                                       int count, int lane) {
+                                       int count, int lane, int w) {
     const int last = count - 1 - cstart;
 #pragma unroll
-    for (int j = 0; j < CHB * REC64 * 8 / 1024; ++j) {
+    for (int j2 = 0; j2 < CHB * REC64 * 8 / 2048; ++j2) {
+        const int j = 2 * j2 + w;
         const int o = j * 1024 + lane * 16;
         dma16(wts + (base + cstart + min(o / (REC64 * 8), last)) * REC64 + (o % (REC64 * 8)) / 8, lrec + j * 128);
     }
@@ -463,12 +468,25 @@ __device__ inline void stage_records64(double* lrec, const double* __restrict__ 
 // CHB records with the z taps repeated (32 doubles each, 8 KB), so that any 8
 // cyclically consecutive z taps are 8 consecutive doubles: 4 records per slot.
 __device__ inline void stage_records64_ring(double* lrec, const double* __restrict__ wts, int64_t base, int cstart,
-                                            int count, int lane) {
+                                            int count, int lane, int w) {
     const int last = count - 1 - cstart;
     const int e = (lane % 16) * 2;
 #pragma unroll
-    for (int j = 0; j < CHB / 4; ++j)
+    for (int j2 = 0; j2 < CHB / 8; ++j2) {
+        const int j = 2 * j2 + w;
         dma16(wts + (base + cstart + min(j * 4 + lane / 16, last)) * REC64 + (e < 24 ? e : e - 8), lrec + j * 128);
+    }
+}
+
+// The next work item of a two-wavefront block (taken by its first thread from
+// the queue shared by the resident blocks; the trailing barrier keeps the slot
+// from being overwritten before both wavefronts have read it).
+__device__ inline int next_item(int32_t* queue, int* slot) {
+    if (threadIdx.x == 0) *slot = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = *slot;
+    __syncthreads();
+    return it;
 }
 
 // This wavefront's 8 right-hand sides of two value rows (16 rows per slot,
@@ -530,7 +548,7 @@ __device__ inline d2 lds_load_d2(uint32_t addr) {
 // n = lr -> (y tap b = nb + 4 (lr >> 3), physical z column lr & 7); the lane
 // (lr, lk) holds x tap mb + 4 (lk & 1) and right-hand sides 4 (lk >> 1) .. + 3
 // of its half, in column lr. A step takes 4 points.
-__global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
+__global__ __launch_bounds__(128, 2) void k_spread_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
                                                          int32_t* __restrict__ queue,
                                                          const Segment* __restrict__ segs,
                                                          const int32_t* __restrict__ lstart,
@@ -543,16 +561,17 @@ __global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restri
                                                          double* __restrict__ slab, double* __restrict__ tgt) {
     constexpr int STEP = CHB - 4;
     __shared__ __align__(16) double srec[2][CHB * REC64];
-    __shared__ __align__(16) double sval[2][CHB * RHW];
-    __shared__ __align__(16) double stg[64 * RHW];
-    const int lane = threadIdx.x;
+    __shared__ __align__(16) double svals[2][2][CHB * RHW];
+    __shared__ __align__(16) double stgs[2][64 * RHW];
+    __shared__ int slot;
+    const int lane = threadIdx.x & 63;
+    const int half = threadIdx.x >> 6;  // the wavefront's half of the right-hand sides
+    double(&sval)[2][CHB * RHW] = svals[half];
+    double* const stg = stgs[half];
     for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(queue, 1);
-        it = __builtin_amdgcn_readfirstlane(it);
+        const int it = next_item(queue, &slot);
         if (it >= nwork) break;
-        const int sid = wave_items[it >> 1];
-        const int half = it & 1;
+        const int sid = wave_items[it];
         const Segment sg = segs[sid];
         const WinDev& wd = wins[sg.win];
         const int lr = lane & 15, lk = lane >> 4;
@@ -601,7 +620,7 @@ __global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restri
         constexpr uint32_t RECB = CHB * REC64 * 8, VALB = CHB * RHW * 8;  // bytes per buffer
         int cc = -1;
         int32_t prow[2];
-        stage_records64(srec[0], wts, base, 0, sg.count, lane);
+        stage_records64(srec[0], wts, base, 0, sg.count, lane, half);
         value_rows(perm, base, 0, sg.count, lane, prow);
         stage_values64(sval[0], xt, prow, half, lane);
         if (STEP < sg.count) value_rows(perm, base, STEP, sg.count, lane, prow);
@@ -614,7 +633,7 @@ __global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restri
                     __syncthreads();
                     cc = c;
                     if ((c + 1) * STEP < sg.count) {
-                        stage_records64(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                        stage_records64(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane, half);
                         stage_values64(sval[(c + 1) & 1], xt, prow, half, lane);
                         if ((c + 2) * STEP < sg.count) value_rows(perm, base, (c + 2) * STEP, sg.count, lane, prow);
                     }
@@ -651,7 +670,7 @@ __global__ __launch_bounds__(64, 2) void k_spread_mfma64(const int32_t* __restri
 // (x tap mb + 4 (lk & 1), rhs 4 (lk >> 1) .. + 3); f sums the x taps of
 // a < 4 in the lanes with even lk, adds those of a >= 4 from lane + 16, and
 // stores.
-__global__ __launch_bounds__(64, 2) void k_gather_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
+__global__ __launch_bounds__(128, 2) void k_gather_mfma64(const int32_t* __restrict__ wave_items, int32_t nwork,
                                                          int32_t* __restrict__ queue,
                                                          const Segment* __restrict__ segs,
                                                          const int32_t* __restrict__ lstart,
@@ -663,14 +682,13 @@ __global__ __launch_bounds__(64, 2) void k_gather_mfma64(const int32_t* __restri
     constexpr int STEP = CHB - 16;
     constexpr int RPD = 32;  // doubles per staged record (z taps repeated)
     __shared__ __align__(16) double srec[2][CHB * RPD];
-    const int lane = threadIdx.x;
+    __shared__ int slot;
+    const int lane = threadIdx.x & 63;
+    const int half = threadIdx.x >> 6;  // the wavefront's half of the right-hand sides
     for (;;) {
-        int it = 0;
-        if (lane == 0) it = atomicAdd(queue, 1);
-        it = __builtin_amdgcn_readfirstlane(it);
+        const int it = next_item(queue, &slot);
         if (it >= nwork) break;
-        const int sid = wave_items[it >> 1];
-        const int half = it & 1;
+        const int sid = wave_items[it];
         const Segment sg = segs[sid];
         const WinDev& wd = wins[sg.win];
         const int lr = lane & 15, lk = lane >> 4;
@@ -698,7 +716,7 @@ __global__ __launch_bounds__(64, 2) void k_gather_mfma64(const int32_t* __restri
         const uint32_t rec0 = lds_addr(&srec[0][0]);
         constexpr uint32_t RECB = CHB * RPD * 8;
         int cc = -1;
-        stage_records64_ring(srec[0], wts, base, 0, sg.count, lane);
+        stage_records64_ring(srec[0], wts, base, 0, sg.count, lane, half);
         for (int z = sg.z0; z <= sg.z1; ++z) {
             const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
             for (int k = p; k < q; k += 16) {
@@ -708,7 +726,7 @@ __global__ __launch_bounds__(64, 2) void k_gather_mfma64(const int32_t* __restri
                     __syncthreads();
                     cc = c;
                     if ((c + 1) * STEP < sg.count)
-                        stage_records64_ring(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane);
+                        stage_records64_ring(srec[(c + 1) & 1], wts, base, (c + 1) * STEP, sg.count, lane, half);
                 }
                 const int pt = k + lr;
                 const uint32_t rb = rec0 + uint32_t(c & 1) * RECB + uint32_t(pt - c * STEP) * (RPD * 8);
@@ -1176,13 +1194,14 @@ void ensure_batched_buffers(Plan& pl) {
         ANV_HIP(hipGetDevice(&dev));
         ANV_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         if (f64) {
-            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma64, 64, 0));
-            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma64, 64, 0));
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma64, 128, 0));
+            ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma64, 128, 0));
         } else {
             ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bs, k_spread_mfma, 64, 0));
             ANV_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bg, k_gather_mfma, 64, 0));
         }
-        const int work = pl.nwave[3] * (f64 ? 2 : 1);
+        // one block per work item in flight (two wavefronts for FP64, one for FP32)
+        const int work = pl.nwave[3];
         pl.b_grid[0] = std::max(1, std::min(work, std::max(1, bs) * ncu));
         pl.b_grid[1] = std::max(1, std::min(work, std::max(1, bg) * ncu));
     }
@@ -1218,8 +1237,8 @@ void batched_pass_t(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
     if (prof) pl.record_stage_event(st);
     if (pl.nwave[3]) {
         if constexpr (f64)
-            hipLaunchKernelGGL(k_spread_mfma64, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                               2 * pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
+            hipLaunchKernelGGL(k_spread_mfma64, dim3(pl.b_grid[0]), dim3(128), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p, pl.segs.p, pl.lstart.p, pl.lstart_off.p, pl.wins_d.p,
                                pl.alone.p, pl.wts64.p, pl.perm.p, xt, N, slab, tgt);
         else
             hipLaunchKernelGGL(k_spread_mfma, dim3(pl.b_grid[0]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
@@ -1251,8 +1270,8 @@ void batched_pass_t(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
     if (prof) pl.record_stage_event(st);
     if (pl.nwave[3]) {
         if constexpr (f64)
-            hipLaunchKernelGGL(k_gather_mfma64, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],
-                               2 * pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p,
+            hipLaunchKernelGGL(k_gather_mfma64, dim3(pl.b_grid[1]), dim3(128), 0, st, pl.wave_items.p + pl.wave_off[3],
+                               pl.nwave[3], pl.b_queue.p + 1, pl.segs.p, pl.lstart.p, pl.lstart_off.p,
                                pl.wins_d.p, pl.wts64.p, hb, N, fsb);
         else
             hipLaunchKernelGGL(k_gather_mfma, dim3(pl.b_grid[1]), dim3(64), 0, st, pl.wave_items.p + pl.wave_off[3],

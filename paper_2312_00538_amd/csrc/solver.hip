@@ -990,9 +990,15 @@ __global__ void k_wb_out(const double* __restrict__ y, const double* __restrict_
     }
 }
 
-__global__ void k_narrow(const double* __restrict__ a, int64_t n, float* __restrict__ b) {
+// b = a rounded to FP32, and a replaced by those rounded values, so that both
+// copies hold the same numbers
+__global__ void k_narrow(double* __restrict__ a, int64_t n, float* __restrict__ b) {
     const int64_t i = blockIdx.x * int64_t(kT) + threadIdx.x;
-    if (i < n) b[i] = float(a[i]);
+    if (i < n) {
+        const float v = float(a[i]);
+        b[i] = v;
+        a[i] = double(v);
+    }
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
@@ -1159,11 +1165,10 @@ void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t 
     if (ws.k == 0) return;
     const int k = ws.k;
     const int ns = (k + kST - 1) / kST;
-    const dim3 g(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk));
-    if (ws.Z32)
-        hipLaunchKernelGGL(k_syrk_mfma<float>, g, dim3(256), 0, st, ws.Z32, pl.N, k, th, ws.chunk, ws.Mpart.p);
-    else
-        hipLaunchKernelGGL(k_syrk_mfma<double>, g, dim3(256), 0, st, ws.Z, pl.N, k, th, ws.chunk, ws.Mpart.p);
+    // the FP64 factor (holding the FP32 copy's values when there is one): the
+    // 128-column panels of the Gram kernel read whole 128-byte rows in FP64
+    hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st,
+                       ws.Z, pl.N, k, th, ws.chunk, ws.Mpart.p);
     hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
                        ws.M.p);
     hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
@@ -1548,7 +1553,7 @@ void build_low_rank(Plan& pl, const anova_ipm_opts& o, LowRankFactor& f, hipStre
         enqueue_matvec(pl, Gd.p, o.rank, N, Y.p, N, st);
         nystrom_core(pl, Y, o.rank, f.Z.p, st);
     }
-    if (o.factor_fp32 && f.rank > 0) {  // FP64 factor, FP32 copy for the products
+    if (o.factor_fp32 && f.rank > 0) {  // FP32 copy for the Woodbury products; the FP64 factor takes its values
         f.Z32.alloc(size_t(N) * f.rank);
         hipLaunchKernelGGL(k_narrow, dim3(nblk(N * f.rank)), dim3(kT), 0, st, f.Z.p, N * f.rank, f.Z32.p);
         ANV_HIP(hipGetLastError());
