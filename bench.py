@@ -81,7 +81,11 @@ def parse():
                     help="requests of the same stream served one at a time (0 = skip)")
     ap.add_argument("--save-alpha", default=None,
                     help="write the first full-ipm solve's alpha and lambda to this .npz file")
-    ap.add_argument("--grid-max-ip", type=int, default=100)
+    ap.add_argument("--grid-max-ip", type=int, default=200)
+    ap.add_argument("--grid-max-kry", type=int, default=300,
+                    help="Krylov cap per Newton solve of the grid (the narrowest kernel at C = 1000 needs more than 100)")
+    ap.add_argument("--grid-precision", choices=["fp64", "mixed"], default="fp64",
+                    help="precision of the grid's plans (mixed-precision plans stall or break down at C >= 268)")
     ap.add_argument("--serving-rate", type=float, default=2.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the autotuned form of the matvec workload")
@@ -228,14 +232,15 @@ def serving(lib, workloads, n, rate, max_active, share):
             "N_max": int(max(r["N"] for r in stream)), "N_median": int(np.median([r["N"] for r in stream]))}
 
 
-def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip):
+def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip, max_kry, precision):
     """Hyperparameter grid over cross-validation folds: 8 sigma x 8 C per fold,
-    mixed-precision plans, solves of a plan sharing its pivoted-Cholesky
-    factor, matvecs of concurrent solves in shared launches."""
+    FP64 (default) or mixed-precision plans, solves of a plan sharing its
+    pivoted-Cholesky factor, matvecs of concurrent solves in shared launches."""
     g = workloads.cv_grid(seed=0)
     p = g["problem"]
     folds = min(folds, len(g["folds"]))
-    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0, max_ip=max_ip)
+    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0, max_ip=max_ip, max_kry=max_kry)
+    prec = lib.PREC_FP64 if precision == "fp64" else lib.PREC_MIXED
     t0 = time.perf_counter()
     probs, data = [], []
     for tr, _ in g["folds"][:folds]:
@@ -243,7 +248,7 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip):
         yd = torch.from_numpy(p.labels[tr]).to(dev)
         data.append((Xd, yd))
         for s in g["sigmas"]:
-            probs.append((lib.Plan(Xd, p.windows, float(s), precision=lib.PREC_MIXED), yd, list(g["Cs"])))
+            probs.append((lib.Plan(Xd, p.windows, float(s), precision=prec), yd, list(g["Cs"])))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     res, launches, matvecs = lib.grid_solve(probs, max_active=max_active, **kw)
@@ -254,13 +259,17 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip):
         status[str(x["status"])] = status.get(str(x["status"]), 0) + 1
     out = {"workload": f"cross-validation grid: N=50000, d=15 (5 windows of 3), {folds} of 5 folds (class-balanced "
                        "training parts of 39874..39982 points), sigma 8 log-spaced in 0.25..4, C 8 log-spaced in "
-                       "0.1..1000; mixed-precision plans, pivoted-Cholesky rank 200 shared per plan, automatic "
-                       f"initial barrier parameter, at most {max_ip} iterations",
+                       f"0.1..1000; {'FP64' if precision == 'fp64' else 'mixed-precision'} plans, pivoted-Cholesky "
+                       "rank 200 shared per plan, automatic initial barrier parameter, at most "
+                       f"{max_ip} IPM and {max_kry} Krylov iterations",
            "solves": len(st), "plans": len(probs), "plan_s": t1 - t0, "wall_s": t2 - t1,
            "solves_per_s": len(st) / (t2 - t1), "status_counts": status,
            "converged": status.get("0", 0), "converged_per_s": status.get("0", 0) / (t2 - t1),
            "ip_iters_mean": float(np.mean([x["ip_iters"] for x in st])),
-           "shared_launches": launches, "matvecs": matvecs, "max_active": max_active}
+           "shared_launches": launches, "matvecs": matvecs, "max_active": max_active,
+           "not_converged": [{"fold": i // len(g["sigmas"]), "sigma": float(g["sigmas"][i % len(g["sigmas"])]),
+                              "C": float(g["Cs"][j]), "status": x["status"], "rel_gap": x["rel_gap"]}
+                             for i, r in enumerate(res) for j, x in enumerate(r[2]) if x["status"] != 0]}
     if ref_solves > 0:
         # the same solves one at a time, FP64 plans (a sample spread over sigma and C)
         Xd, yd = data[0]
@@ -515,7 +524,7 @@ def main():
             progress("serving, one at a time done")
     if a.grid_folds > 0:
         out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves,
-                           a.grid_max_ip)
+                           a.grid_max_ip, a.grid_max_kry, a.grid_precision)
         progress(f"grid: {out['grid']['solves_per_s']:.2f} solves/s, {out['grid']['converged']} converged")
     if not a.no_cpu_baseline:
         rec, rows, ref = cpu_baseline(p, a.cpu_seconds)

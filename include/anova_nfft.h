@@ -78,7 +78,7 @@ typedef struct {
     int32_t reg_p;       /* smoothness of the regularisation; <= 0 picks per axis  */
     int32_t precision;   /* ANOVA_PREC_FP64 or ANOVA_PREC_MIXED                    */
     int32_t seg_points;  /* points per spreading work item; <= 0 = default         */
-    int32_t batch_min_rhs; /* mixed precision with cutoff_m = 4 only: anova_matvec
+    int32_t batch_min_rhs; /* cutoff_m = 4 only (either precision): anova_matvec
                             calls with R >= batch_min_rhs run the batched kernels
                             (16 right-hand sides per pass, matrix-core spreading
                             and gathering); 0 = default 2, < 0 = never        */
@@ -113,11 +113,14 @@ int anova_plan_create(const double* X, int64_t N, int32_t d, int64_t ldx,
  * window is evaluated by NFFT fast summation (spread with the Kaiser-Bessel
  * window, grid convolution with the kernel's Fourier coefficients, gather)
  * and the windows are summed in FP64 in a fixed order, so results are
- * bitwise reproducible for a given plan, input and R. Mixed-precision plans
- * with cutoff_m = 4 take R >= batch_min_rhs right-hand sides 16 at a time
- * through the batched kernels (same algorithm and summation orders, FP32
- * matrix-core contractions); their results agree with the one-at-a-time
- * kernels to FP32 rounding, not bit for bit. The batched path allocates its
+ * bitwise reproducible for a given plan, input and R. Plans with
+ * cutoff_m = 4 take R >= batch_min_rhs right-hand sides 16 at a time through
+ * the batched kernels (same algorithm, spreading and gathering as matrix-core
+ * contractions): FP64 plans on FP64 matrix cores, agreeing with the
+ * one-at-a-time kernels to FP64 rounding (below 1e-11 relative); mixed plans
+ * spread in FP32 and gather in split-bf16 (three bf16 products per FP32
+ * product), agreeing with the one-at-a-time kernels to FP32 rounding. Neither
+ * is bit for bit the one-vector result. The batched path allocates its
  * scratch (about 16x the single-vector scratch) on first use.
  *   x   device, N x R FP64, column r at x + r*ldx_ (ldx_ >= N).
  *   y   device, N x R FP64 output, column r at y + r*ldy (ldy >= N); must not
@@ -240,7 +243,8 @@ typedef struct {
                             on FP64 plans the gap, measured with the plan's
                             fast-summation operator, must fall to tol / 2 (the
                             other half covers its difference from the exact
-                            kernel's gap); mixed-precision plans stop at tol   */
+                            kernel's gap); mixed-precision plans stop at tol.
+                            mu is never reduced below tol / 1000              */
     double  tol_inf;     /* on ||xi_lambda||/||xi_lambda^0|| (Table 1: 1e-1)    */
     double  tol_kry;     /* upper bound of the Krylov relative tolerance (1e-3)  */
     double  sigma_bar;   /* barrier reduction (Table 1: 0.6)                     */

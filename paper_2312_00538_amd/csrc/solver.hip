@@ -306,6 +306,14 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int
             rw = (i < i1) ? (theta ? 1.0 / theta[i] : 1.0) : 0.0;
         }
     };
+    // 16 x 16 result blocks: row block rb0 + tr of this wave, column block
+    // cb0 + tc. Blocks past k and blocks wholly above the diagonal are never
+    // read by the fold, so the wave skips them (the tests are wave-uniform).
+    const int nb = (k + 15) / 16;
+    const int rb0 = sa * (kST / 16) + 2 * w, cb0 = sb * (kST / 16);
+    auto live = [&](int tr, int tc) __attribute__((always_inline)) {
+        return rb0 + tr < nb && cb0 + tc < nb && cb0 + tc <= rb0 + tr;
+    };
     if (i0 < i1) load_panel(i0);
     for (int64_t ib0 = i0; ib0 < i1; ib0 += kSP) {
 #pragma unroll
@@ -317,17 +325,22 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int
         if (t < kSP) wt[t] = rw;
         __syncthreads();
         if (ib0 + kSP < i1) load_panel(ib0 + kSP);
+        if (live(1, 0) || live(0, 0)) {
 #pragma unroll
-        for (int s4 = 0; s4 < kSP / 4; ++s4) {
-            const int r = 4 * s4 + lg;
-            double av[2];
+            for (int s4 = 0; s4 < kSP / 4; ++s4) {
+                const int r = 4 * s4 + lg;
+                double av[2];
 #pragma unroll
-            for (int tr = 0; tr < 2; ++tr) av[tr] = pa[(2 * w + tr) * 16 + lm][r] * wt[r];
+                for (int tr = 0; tr < 2; ++tr) av[tr] = pa[(2 * w + tr) * 16 + lm][r] * wt[r];
 #pragma unroll
-            for (int tc = 0; tc < 8; ++tc) {
-                const double bv = pb[tc * 16 + lm][r];
+                for (int tc = 0; tc < 8; ++tc) {
+                    if (!live(1, tc) && !live(0, tc)) continue;
+                    const double bv = pb[tc * 16 + lm][r];
 #pragma unroll
-                for (int tr = 0; tr < 2; ++tr) acc[tr][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tr], bv, acc[tr][tc], 0, 0, 0);
+                    for (int tr = 0; tr < 2; ++tr)
+                        if (live(tr, tc))
+                            acc[tr][tc] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[tr], bv, acc[tr][tc], 0, 0, 0);
+                }
             }
         }
         __syncthreads();
@@ -335,12 +348,14 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int
 #pragma unroll
     for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-        for (int tc = 0; tc < 8; ++tc)
+        for (int tc = 0; tc < 8; ++tc) {
+            if (!live(tr, tc)) continue;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int ia = sa * kST + (2 * w + tr) * 16 + lg + 4 * e, ib = sb * kST + tc * 16 + lm;
                 if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc[tr][tc][e];
             }
+        }
 }
 
 // M[a][b] = M[b][a] = diag [a == b] + sum_c part[c][a][b] for a >= b (chunks in
@@ -1068,6 +1083,8 @@ __global__ void k_gaussian(double* __restrict__ G, int64_t N, int k, uint64_t se
 // fraction of the gap tolerance at which the IPM stops (the rest covers the
 // difference between the gap in the fast-summation kernel and in the exact one)
 constexpr double kGapMargin = 0.5;
+// the barrier parameter is not reduced below this fraction of the tolerance
+constexpr double kMuFloor = 1e-3;
 
 // ------------------------------------------------------------------ host helpers
 struct Reducer {
@@ -1755,6 +1772,10 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         // Section 2: a constant reduction factor, or one that changes every iteration;
         // the default scales the reduction by the previous step length
         mu *= (o.mu_rule == 1) ? o.sigma_bar : 1.0 - (1.0 - o.sigma_bar) * s_prev;
+        // never below kMuFloor * tol: the stop test asks only mu <= tol, a smaller
+        // mu moves the central point by less than the gap tolerance (its duality
+        // gap is 2 N mu), and the barrier weights of rows at a bound grow like 1/mu
+        mu = std::max(mu, kMuFloor * o.tol);
         hipLaunchKernelGGL(k_theta, dim3(nblk(N)), dim3(kT), 0, st, alpha, N, C, mu, th.p);
         const double r2 = red.dot(labels, alpha, N, st);
         hipLaunchKernelGGL(k_rhs, dim3(nblk(n1)), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, r2,
