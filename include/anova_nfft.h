@@ -357,6 +357,31 @@ int anova_rff_factor(anova_plan_t plan, int32_t k, const double* w, const double
 int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg,
                   double* Zt, int64_t ldz, void* stream);
 
+/* The low-rank-plus-diagonal preconditioner of Section 5 applied to one
+ * vector: out = (Theta + Y Z Z^T Y)^{-1} r with Theta = diag(theta) and
+ * Y = diag(y), through the Sherman-Morrison-Woodbury form of Section 5,
+ *   Theta^{-1} r - Theta^{-1} Y Z (I + Z^T Theta^{-1} Z)^{-1} Z^T Y Theta^{-1} r,
+ * by the kernels the interior point method uses every iteration (the
+ * capacitance matrix on the matrix cores, its Cholesky factor, the two N x k
+ * passes).
+ *   N, k   sizes, N >= 1, 1 <= k <= 1024.
+ *   Z      device, N x k FP64 factor, column j at Z + j*ldz (ldz >= N);
+ *          copied, not modified.
+ *   theta  device, N FP64 diagonal, every entry > 0.
+ *   y      device, N FP64 signs (+-1), or NULL for Y = I.
+ *   r      device, N FP64 input.   out  device, N FP64 output (not r).
+ *   fp32_products  0: the N x k passes read the FP64 factor; 1: the factor is
+ *          first rounded to FP32 values and the passes read an FP32 copy (the
+ *          solver's anova_ipm_opts.factor_fp32 form; the result is that of the
+ *          rounded factor).
+ * Allocates its scratch per call and synchronises `stream`. Errors:
+ * ANOVA_INVALID_ARG (sizes, NULL pointers, ldz < N), ANOVA_NUMERICAL (the
+ * capacitance matrix is not numerically positive definite),
+ * ANOVA_OUT_OF_MEMORY, ANOVA_HIP_ERROR. */
+int anova_lowrank_apply(int64_t N, int32_t k, const double* Z, int64_t ldz,
+                        const double* theta, const double* y, const double* r,
+                        int32_t fp32_products, double* out, void* stream);
+
 /* ------------------------------------------------------------------ serving
  * A request server that runs interior point solves (svm_ipm_solve semantics)
  * of different sizes on one GPU with continuous batching. Requests are

@@ -30,7 +30,7 @@ EXPORTED = [
     "anova_server_counters", "anova_server_destroy", "anova_request_footprint", "anova_grid_solve",
     "anova_tune_opts_default", "anova_autotune", "anova_rp_cholesky", "anova_decision_function",
     "anova_rff_factor", "anova_mi_windows", "anova_matvec_noalloc", "anova_kaiser_bessel",
-    "anova_axis_coefficients",
+    "anova_axis_coefficients", "anova_lowrank_apply",
 ]
 STAGES = ["permute", "spread", "fold", "convolve", "gather", "window_sum"]
 
@@ -136,6 +136,7 @@ def load_library(path: str = LIB_PATH):
                            ctypes.POINTER(IpmStats), P], ctypes.c_int),
         "anova_pivoted_cholesky": ([P, i32, dbl, P, i64, P, ctypes.POINTER(i32), P], ctypes.c_int),
         "anova_nystrom": ([P, P, i32, i64, P, i64, P], ctypes.c_int),
+        "anova_lowrank_apply": ([i64, i32, P, i64, P, P, P, i32, P, P], ctypes.c_int),
         "anova_last_error": ([], ctypes.c_char_p),
         "anova_profile_begin": ([P], ctypes.c_int),
         "anova_profile_end": ([P, P, i32, ctypes.POINTER(i32)], ctypes.c_int),
@@ -414,6 +415,26 @@ def axis_coefficients(lo: float, hi: float, sigma: float, opts: Opts | None = No
                                        bk.ctypes.data_as(ctypes.c_void_p), circ.ctypes.data_as(ctypes.c_void_p),
                                        ax.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rp)))
     return dict(bk=bk, circ=circ, center=ax[0], scale=ax[1], sigma_a=ax[2], kerr=ax[3], reg_p=rp.value)
+
+
+def lowrank_apply(Zt, theta, r, y=None, fp32_products: bool = False, stream=None):
+    """(Theta + Y Z Z^T Y)^{-1} r through the solver's preconditioner kernels
+    (anova_lowrank_apply). Zt: (k, N) device FP64, row j = column j of Z;
+    theta, r, y: (N,) device FP64 (y None = identity)."""
+    import torch
+    lib = load_library()
+    Zt = _dev_f64(Zt, "Zt")
+    theta, r = _dev_f64(theta, "theta"), _dev_f64(r, "r")
+    k, N = int(Zt.shape[0]), int(Zt.shape[1])
+    with _on_stream(stream, r) as s:
+        Zc, th, rc = Zt.contiguous(), theta.contiguous(), r.contiguous()
+        yc = _dev_f64(y, "y").contiguous() if y is not None else None
+        out = torch.empty(N, dtype=torch.float64, device=r.device)
+        _check(lib.anova_lowrank_apply(N, k, ctypes.c_void_p(Zc.data_ptr()), N, ctypes.c_void_p(th.data_ptr()),
+                                       ctypes.c_void_p(yc.data_ptr()) if yc is not None else None,
+                                       ctypes.c_void_p(rc.data_ptr()), 1 if fp32_products else 0,
+                                       ctypes.c_void_p(out.data_ptr()), s))
+    return out
 
 
 def request_footprint(N: int, d: int, P: int, nfft: Opts | None = None, ipm: IpmOpts | None = None) -> int:

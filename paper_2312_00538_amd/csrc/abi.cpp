@@ -287,6 +287,15 @@ int anova_nystrom(anova_plan_t plan, const double* G, int32_t k, int64_t ldg, do
     });
 }
 
+int anova_lowrank_apply(int64_t N, int32_t k, const double* Z, int64_t ldz, const double* theta, const double* y,
+                        const double* r, int32_t fp32_products, double* out, void* stream) {
+    return guarded([&] {
+        ANV_CHECK(fp32_products == 0 || fp32_products == 1, "fp32_products must be 0 or 1");
+        anv::lowrank_apply(N, k, Z, ldz, theta, y, r, fp32_products != 0, out, static_cast<hipStream_t>(stream));
+        return ANOVA_OK;
+    });
+}
+
 int anova_server_opts_default(anova_server_opts* o) {
     if (!o) return ANOVA_INVALID_ARG;
     std::memset(o, 0, sizeof(*o));

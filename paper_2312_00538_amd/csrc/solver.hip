@@ -48,7 +48,8 @@ __device__ void block_sums(double (&v)[NS], double* __restrict__ out) {
 __global__ void k_fold_partials(const double* __restrict__ part, int nb, int ns, double* __restrict__ out) {
     const int q = blockIdx.x, j = threadIdx.x;
     double s = 0.0;
-    for (int b = j; b < nb; b += 64) s += part[b * ns + q];
+#pragma unroll 8
+    for (int b = j; b < nb; b += 64) s += part[b * ns + q];  // unrolled: the loads go out together
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if (j == 0) out[q] = s;
@@ -204,21 +205,39 @@ __global__ void k_argmax_sum(const double* __restrict__ d, int64_t n, double* __
     }
 }
 
+// out = {largest value (ties: smallest index), its index, sum of the block
+// sums}: lane j takes blocks j, j + 64, ... in order, then a fixed xor tree
+// combines the lanes (the argmax does not depend on the order; the sum's order
+// is fixed)
 __global__ void k_argmax_final(const double* __restrict__ pval, const int64_t* __restrict__ pidx,
                                const double* __restrict__ psum, int nb, double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
     double best = -INFINITY, sum = 0.0;
     int64_t bi = INT64_MAX;
-    for (int b = 0; b < nb; ++b) {
-        if (pval[b] > best || (pval[b] == best && pidx[b] < bi)) {
-            best = pval[b];
-            bi = pidx[b];
+#pragma unroll 4
+    for (int b = threadIdx.x; b < nb; b += 64) {
+        const double v = pval[b];
+        const int64_t i = pidx[b];
+        if (v > best || (v == best && i < bi)) {
+            best = v;
+            bi = i;
         }
         sum += psum[b];
     }
-    out[0] = best;
-    out[1] = double(bi);
-    out[2] = sum;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double v = __shfl_xor(best, o, 64);
+        const int64_t i = __shfl_xor(bi, o, 64);
+        if (v > best || (v == best && i < bi)) {
+            best = v;
+            bi = i;
+        }
+        sum += __shfl_xor(sum, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        out[0] = best;
+        out[1] = double(bi);
+        out[2] = sum;
+    }
 }
 
 __global__ void k_fill(double* __restrict__ x, int64_t n, double v) {
@@ -358,6 +377,98 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int
         }
 }
 
+// The same partial sums for k <= 256, balanced over the wavefronts: one block
+// per row chunk computes every lower 16 x 16 result block over its rows, the
+// blocks dealt to its kSyW wavefronts in turn (block q, counted down the block
+// columns, to wavefront q % kSyW, slot q / kSyW), so that every wavefront issues
+// nearly the same number of matrix-core products. 16-row panels of Z (all k
+// columns) and their weights 1 / theta are staged in LDS, double-buffered; the
+// next panel's loads are in flight while the current one is multiplied.
+constexpr int kSyW = 8;
+constexpr int kSyKP = 256 + 1;  // panel row stride in LDS
+template <int NS>
+__global__ __launch_bounds__(64 * kSyW) void k_syrk_tri(const double* __restrict__ Z, int64_t N, int k,
+                                                         const double* __restrict__ theta, int64_t chunk,
+                                                         double* __restrict__ part) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double pz[2][kSP][kSyKP], wt[2][kSP];
+    __shared__ int blk[kSyW * NS];  // block q: I | J << 8 (-1: none)
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int nb = (k + 15) >> 4, nq = nb * (nb + 1) / 2;
+    if (t < kSyW * NS) {
+        int q = t, J = 0, v = -1;
+        if (q < nq) {
+            while (q >= nb - J) {
+                q -= nb - J;
+                ++J;
+            }
+            v = (J + q) | (J << 8);
+        }
+        blk[t] = v;
+    }
+    const int c = blockIdx.x;
+    const int64_t i0 = int64_t(c) * chunk, i1 = std::min<int64_t>(N, i0 + chunk);
+    constexpr int PE = kSP * 256 / (64 * kSyW);  // panel elements per thread
+    double ra[PE], rw = 0.0;
+    auto load_panel = [&](int64_t ib0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < PE; ++m) {
+            const int e = t + 64 * kSyW * m, col = e / kSP, r = e % kSP;
+            const int64_t i = ib0 + r;
+            ra[m] = (col < k && i < i1) ? Z[int64_t(col) * N + i] : 0.0;
+        }
+        if (t < kSP) {
+            const int64_t i = ib0 + t;
+            rw = (i < i1) ? (theta ? 1.0 / theta[i] : 1.0) : 0.0;
+        }
+    };
+    d4 acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // the block table
+    int cI[NS], cJ[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int v = __builtin_amdgcn_readfirstlane(blk[s * kSyW + w]);
+        cI[s] = v < 0 ? -1 : (v & 255);
+        cJ[s] = v < 0 ? -1 : (v >> 8);
+    }
+    if (i0 < i1) load_panel(i0);
+    int buf = 0;
+    for (int64_t ib0 = i0; ib0 < i1; ib0 += kSP, buf ^= 1) {
+#pragma unroll
+        for (int m = 0; m < PE; ++m) {
+            const int e = t + 64 * kSyW * m;
+            pz[buf][e % kSP][e / kSP] = ra[m];
+        }
+        if (t < kSP) wt[buf][t] = rw;
+        __syncthreads();
+        if (ib0 + kSP < i1) load_panel(ib0 + kSP);
+#pragma unroll
+        for (int s4 = 0; s4 < kSP / 4; ++s4) {
+            const int r = 4 * s4 + (l >> 4);
+            const double wr = wt[buf][r];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                if (cI[s] >= 0) {
+                    const double a = pz[buf][r][16 * cI[s] + (l & 15)] * wr;
+                    const double b = pz[buf][r][16 * cJ[s] + (l & 15)];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (cI[s] < 0) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ia = 16 * cI[s] + (l >> 4) + 4 * e, ib = 16 * cJ[s] + (l & 15);
+            if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc[s][e];
+        }
+    }
+}
+
 // M[a][b] = M[b][a] = diag [a == b] + sum_c part[c][a][b] for a >= b (chunks in
 // order); threads run along rows of the lower triangle, so the partial sums are
 // read contiguously
@@ -373,12 +484,54 @@ __global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, 
     M[int64_t(b) * k + a] = s;
 }
 
+// Two-level form of k_syrk_fold for the capacitance matrix: group g of
+// gridDim.y adds its run of consecutive chunks (in chunk order) for every
+// lower-triangle entry, then k_syrk_fold_fin adds the group sums in group order.
+// Spreading the long sums over groups gives their loads gridDim.y times more
+// blocks than one thread per entry does.
+constexpr int kFoldGroups = 16;
+__global__ void k_syrk_fold_grp(const double* __restrict__ part, int nchunk, int k, double* __restrict__ gsum) {
+    const int64_t kk = int64_t(k) * k;
+    const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (e >= kk || e % k > e / k) return;
+    const int g = blockIdx.y, ng = gridDim.y;
+    const int c0 = int(int64_t(nchunk) * g / ng), c1 = int(int64_t(nchunk) * (g + 1) / ng);
+    double s = 0.0;
+#pragma unroll 8
+    for (int c = c0; c < c1; ++c) s += part[c * kk + e];
+    gsum[g * kk + e] = s;
+}
+
+__global__ void k_syrk_fold_fin(const double* __restrict__ gsum, int ng, int k, double diag,
+                                double* __restrict__ M, int ldm) {
+    const int64_t kk = int64_t(k) * k;
+    const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
+    if (e >= kk) return;
+    const int a = int(e / k), b = int(e % k);
+    if (b > a) return;
+    double s = (a == b) ? diag : 0.0;
+    for (int g = 0; g < ng; ++g) s += gsum[g * kk + e];
+    M[int64_t(a) * ldm + b] = s;
+    M[int64_t(b) * ldm + a] = s;
+}
+
 // row chunks of k_syrk_mfma: enough blocks to fill the GPU, partials within 256 MB,
 // at least 256 rows per chunk (the fold reads nchunk k x k partials), chunks a
 // whole number of panels
 void syrk_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
     const int ns = (k + kST - 1) / kST, pairs = ns * (ns + 1) / 2;
     int64_t want = std::max<int64_t>(1, (1024 + pairs - 1) / pairs);
+    want = std::min<int64_t>(want, std::max<int64_t>(1, (int64_t(256) << 20) / (int64_t(k) * k * 8)));
+    want = std::min<int64_t>(want, std::max<int64_t>(1, N / 256));
+    chunk = (N + want - 1) / want;
+    chunk = (chunk + kSP - 1) / kSP * kSP;
+    nchunk = int((N + chunk - 1) / chunk);
+}
+
+// row chunks of k_syrk_tri (k <= 256): one block per compute unit, at least
+// 256 rows per chunk, partials within 256 MB, chunks a whole number of panels
+void syrk_tri_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
+    int64_t want = 256;
     want = std::min<int64_t>(want, std::max<int64_t>(1, (int64_t(256) << 20) / (int64_t(k) * k * 8)));
     want = std::min<int64_t>(want, std::max<int64_t>(1, N / 256));
     chunk = (N + want - 1) / want;
@@ -572,6 +725,7 @@ __global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double*
     const int tid = threadIdx.x;
     for (int i = tid; i < k; i += blockDim.x) {
         double v = 0.0;
+#pragma unroll 8
         for (int g = 0; g < nseg; ++g) v += wpart[int64_t(g) * k + i];
         sx[i] = v;
     }
@@ -628,6 +782,310 @@ __global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double*
         __syncthreads();
     }
     for (int i = tid; i < k; i += blockDim.x) t[i] = sx[i];
+}
+
+// Capacitance factor and solves for k <= kRegCholK. k_chol_reg leaves L in
+// the lower triangle of M and L^T in its strict upper triangle (M[i][j] =
+// L[max(i, j)][min(i, j)]), so that k_chol_solve_w reads only rows of M.
+constexpr int kRegCholK = 256;
+constexpr int kRegWaves = 8;   // slots per wavefront: 12 up to k = 208 (91 blocks), 17 up to k = 256 (136)
+
+// In-place Cholesky, one block of kRegWaves wavefronts, blocked by 16 x 16. The
+// nb (nb + 1) / 2 lower blocks stay in registers in the FP64 matrix-core result
+// layout (lane l, element e: row l / 16 + 4 e, column l % 16); block q, counted
+// down the block columns, belongs to wavefront q % kRegWaves, slot q / kRegWaves. The matrix
+// is padded to whole blocks with the identity. For block column p: (a) its
+// owners copy it to LDS; (b) wavefront 0 factors the diagonal block (lane r
+// holds row r, shuffles broadcast the pivots); (c) one thread per row below it
+// solves x L_pp^T = m; (d) the finished column goes to global memory in both
+// triangles, and every wavefront subtracts P_I P_J^T from its blocks (I, J),
+// J > p, on the matrix cores. The LDS copy is double-buffered: the barriers of
+// (a)-(c) of column p + 1 separate (d) of column p - 1 from the reuse of its
+// buffer. status[0] = 0 ok, 1 = non-positive pivot.
+template <int NS>
+__global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict__ M, int k, int ldm,
+                                                              int* __restrict__ status) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double pan[2][16][16][17];  // [buffer][block row][row][column]
+    __shared__ double rdiag[16];
+    __shared__ int blk[kRegWaves * NS];    // block q: I | J << 8 (-1: none)
+    __shared__ int bad;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int nb = (k + 15) >> 4, nq = nb * (nb + 1) / 2;
+    if (t == 0) bad = 0;
+    if (t < kRegWaves * NS) {
+        int q = t, J = 0, v = -1;
+        if (q < nq) {
+            while (q >= nb - J) {
+                q -= nb - J;
+                ++J;
+            }
+            v = (J + q) | (J << 8);
+        }
+        blk[t] = v;
+    }
+    __syncthreads();
+    // block coordinates of slot s of this wavefront (wave-uniform)
+    auto coords = [&](int s, int& I, int& J) __attribute__((always_inline)) {
+        const int v = __builtin_amdgcn_readfirstlane(blk[s * kRegWaves + w]);
+        I = v < 0 ? -1 : (v & 255);
+        J = v < 0 ? -1 : (v >> 8);
+    };
+    d4 acc[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        int I, J;
+        coords(s, I, J);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            double v = 0.0;
+            if (I >= 0) {
+                const int row = 16 * I + (l >> 4) + 4 * e, col = 16 * J + (l & 15);
+                v = (row < k && col < k) ? M[int64_t(row) * ldm + col] : (row == col ? 1.0 : 0.0);
+            }
+            acc[s][e] = v;
+        }
+    }
+    for (int p = 0; p < nb; ++p) {
+        double (*P)[16][17] = pan[p & 1];
+        // (a)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int I, J;
+            coords(s, I, J);
+            if (J == p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) P[I][(l >> 4) + 4 * e][l & 15] = acc[s][e];
+        }
+        __syncthreads();
+        // (b)
+        if (w == 0) {
+            double d[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) d[c] = (l < 16 && c <= l) ? P[p][l][c] : 0.0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                double dcc = __shfl(d[c], c, 64);
+                if (!(dcc > 0.0)) {
+                    if (l == 0) bad = 1;
+                    dcc = 1e-300;
+                }
+                dcc = sqrt(dcc);
+                const double rdc = 1.0 / dcc;
+                if (l == c) d[c] = dcc;
+                else if (l > c) d[c] *= rdc;
+#pragma unroll
+                for (int cc = c + 1; cc < 16; ++cc) {
+                    const double lcc = __shfl(d[c], cc, 64);  // L[cc][c], from lane cc
+                    if (cc <= l && l < 16) d[cc] -= d[c] * lcc;
+                }
+            }
+            if (l < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) P[p][l][c] = c <= l ? d[c] : 0.0;
+                rdiag[l] = 1.0 / d[l];
+            }
+        }
+        __syncthreads();
+        // (c)
+        if (t < (nb - 1 - p) * 16) {
+            const int I = p + 1 + (t >> 4), r = t & 15;
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = P[I][r][c];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                double v = x[c];
+#pragma unroll
+                for (int q = 0; q < c; ++q) v -= x[q] * P[p][c][q];
+                x[c] = v * rdiag[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) P[I][r][c] = x[c];
+        }
+        __syncthreads();
+        // (d) the finished column, then the trailing update
+        for (int idx = t; idx < (nb - p) * 256; idx += 64 * kRegWaves) {
+            const int I = p + (idx >> 8), r = (idx >> 4) & 15, c = idx & 15;
+            const int row = 16 * I + r, col = 16 * p + c;
+            if (row < k && col < k && (I > p || c <= r)) {
+                const double v = P[I][r][c];
+                M[int64_t(row) * ldm + col] = v;
+                M[int64_t(col) * ldm + row] = v;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            int I, J;
+            coords(s, I, J);
+            if (J > p) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) {
+                    const double a = -P[I][l & 15][4 * s4 + (l >> 4)];
+                    const double b = P[J][l & 15][4 * s4 + (l >> 4)];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (t == 0) status[0] = bad;
+}
+
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// t = (L L^T)^{-1} w for k <= kRegCholK with the factor as k_chol_reg leaves
+// it (row stride ldm, a multiple of 16), w the sum of the nseg partial vectors
+// wpart[g][:] (segments in order). One wavefront; lane l holds entries l + 64 r
+// (r = 0..3). Forward sweep, step j: lane j % 64 finishes z_j, a lane broadcast
+// hands it to every lane, and each lane subtracts L[i][j] z_j from its entries
+// i > j, read from row j of M right of the diagonal (L^T's row j). The backward
+// sweep runs the same way down the rows, reading row j left of the diagonal
+// (L's row j). Rows stream into an LDS ring by direct 16-byte loads kSwAhead
+// rows ahead of the step that needs them (two 1 KB pieces per row, rows past the
+// end going to a spare slot so that every step issues the same two), and the
+// steps go in groups of four rows, which one LDS read block serves.
+constexpr int kSwRing = 32, kSwAhead = 24, kSwG = 4;
+static_assert(2 * (kSwAhead + kSwG) <= 63, "loads in flight must fit the vector memory counter");
+
+__device__ __forceinline__ void dma_row(const double* __restrict__ Lm, int k, int ldm, int j, double* slot, int l) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = 128 * h + 2 * l;
+        const double* src = Lm + int64_t(j) * ldm + (e < k ? e : 0);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(slot + 128 * h), 16, 0, 0);
+    }
+}
+
+// the lane's four entries of the kSwG rows in ring slots s0 .. s0 + 3 (mod
+// kSwRing), read and waited for in one block
+__device__ __forceinline__ void ring_read(const double* ring, int s0, int l, double (&v)[kSwG][4]) {
+    const unsigned a0 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 0) % kSwRing) * 256 + l)) ;
+    const unsigned a1 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 1) % kSwRing) * 256 + l));
+    const unsigned a2 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 2) % kSwRing) * 256 + l));
+    const unsigned a3 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 3) % kSwRing) * 256 + l));
+    asm volatile(
+        "ds_read_b64 %0, %16\n\tds_read_b64 %1, %16 offset:512\n\t"
+        "ds_read_b64 %2, %16 offset:1024\n\tds_read_b64 %3, %16 offset:1536\n\t"
+        "ds_read_b64 %4, %17\n\tds_read_b64 %5, %17 offset:512\n\t"
+        "ds_read_b64 %6, %17 offset:1024\n\tds_read_b64 %7, %17 offset:1536\n\t"
+        "ds_read_b64 %8, %18\n\tds_read_b64 %9, %18 offset:512\n\t"
+        "ds_read_b64 %10, %18 offset:1024\n\tds_read_b64 %11, %18 offset:1536\n\t"
+        "ds_read_b64 %12, %19\n\tds_read_b64 %13, %19 offset:512\n\t"
+        "ds_read_b64 %14, %19 offset:1024\n\tds_read_b64 %15, %19 offset:1536\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]), "=&v"(v[1][1]),
+          "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]), "=&v"(v[2][2]), "=&v"(v[2][3]),
+          "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]), "=&v"(v[3][3])
+        : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
+        : "memory");
+}
+
+// kSwG steps on rows j of entry slot RJ (row order as in v); entries whose
+// value must not change read as zero (masked by the caller's predicate)
+template <int RJ, bool FWD>
+__device__ __forceinline__ void sweep_group(double (&b)[4], const double (&rd)[4], const double (&v)[kSwG][4],
+                                            const int (&rows)[kSwG], int k, int l) {
+    const int lo = 64 * RJ;
+#pragma unroll
+    for (int q = 0; q < kSwG; ++q) {
+        const int j = rows[q];
+        if (j < k) {
+            const double xj = lane_bcast(b[RJ] * rd[RJ], j - lo);
+            if (l == j - lo) b[RJ] = xj;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = l + 64 * r;
+                if (FWD ? (r >= RJ && i > j && i < k) : (r <= RJ && i < j)) b[r] -= v[q][r] * xj;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(64) void k_chol_solve_w(const double* __restrict__ Lm, int k, int ldm,
+                                                      const double* __restrict__ wpart, int nseg,
+                                                      double* __restrict__ t) {
+    __shared__ __attribute__((aligned(16))) double ring[(kSwRing + 1) * 256];
+    double* spare = ring + kSwRing * 256;
+    const int l = threadIdx.x;
+    double b[4], rd[4];
+    // w: the partial vectors added in segment order, the loads of eight
+    // segments issued together (a plain loop waits for every load in turn)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = l + 64 * r;
+        b[r] = 0.0;
+        rd[r] = 1.0 / (i < k ? Lm[int64_t(i) * ldm + i] : 1.0);
+    }
+    for (int g = 0; g < nseg; g += 8) {  // segments past nseg add exact zeros
+        double x[8][4];
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = l + 64 * r;
+                x[q][r] = (i < k && g + q < nseg) ? wpart[int64_t(g + q) * k + i] : 0.0;
+            }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) b[r] += x[q][r];
+    }
+    // stream position p of a sweep holds row row_of(p): groups of kSwG aligned
+    // rows (4 g .. 4 g + 3), ascending for the forward sweep and descending
+    // (groups and rows within them) for the backward one; rows >= k are spare
+    const int ng = (k + kSwG - 1) / kSwG, npos = ng * kSwG;
+#pragma unroll
+    for (int sw = 0; sw < 2; ++sw) {
+        const bool fwd = sw == 0;
+        auto row_of = [&](int p) __attribute__((always_inline)) {
+            return fwd ? p : kSwG * (ng - 1 - p / kSwG) + (kSwG - 1 - p % kSwG);
+        };
+        auto issue = [&](int p) __attribute__((always_inline)) {
+            const int j = p < npos ? row_of(p) : k;
+            if (j < k)
+                dma_row(Lm, k, ldm, j, ring + (p % kSwRing) * 256, l);
+            else
+                dma_row(Lm, k, ldm, 0, spare, l);
+        };
+        for (int p = 0; p < kSwAhead; ++p) issue(p);
+        for (int p0 = 0; p0 < npos; p0 += kSwG) {
+#pragma unroll
+            for (int q = 0; q < kSwG; ++q) issue(p0 + kSwAhead + q);
+            // the group's rows have landed once at most 2 kSwAhead pieces are outstanding
+            __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * kSwAhead) & 15) | (((2 * kSwAhead) >> 4) << 14));
+            double v[kSwG][4];
+            ring_read(ring, p0 % kSwRing, l, v);
+            int rows[kSwG];
+#pragma unroll
+            for (int q = 0; q < kSwG; ++q) rows[q] = row_of(p0 + q);
+            const int rj = (fwd ? rows[0] : rows[kSwG - 1]) >> 6;  // the group's lowest row
+            if (fwd) {
+                switch (rj) {
+                    case 0: sweep_group<0, true>(b, rd, v, rows, k, l); break;
+                    case 1: sweep_group<1, true>(b, rd, v, rows, k, l); break;
+                    case 2: sweep_group<2, true>(b, rd, v, rows, k, l); break;
+                    default: sweep_group<3, true>(b, rd, v, rows, k, l); break;
+                }
+            } else {
+                switch (rj) {
+                    case 0: sweep_group<0, false>(b, rd, v, rows, k, l); break;
+                    case 1: sweep_group<1, false>(b, rd, v, rows, k, l); break;
+                    case 2: sweep_group<2, false>(b, rd, v, rows, k, l); break;
+                    default: sweep_group<3, false>(b, rd, v, rows, k, l); break;
+                }
+            }
+        }
+        // the sweep's trailing spare loads land before the ring is reused
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (l + 64 * r < k) t[l + 64 * r] = b[r];
 }
 
 // ------------------------------------------------------------------ IPM vector kernels
@@ -703,10 +1161,13 @@ __global__ void k_step_partial(const double* __restrict__ a, const double* __res
 }
 
 __global__ void k_min_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-    if (threadIdx.x != 0) return;
+    // lane j takes partials j, j + 64, ...; the minimum does not depend on the order
     double m = INFINITY;
-    for (int b = 0; b < nb; ++b) m = fmin(m, part[b]);
-    out[0] = m;
+#pragma unroll 8
+    for (int b = threadIdx.x; b < nb; b += 64) m = fmin(m, part[b]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmin(m, __shfl_xor(m, o, 64));
+    if (threadIdx.x == 0) out[0] = m;
 }
 
 __global__ void k_step(double* __restrict__ a, const double* __restrict__ da, int64_t N, double s) {
@@ -1138,10 +1599,11 @@ struct Workspace {
     Workspace& operator=(const Workspace&) = delete;
     const double* Z = nullptr;            // N x k column-major low-rank factor Z^T
     const float* Z32 = nullptr;           // its FP32 copy, when the N x k products run in FP32
-    DevBuf<double> M, Mpart, t;           // capacitance (its factor in place), partials, M^{-1} w
+    DevBuf<double> M, Mpart, Mgrp, t;     // capacitance (its factor in place), partials, group sums, M^{-1} w
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
     DevBuf<double> wpart;                 // per-segment partials of Z^T u
+    int ldm = 0;                          // leading dimension of M
     int nchunk = 0;
     int64_t chunk = 0;
     int nseg = 1;
@@ -1157,9 +1619,9 @@ void kmv(Plan& pl, const MatvecHook* hook, const double* x, double* y, hipStream
 }
 
 // A_hat^{-1} applied to r (first N entries); out[N] = r[N] * inv_s[0] (device) when has_last
-void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, const double* r,
-                    const double* inv_s, bool has_last, double* out, hipStream_t st) {
-    const int64_t N = pl.N;
+void woodbury_apply(Workspace& ws, const double* y, const double* th, const double* r, const double* inv_s,
+                    bool has_last, double* out, hipStream_t st) {
+    const int64_t N = ws.N;
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
         const dim3 g(unsigned((ws.k + kGemvCols - 1) / kGemvCols), unsigned(ws.nseg));
@@ -1167,8 +1629,12 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
             hipLaunchKernelGGL(k_gemv_t_seg<float>, g, dim3(kT), 0, st, ws.Z32, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
         else
             hipLaunchKernelGGL(k_gemv_t_seg<double>, g, dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
-        hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k, ws.wpart.p,
-                           ws.nseg, ws.t.p);
+        if (ws.k <= kRegCholK)
+            hipLaunchKernelGGL(k_chol_solve_w, dim3(1), dim3(64), 0, st, ws.M.p, ws.k, ws.ldm, ws.wpart.p, ws.nseg,
+                               ws.t.p);
+        else
+            hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k,
+                               ws.wpart.p, ws.nseg, ws.t.p);
     }
     if (ws.Z32)
         hipLaunchKernelGGL(k_wb_out<float>, dim3(nblk(N + 1)), dim3(kT), 0, st, y, th, r, ws.Z32, N, ws.k, ws.t.p,
@@ -1178,17 +1644,28 @@ void woodbury_apply(Plan& pl, Workspace& ws, const double* y, const double* th, 
                            inv_s, has_last ? 1 : 0, out);
 }
 
-void refresh_capacitance(Plan& pl, Workspace& ws, const double* th, hipStream_t st) {
+void refresh_capacitance(Workspace& ws, const double* th, hipStream_t st) {
     if (ws.k == 0) return;
     const int k = ws.k;
     const int ns = (k + kST - 1) / kST;
     // the FP64 factor (holding the FP32 copy's values when there is one): the
     // 128-column panels of the Gram kernel read whole 128-byte rows in FP64
-    hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0, st,
-                       ws.Z, pl.N, k, th, ws.chunk, ws.Mpart.p);
-    hipLaunchKernelGGL(k_syrk_fold, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mpart.p, ws.nchunk, k, 1.0,
-                       ws.M.p);
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
+    if (k <= kRegCholK)
+        hipLaunchKernelGGL(k <= 208 ? k_syrk_tri<12> : k_syrk_tri<17>, dim3(unsigned(ws.nchunk)), dim3(64 * kSyW), 0,
+                           st, ws.Z, ws.N, k, th, ws.chunk, ws.Mpart.p);
+    else
+        hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0,
+                           st, ws.Z, ws.N, k, th, ws.chunk, ws.Mpart.p);
+    const int ng = std::min(ws.nchunk, kFoldGroups);
+    hipLaunchKernelGGL(k_syrk_fold_grp, dim3(nblk(int64_t(k) * k), unsigned(ng)), dim3(kT), 0, st, ws.Mpart.p,
+                       ws.nchunk, k, ws.Mgrp.p);
+    hipLaunchKernelGGL(k_syrk_fold_fin, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mgrp.p, ng, k, 1.0, ws.M.p,
+                       ws.ldm);
+    if (k <= kRegCholK)
+        hipLaunchKernelGGL(k <= 208 ? k_chol_reg<12> : k_chol_reg<17>, dim3(1), dim3(64 * kRegWaves), 0, st, ws.M.p, k,
+                           ws.ldm, ws.status.p);
+    else
+        hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
     // read back through pinned memory: an asynchronous copy into pageable
     // (here: stack) memory is not guaranteed to have landed when the stream's
     // later work completes
@@ -1201,11 +1678,18 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
     ws.N = N;
     ws.k = k;
     if (k > 0) {
-        ws.M.alloc(size_t(k) * k);
+        // rows of the register-resident factor start on 128-byte boundaries (the
+        // solve streams them into LDS in 16-byte pieces)
+        ws.ldm = k <= kRegCholK ? (k + 15) / 16 * 16 : k;
+        ws.M.alloc(size_t(k) * ws.ldm);
         ws.t.alloc(k);
         ws.status.alloc(1);
-        syrk_chunks(N, k, ws.nchunk, ws.chunk);
+        if (k <= kRegCholK)
+            syrk_tri_chunks(N, k, ws.nchunk, ws.chunk);
+        else
+            syrk_chunks(N, k, ws.nchunk, ws.chunk);
         ws.Mpart.alloc(size_t(ws.nchunk) * k * k);
+        ws.Mgrp.alloc(size_t(std::min(ws.nchunk, kFoldGroups)) * k * k);
         // segments of Z^T u: about 1024 blocks in all (fewer partial sums for the
         // solve to fold, and still four blocks per compute unit)
         const int64_t ncb = (k + kGemvCols - 1) / kGemvCols;
@@ -1437,6 +1921,33 @@ void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st
 }
 
 }  // namespace
+
+void lowrank_apply(int64_t N, int k, const double* Z, int64_t ldz, const double* theta, const double* y,
+                   const double* r, bool fp32_products, double* out, hipStream_t st) {
+    ANV_CHECK(N >= 1 && k >= 1 && k <= 1024, "need N >= 1 and 1 <= k <= 1024");
+    ANV_CHECK(Z && theta && r && out && ldz >= N, "NULL pointer or ldz < N");
+    DevBuf<double> zc, yc;
+    DevBuf<float> z32;
+    zc.alloc(size_t(N) * k);
+    ANV_HIP(hipMemcpy2DAsync(zc.p, N * sizeof(double), Z, ldz * sizeof(double), N * sizeof(double), k,
+                             hipMemcpyDeviceToDevice, st));
+    if (!y) {
+        yc.alloc(N);
+        hipLaunchKernelGGL(k_fill, dim3(nblk(N)), dim3(kT), 0, st, yc.p, N, 1.0);
+        y = yc.p;
+    }
+    Workspace ws;
+    ws.Z = zc.p;
+    if (fp32_products) {  // as the solver does: both copies hold the FP32-rounded values
+        z32.alloc(size_t(N) * k);
+        hipLaunchKernelGGL(k_narrow, dim3(nblk(int64_t(N) * k)), dim3(kT), 0, st, zc.p, int64_t(N) * k, z32.p);
+        ws.Z32 = z32.p;
+    }
+    setup_factor_storage(ws, N, k);
+    refresh_capacitance(ws, theta, st);  // synchronises the stream
+    woodbury_apply(ws, y, theta, r, nullptr, false, out, st);
+    host_wait(st);                       // the buffers above are released on return
+}
 
 int pivoted_cholesky(Plan& pl, int rank, double err_tol, double* L, int64_t ldl, int64_t* piv, hipStream_t st,
                      const double* uniforms) {
@@ -1784,9 +2295,9 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         double s_last = 1.0;
         const bool prec = o.precond != ANOVA_PRECOND_NONE;  // diag(A_hat, s); without a factor A_hat = Theta
         if (prec) {
-            refresh_capacitance(pl, ws, th.p, st);
+            refresh_capacitance(ws, th.p, st);
             if (!gmres) {
-                woodbury_apply(pl, ws, labels, th.p, labels, nullptr, false, ytmp.p, st);
+                woodbury_apply(ws, labels, th.p, labels, nullptr, false, ytmp.p, st);
                 s_last = red.dot(labels, ytmp.p, N, st);
                 if (!(s_last > 0.0)) {
                     status = ANOVA_NUMERICAL;
@@ -1798,7 +2309,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         const double* inv_s = &ks->inv_s;  // device address
         auto precond = [&](const double* r, double* out) {
             if (prec)
-                woodbury_apply(pl, ws, labels, th.p, r, inv_s, true, out, st);
+                woodbury_apply(ws, labels, th.p, r, inv_s, true, out, st);
             else
                 hipLaunchKernelGGL(k_copy, dim3(nblk(n1)), dim3(kT), 0, st, r, out, n1);
         };
@@ -1825,7 +2336,7 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
             auto pinv_head = [&](const double* v) -> const double* {
                 const double* z = v;
                 if (prec) {
-                    woodbury_apply(pl, ws, labels, th.p, v, nullptr, false, gz.p, st);
+                    woodbury_apply(ws, labels, th.p, v, nullptr, false, gz.p, st);
                     z = gz.p;
                 }
                 red.dot_dev(labels, z, N, ytz_d, st);

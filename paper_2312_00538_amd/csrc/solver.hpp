@@ -31,6 +31,12 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
               double* lambda, anova_ipm_stats* stats, hipStream_t st, const LowRankFactor* factor = nullptr,
               const MatvecHook* hook = nullptr);
 
+// out = (Theta + Y Z Z^T Y)^{-1} r through the capacitance refresh and the
+// Woodbury passes of the IPM's preconditioner (Z: N x k, column j at Z + j*ldz;
+// y NULL = identity); synchronises the stream
+void lowrank_apply(int64_t N, int k, const double* Z, int64_t ldz, const double* theta, const double* y,
+                   const double* r, bool fp32_products, double* out, hipStream_t st);
+
 // returns the rank used
 // uniforms: NULL for the greedy rule (Algorithm 2), else one value in [0, 1)
 // per step for randomly pivoted Cholesky
