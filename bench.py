@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--grid-max-ip", type=int, default=200)
     ap.add_argument("--grid-max-kry", type=int, default=300,
                     help="Krylov cap per Newton solve of the grid (the narrowest kernel at C = 1000 needs more than 100)")
+    ap.add_argument("--grid-krylov", choices=["minres", "gmres"], default="gmres",
+                    help="Krylov method of the grid's solves (GMRES converges all 320 within the caps)")
     ap.add_argument("--grid-precision", choices=["fp64", "mixed"], default="fp64",
                     help="precision of the grid's plans (mixed-precision plans stall or break down at C >= 268)")
     ap.add_argument("--serving-rate", type=float, default=2.0)
@@ -232,14 +234,15 @@ def serving(lib, workloads, n, rate, max_active, share):
             "N_max": int(max(r["N"] for r in stream)), "N_median": int(np.median([r["N"] for r in stream]))}
 
 
-def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip, max_kry, precision):
+def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip, max_kry, precision, krylov):
     """Hyperparameter grid over cross-validation folds: 8 sigma x 8 C per fold,
     FP64 (default) or mixed-precision plans, solves of a plan sharing its
     pivoted-Cholesky factor, matvecs of concurrent solves in shared launches."""
     g = workloads.cv_grid(seed=0)
     p = g["problem"]
     folds = min(folds, len(g["folds"]))
-    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0, max_ip=max_ip, max_kry=max_kry)
+    kw = dict(precond=lib.PRECOND_PCHOL, rank=200, mu0=0.0, max_ip=max_ip, max_kry=max_kry,
+              krylov=lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES)
     prec = lib.PREC_FP64 if precision == "fp64" else lib.PREC_MIXED
     t0 = time.perf_counter()
     probs, data = [], []
@@ -260,7 +263,7 @@ def grid(lib, torch, workloads, dev, folds, max_active, ref_solves, max_ip, max_
     out = {"workload": f"cross-validation grid: N=50000, d=15 (5 windows of 3), {folds} of 5 folds (class-balanced "
                        "training parts of 39874..39982 points), sigma 8 log-spaced in 0.25..4, C 8 log-spaced in "
                        f"0.1..1000; {'FP64' if precision == 'fp64' else 'mixed-precision'} plans, pivoted-Cholesky "
-                       "rank 200 shared per plan, automatic initial barrier parameter, at most "
+                       f"rank 200 shared per plan, {krylov.upper()}, automatic initial barrier parameter, at most "
                        f"{max_ip} IPM and {max_kry} Krylov iterations",
            "solves": len(st), "plans": len(probs), "plan_s": t1 - t0, "wall_s": t2 - t1,
            "solves_per_s": len(st) / (t2 - t1), "status_counts": status,
@@ -524,7 +527,7 @@ def main():
             progress("serving, one at a time done")
     if a.grid_folds > 0:
         out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves,
-                           a.grid_max_ip, a.grid_max_kry, a.grid_precision)
+                           a.grid_max_ip, a.grid_max_kry, a.grid_precision, a.grid_krylov)
         progress(f"grid: {out['grid']['solves_per_s']:.2f} solves/s, {out['grid']['converged']} converged")
     if not a.no_cpu_baseline:
         rec, rows, ref = cpu_baseline(p, a.cpu_seconds)

@@ -1013,7 +1013,7 @@ __global__ __launch_bounds__(64) void k_chol_solve_w(const double* __restrict__ 
     double* spare = ring + kSwRing * 256;
     const int l = threadIdx.x;
     double b[4], rd[4];
-    // w: the partial vectors added in segment order, the loads of eight
+    // w: the partial vectors added in segment order, the loads of sixteen
     // segments issued together (a plain loop waits for every load in turn)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1021,17 +1021,17 @@ __global__ __launch_bounds__(64) void k_chol_solve_w(const double* __restrict__ 
         b[r] = 0.0;
         rd[r] = 1.0 / (i < k ? Lm[int64_t(i) * ldm + i] : 1.0);
     }
-    for (int g = 0; g < nseg; g += 8) {  // segments past nseg add exact zeros
-        double x[8][4];
+    for (int g = 0; g < nseg; g += 16) {  // segments past nseg add exact zeros
+        double x[16][4];
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 16; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = l + 64 * r;
                 x[q][r] = (i < k && g + q < nseg) ? wpart[int64_t(g + q) * k + i] : 0.0;
             }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
+        for (int q = 0; q < 16; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) b[r] += x[q][r];
     }
