@@ -79,6 +79,10 @@ def parse():
                     help="requests of the Poisson serving stream (0 = skip)")
     ap.add_argument("--serving-reference-requests", type=int, default=100,
                     help="requests of the same stream served one at a time (0 = skip)")
+    ap.add_argument("--serving-krylov", choices=["minres", "gmres"], default="gmres")
+    ap.add_argument("--serving-max-kry", type=int, default=300)
+    ap.add_argument("--serving-max-ip", type=int, default=400,
+                    help="IPM iteration cap of the served solves (Algorithm 1 needs more iterations as N grows)")
     ap.add_argument("--save-alpha", default=None,
                     help="write the first full-ipm solve's alpha and lambda to this .npz file")
     ap.add_argument("--grid-max-ip", type=int, default=200)
@@ -190,7 +194,7 @@ def ipm_latency(lib, torch, dev, make, n, precond, rank, label, krylov=0, oversa
             "krylov": ("minres", "gmres")[krylov], "precision": "fp64", "oversampling": oversample}
 
 
-def serving(lib, workloads, n, rate, max_active, share):
+def serving(lib, workloads, n, rate, max_active, share, krylov="minres", max_kry=100, max_ip=200):
     """Replays a Poisson stream of training requests (arrival times from the
     stream, inputs generated beforehand) against a request server; latency is
     submit -> result on the host, as the server measures it."""
@@ -207,7 +211,8 @@ def serving(lib, workloads, n, rate, max_active, share):
             delay = r["arrival"] - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            tickets[i] = srv.submit(p.X, p.labels, p.windows, p.sigma, p.C, mu0=0.0, max_ip=200)
+            tickets[i] = srv.submit(p.X, p.labels, p.windows, p.sigma, p.C, mu0=0.0, max_ip=max_ip, max_kry=max_kry,
+                                    krylov=lib.KRYLOV_GMRES if krylov == "gmres" else lib.KRYLOV_MINRES)
 
     th = threading.Thread(target=submitter)
     th.start()
@@ -215,19 +220,30 @@ def serving(lib, workloads, n, rate, max_active, share):
     for i in range(n):
         while tickets[i] is None:
             time.sleep(0.001)
-        res.append(srv.wait(tickets[i])[1])
+        try:
+            res.append(srv.wait(tickets[i])[1])
+        except lib.AnovaError as e:        # a request the server rejects (reported at wait)
+            res.append({"status": e.status, "latency_ms": float("nan"), "queue_ms": float("nan")})
         if (i + 1) % 20 == 0:
             progress(f"serving (max_active {max_active}): {i + 1} of {n} requests done")
     t_end = time.perf_counter()
     th.join()
     launches, matvecs = srv.counters()
     srv.close()
-    lat = np.array([r["latency_ms"] for r in res])
+    lat = np.array([r["latency_ms"] for r in res if np.isfinite(r["latency_ms"])])
+    status = {}
+    for r in res:
+        status[str(r["status"])] = status.get(str(r["status"]), 0) + 1
     span = t_end - t0 - stream[0]["arrival"]
     return {"requests": n, "rate_per_s": rate, "max_active": max_active, "shared_launches": bool(share),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "queue_p50_ms": float(np.percentile([r["queue_ms"] for r in res], 50)),
             "solves_per_s": n / span, "converged": int(sum(r["status"] == 0 for r in res)),
+            "status_counts": status, "krylov": krylov, "max_kry": max_kry,
+            "not_converged": [{"N": r0["N"], "d": r0["d"], "sigma": r0["sigma"], "C": r0["C"], "status": r["status"],
+                               **({k: r["stats"][k] for k in ("ip_iters", "rel_gap", "mu", "xi_alpha_rel")}
+                                  if "stats" in r else {})}
+                              for r0, r in zip(stream, res) if r["status"] != 0],
             "matvecs_in_shared_launches": matvecs, "shared_launch_count": launches,
             "matvecs_per_shared_launch": matvecs / launches if launches else None,
             "p90_ms": float(np.percentile(lat, 90)), "max_ms": float(lat.max()),
@@ -517,13 +533,15 @@ def main():
     if a.serving_requests > 0:
         label = (f"serving: Poisson stream, rate {a.serving_rate}/s, N log-uniform 5e3..1e6, d uniform 6..60 "
                  "(3-feature windows), sigma log-uniform 0.5..2, C log-uniform 0.1..100; FP64 IPM, "
-                 "pivoted-Cholesky rank 200, automatic initial barrier parameter, at most 200 iterations")
-        cont = serving(lib, workloads, a.serving_requests, a.serving_rate, a.serving_max_active, True)
+                 f"pivoted-Cholesky rank 200, {a.serving_krylov.upper()}, automatic initial barrier parameter, at most "
+                 f"{a.serving_max_ip} IPM and {a.serving_max_kry} Krylov iterations")
+        cont = serving(lib, workloads, a.serving_requests, a.serving_rate, a.serving_max_active, True,
+                       a.serving_krylov, a.serving_max_kry, a.serving_max_ip)
         progress(f"serving, continuous batching: p50 {cont['p50_ms']:.0f} ms p99 {cont['p99_ms']:.0f} ms")
         out["serving"] = {"workload": label, "continuous_batching": cont}
         if a.serving_reference_requests > 0:
             out["serving"]["one_at_a_time"] = serving(lib, workloads, a.serving_reference_requests, a.serving_rate, 1,
-                                                      False)
+                                                      False, a.serving_krylov, a.serving_max_kry, a.serving_max_ip)
             progress("serving, one at a time done")
     if a.grid_folds > 0:
         out["grid"] = grid(lib, torch, workloads, dev, a.grid_folds, a.grid_max_active, a.grid_reference_solves,

@@ -186,7 +186,7 @@ def initial_point(y, C):
 
 
 def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0=0.99995,
-              mu0=1.0, mu_rule="adaptive", record=False, mu_floor=1e-3):
+              mu0=1.0, mu_rule="adaptive", record=False, mu_floor=1e-2):
     """Algorithm 1 (Section 2) with the Newton system (eq. "Newton") solved by a
     dense LU solve of the (N+1) x (N+1) saddle-point matrix.
 
@@ -208,10 +208,11 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
     mu_rule="adaptive" uses sigma_it = 1 - (1 - sigma_bar) * s_prev with s_prev
     the previous step length (s_prev = 1 before the first step), i.e. sigma_bar
     after full steps and little reduction after steps cut short by the box.
-    Either way mu is not reduced below mu_floor * tol: the stop test needs
-    mu <= tol only, and past that point a smaller mu changes the central point
-    by less than the gap tolerance (its duality gap is 2 N mu) while the barrier
-    weights mu / alpha^2 of the rows at a bound grow like 1 / mu.
+    Either way mu is not reduced below mu_floor * tol * (1 + |Pr|) / (2 N), the
+    value whose central point (duality gap 2 N mu) has the relative gap
+    mu_floor * tol: a smaller mu changes nothing the stop test can see, while
+    the barrier weights mu / alpha^2 of the rows at a bound grow like 1 / mu.
+    Pr is the primal objective of the current iterate.
     """
     y = np.asarray(y, dtype=np.float64)
     N = y.shape[0]
@@ -237,7 +238,7 @@ def ipm_dense(K, y, C, tol=1e-6, tol_inf=1e-1, max_ip=100, sigma_bar=0.6, gamma0
             mu = sigma_bar * mu
         else:
             mu = (1.0 - (1.0 - sigma_bar) * s_prev) * mu
-        mu = max(mu, mu_floor * tol)
+        mu = max(mu, mu_floor * tol * (1.0 + abs(Pr)) / (2.0 * N))
         theta = mu * (1.0 / alpha ** 2 + 1.0 / (C - alpha) ** 2)
         r1 = 1.0 - YKY @ alpha + lam * y + mu / alpha - mu / (C - alpha)
         r2 = float(y @ alpha)

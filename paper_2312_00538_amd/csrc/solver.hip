@@ -1544,8 +1544,9 @@ __global__ void k_gaussian(double* __restrict__ G, int64_t N, int k, uint64_t se
 // fraction of the gap tolerance at which the IPM stops (the rest covers the
 // difference between the gap in the fast-summation kernel and in the exact one)
 constexpr double kGapMargin = 0.5;
-// the barrier parameter is not reduced below this fraction of the tolerance
-constexpr double kMuFloor = 1e-3;
+// the barrier parameter is not reduced below the value whose central point has
+// this fraction of the gap tolerance as its relative duality gap
+constexpr double kMuFloor = 1e-2;
 
 // ------------------------------------------------------------------ host helpers
 struct Reducer {
@@ -2283,10 +2284,10 @@ int ipm_solve(Plan& pl, const double* labels, double C, const anova_ipm_opts& o,
         // Section 2: a constant reduction factor, or one that changes every iteration;
         // the default scales the reduction by the previous step length
         mu *= (o.mu_rule == 1) ? o.sigma_bar : 1.0 - (1.0 - o.sigma_bar) * s_prev;
-        // never below kMuFloor * tol: the stop test asks only mu <= tol, a smaller
-        // mu moves the central point by less than the gap tolerance (its duality
-        // gap is 2 N mu), and the barrier weights of rows at a bound grow like 1/mu
-        mu = std::max(mu, kMuFloor * o.tol);
+        // never below the mu whose central point has a relative duality gap of
+        // kMuFloor * tol (its gap is 2 N mu): a smaller mu changes nothing the stop
+        // test can see, and the barrier weights of rows at a bound grow like 1/mu
+        mu = std::max(mu, kMuFloor * o.tol * (1.0 + std::fabs(Pr)) / (2.0 * double(N)));
         hipLaunchKernelGGL(k_theta, dim3(nblk(N)), dim3(kT), 0, st, alpha, N, C, mu, th.p);
         const double r2 = red.dot(labels, alpha, N, st);
         hipLaunchKernelGGL(k_rhs, dim3(nblk(n1)), dim3(kT), 0, st, labels, alpha, kya.p, N, lam, mu, C, r2,
