@@ -490,10 +490,11 @@ __global__ void k_syrk_fold(const double* __restrict__ part, int nchunk, int k, 
 // Spreading the long sums over groups gives their loads gridDim.y times more
 // blocks than one thread per entry does.
 constexpr int kFoldGroups = 16;
-__global__ void k_syrk_fold_grp(const double* __restrict__ part, int nchunk, int k, double* __restrict__ gsum) {
+__global__ void k_syrk_fold_grp(const double* __restrict__ part, int nchunk, int k, double* __restrict__ gsum,
+                                int full = 0) {
     const int64_t kk = int64_t(k) * k;
     const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
-    if (e >= kk || e % k > e / k) return;
+    if (e >= kk || (!full && e % k > e / k)) return;
     const int g = blockIdx.y, ng = gridDim.y;
     const int c0 = int(int64_t(nchunk) * g / ng), c1 = int(int64_t(nchunk) * (g + 1) / ng);
     double s = 0.0;
@@ -502,17 +503,18 @@ __global__ void k_syrk_fold_grp(const double* __restrict__ part, int nchunk, int
     gsum[g * kk + e] = s;
 }
 
+// full != 0: every entry of a general k x k sum (no mirroring)
 __global__ void k_syrk_fold_fin(const double* __restrict__ gsum, int ng, int k, double diag,
-                                double* __restrict__ M, int ldm) {
+                                double* __restrict__ M, int ldm, int full = 0) {
     const int64_t kk = int64_t(k) * k;
     const int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
     if (e >= kk) return;
     const int a = int(e / k), b = int(e % k);
-    if (b > a) return;
+    if (!full && b > a) return;
     double s = (a == b) ? diag : 0.0;
     for (int g = 0; g < ng; ++g) s += gsum[g * kk + e];
     M[int64_t(a) * ldm + b] = s;
-    M[int64_t(b) * ldm + a] = s;
+    if (!full) M[int64_t(b) * ldm + a] = s;
 }
 
 // row chunks of k_syrk_mfma: enough blocks to fill the GPU, partials within 256 MB,
@@ -537,6 +539,131 @@ void syrk_tri_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
     chunk = (N + want - 1) / want;
     chunk = (chunk + kSP - 1) / kSP * kSP;
     nchunk = int((N + chunk - 1) / chunk);
+}
+
+// A^T B for two N x k column-major matrices (k <= 208), partial sums per row
+// chunk: two blocks of 16 wavefronts per chunk (blockIdx.y) share the nb x nb
+// 16 x 16 blocks of the product, dealt evenly over their wavefronts (block
+// q = I nb + J to split q % 2, wavefront (q / 2) % 16, slot q / 32), from 16-row
+// panels of both matrices in LDS. The Nystrom method's Q^T (K Q).
+constexpr int kGrW = 16, kGrSplit = 2, kGrSlots = 6;  // 169 blocks at k = 208
+__global__ __launch_bounds__(64 * kGrW) void k_gram_mfma(const double* __restrict__ A, const double* __restrict__ B,
+                                                         int64_t N, int k, int64_t chunk, double* __restrict__ part) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double pa[kSP][kSyKP], pb[kSP][kSyKP];
+    __shared__ int blk[kGrW * kGrSlots];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int nb = (k + 15) >> 4, nq = nb * nb;
+    if (t < kGrW * kGrSlots) {
+        const int q = t * kGrSplit + int(blockIdx.y);
+        blk[t] = q < nq ? (q / nb) | ((q % nb) << 8) : -1;
+    }
+    const int c = blockIdx.x;
+    const int64_t i0 = int64_t(c) * chunk, i1 = std::min<int64_t>(N, i0 + chunk);
+    constexpr int PE = kSP * 256 / (64 * kGrW);  // panel elements per thread and matrix
+    double ra[PE], rb[PE];
+    auto load_panel = [&](int64_t ib0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int m = 0; m < PE; ++m) {
+            const int e = t + 64 * kGrW * m, col = e / kSP, r = e % kSP;
+            const int64_t i = ib0 + r;
+            const bool ok = col < k && i < i1;
+            ra[m] = ok ? A[int64_t(col) * N + i] : 0.0;
+            rb[m] = ok ? B[int64_t(col) * N + i] : 0.0;
+        }
+    };
+    d4 acc[kGrSlots];
+#pragma unroll
+    for (int s = 0; s < kGrSlots; ++s) acc[s] = d4{0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // the block table
+    int cI[kGrSlots], cJ[kGrSlots];
+#pragma unroll
+    for (int s = 0; s < kGrSlots; ++s) {
+        const int v = __builtin_amdgcn_readfirstlane(blk[s * kGrW + w]);
+        cI[s] = v < 0 ? -1 : (v & 255);
+        cJ[s] = v < 0 ? -1 : (v >> 8);
+    }
+    if (i0 < i1) load_panel(i0);
+    for (int64_t ib0 = i0; ib0 < i1; ib0 += kSP) {
+#pragma unroll
+        for (int m = 0; m < PE; ++m) {
+            const int e = t + 64 * kGrW * m;
+            pa[e % kSP][e / kSP] = ra[m];
+            pb[e % kSP][e / kSP] = rb[m];
+        }
+        __syncthreads();
+        if (ib0 + kSP < i1) load_panel(ib0 + kSP);
+#pragma unroll
+        for (int s4 = 0; s4 < kSP / 4; ++s4) {
+            const int r = 4 * s4 + (l >> 4);
+#pragma unroll
+            for (int s = 0; s < kGrSlots; ++s) {
+                if (cI[s] >= 0) {
+                    const double a = pa[r][16 * cI[s] + (l & 15)];
+                    const double b = pb[r][16 * cJ[s] + (l & 15)];
+                    acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[s], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // before the panels are overwritten
+    }
+#pragma unroll
+    for (int s = 0; s < kGrSlots; ++s) {
+        if (cI[s] < 0) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int ia = 16 * cI[s] + (l >> 4) + 4 * e, ib = 16 * cJ[s] + (l & 15);
+            if (ia < k && ib < k) part[(int64_t(c) * k + ia) * k + ib] = acc[s][e];
+        }
+    }
+}
+
+// out = Y T for Y: N x k column-major, T: k x kc row-major, out: N x kc
+// column-major (kc <= 208): a block of 16 wavefronts takes 256 rows, each
+// wavefront 16 rows and all column blocks, on the matrix cores; 16-row pieces of
+// T are staged in LDS in turn while Y streams through once.
+constexpr int kGmW = 16, kGmCB = 13;  // column blocks of 16: kc <= 208
+constexpr int kGmTP = 16 * kGmCB + 4;  // staged row stride of T
+__global__ __launch_bounds__(64 * kGmW) void k_gemm_nk_mfma(const double* __restrict__ Y, int64_t N, int k,
+                                                            const double* __restrict__ T, int kc,
+                                                            double* __restrict__ out) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    __shared__ double tp[16][kGmTP];
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    const int64_t row0 = int64_t(blockIdx.x) * (16 * kGmW) + 16 * w;
+    const int64_t ri = row0 + (l & 15);
+    d4 acc[kGmCB];
+#pragma unroll
+    for (int cb = 0; cb < kGmCB; ++cb) acc[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < k; m0 += 16) {
+        for (int e = t; e < 16 * 16 * kGmCB; e += 64 * kGmW) {
+            const int mr = e / (16 * kGmCB), j = e % (16 * kGmCB);
+            tp[mr][j] = (m0 + mr < k && j < kc) ? T[int64_t(m0 + mr) * kc + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int mr = 4 * s4 + (l >> 4), m = m0 + mr;
+            const double a = (m < k && ri < N) ? Y[int64_t(m) * N + ri] : 0.0;
+#pragma unroll
+            for (int cb = 0; cb < kGmCB; ++cb) {
+                if (16 * cb < kc) {
+                    const double b = tp[mr][16 * cb + (l & 15)];
+                    acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();  // before the next piece of T is staged
+    }
+#pragma unroll
+    for (int cb = 0; cb < kGmCB; ++cb) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t row = row0 + (l >> 4) + 4 * e;
+            const int col = 16 * cb + (l & 15);
+            if (row < N && col < kc) out[int64_t(col) * N + row] = acc[cb][e];
+        }
+    }
 }
 
 // w_part[s][j] = sum over rows of segment s of Z[j N + i] u[i]: one block per
@@ -1806,21 +1933,51 @@ std::vector<double> inv_lower_transposed(const std::vector<double>& L, int k) {
     return T;
 }
 
+// out = Y T (Y: N x k column-major, T: k x kc row-major, out: N x kc column-major)
+void gemm_nk(const double* Y, int64_t N, int k, const double* T, int kc, double* out, hipStream_t st) {
+    if (k <= 16 * kGmCB && kc <= 16 * kGmCB)
+        hipLaunchKernelGGL(k_gemm_nk_mfma, dim3(unsigned((N + 16 * kGmW - 1) / (16 * kGmW))), dim3(64 * kGmW), 0, st, Y,
+                           N, k, T, kc, out);
+    else
+        hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((kc + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
+                           Y, N, k, T, kc, out);
+}
+
 struct Gram {
-    DevBuf<double> part, M;
-    int nchunk = 1, nchunk_s = 1;
-    int64_t chunk = 1, chunk_s = 1;
+    DevBuf<double> part, M, gsum;
+    int nchunk = 1, nchunk_s = 1, nchunk_t = 1;
+    int64_t chunk = 1, chunk_s = 1, chunk_t = 1;
     void setup(int64_t N, int k) {
         chunk = 8192;
         nchunk = int(std::min<int64_t>(256, (N + chunk - 1) / chunk));
         chunk = (N + nchunk - 1) / nchunk;
         syrk_chunks(N, k, nchunk_s, chunk_s);
-        part.alloc(size_t(std::max(nchunk, nchunk_s)) * k * k);
+        syrk_tri_chunks(N, k, nchunk_t, chunk_t);
+        part.alloc(size_t(std::max(std::max(nchunk, nchunk_s), nchunk_t)) * k * k);
+        gsum.alloc(size_t(kFoldGroups) * k * k);
         M.alloc(size_t(k) * k);
     }
-    // host copy of A^T B (k x k, row-major); A == B goes to the matrix cores
+    // the chunk partials of the balanced kernels, folded in order (full: a
+    // general product; else the lower triangle, mirrored)
+    void fold_tri(int k, bool full, hipStream_t st) {
+        const int ng = std::min(nchunk_t, kFoldGroups);
+        hipLaunchKernelGGL(k_syrk_fold_grp, dim3(nblk(int64_t(k) * k), unsigned(ng)), dim3(kT), 0, st, part.p,
+                           nchunk_t, k, gsum.p, full ? 1 : 0);
+        hipLaunchKernelGGL(k_syrk_fold_fin, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, gsum.p, ng, k, 0.0, M.p, k,
+                           full ? 1 : 0);
+    }
+    // host copy of A^T B (k x k, row-major), on the matrix cores for k <= 208
+    // (A == B: k <= 256)
     std::vector<double> run(const double* A, const double* B, int64_t N, int k, hipStream_t st) {
-        if (A == B) {
+        if (A == B && k <= kRegCholK) {
+            hipLaunchKernelGGL(k <= 208 ? k_syrk_tri<12> : k_syrk_tri<17>, dim3(unsigned(nchunk_t)), dim3(64 * kSyW), 0,
+                               st, A, N, k, (const double*)nullptr, chunk_t, part.p);
+            fold_tri(k, false, st);
+        } else if (A != B && k <= 208) {
+            hipLaunchKernelGGL(k_gram_mfma, dim3(unsigned(nchunk_t), kGrSplit), dim3(64 * kGrW), 0, st, A, B, N, k,
+                               chunk_t, part.p);
+            fold_tri(k, true, st);
+        } else if (A == B) {
             const int ns = (k + kST - 1) / kST;
             hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(nchunk_s)), dim3(256), 0, st, A,
                                N, k, (const double*)nullptr, chunk_s, part.p);
@@ -1865,8 +2022,7 @@ void orthonormalize(DevBuf<double>& Y, DevBuf<double>& tmp, int64_t N, int k, hi
         }
         std::vector<double> Th = inv_lower_transposed(L, k);
         ANV_HIP(hipMemcpyAsync(T.p, Th.data(), Th.size() * sizeof(double), hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((k + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
-                           Y.p, N, k, T.p, k, tmp.p);
+        gemm_nk(Y.p, N, k, T.p, k, tmp.p, st);
         std::swap(Y.p, tmp.p);
     }
     host_wait(st);
@@ -1915,8 +2071,7 @@ void nystrom_core(Plan& pl, DevBuf<double>& Y, int k, double* Zt, hipStream_t st
     DevBuf<double> Td;
     Td.alloc(size_t(k) * k);
     ANV_HIP(hipMemcpyAsync(Td.p, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gemm_nk, dim3(nblk(N), unsigned((k + 15) / 16)), dim3(kT), k * 16 * sizeof(double), st,
-                       tmp.p, N, k, Td.p, k, Zt);
+    gemm_nk(tmp.p, N, k, Td.p, k, Zt, st);
     ANV_HIP(hipGetLastError());
     host_wait(st);
 }
