@@ -911,13 +911,25 @@ __global__ __launch_bounds__(256) void k_fold_cols_b(const WinDev* __restrict__ 
     const int2 rr = fold[f];
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     if (part < parts) {
-        for (int s = rr.x + part; s < rr.y; s += parts) {
-            const v4<T> v = *reinterpret_cast<const v4<T>*>(slab + (sbase[s] + int64_t(L) * lanes + pos) * RB + 4 * q4);
+        auto at = [&](int s) __attribute__((always_inline)) {
+            return *reinterpret_cast<const v4<T>*>(slab + (sbase[s] + int64_t(L) * lanes + pos) * RB + 4 * q4);
+        };
+        auto add = [&](const v4<T>& v) __attribute__((always_inline)) {
             s0 += v[0];
             s1 += v[1];
             s2 += v[2];
             s3 += v[3];
+        };
+        int s = rr.x + part;
+        // four items' loads in flight at a time, added in item order
+        for (; s + 3 * parts < rr.y; s += 4 * parts) {
+            const v4<T> v0 = at(s), v1 = at(s + parts), v2 = at(s + 2 * parts), v3 = at(s + 3 * parts);
+            add(v0);
+            add(v1);
+            add(v2);
+            add(v3);
         }
+        for (; s < rr.y; s += parts) add(at(s));
     }
     red[t][0] = s0;
     red[t][1] = s1;
