@@ -712,6 +712,53 @@ __global__ __launch_bounds__(kT) void k_gemv_t_seg(const ZT* __restrict__ Z, int
     if (threadIdx.x < nc) wpart[int64_t(sgi) * k + j0 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// The same for the FP32 factor copy with N and the segment length multiples of
+// 4: a thread takes 4 consecutive rows at a time, so every factor load moves 16
+// bytes per lane (the one-row form moves 4 and reaches less of the HBM rate)
+__global__ __launch_bounds__(kT) void k_gemv_t_seg4(const float* __restrict__ Z, int64_t N, int k,
+                                                    const double* __restrict__ u, int64_t seg,
+                                                    double* __restrict__ wpart) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const int j0 = blockIdx.x * kGemvCols, sgi = blockIdx.y;
+    const int nc = min(kGemvCols, k - j0);
+    const int64_t r0 = int64_t(sgi) * seg, r1 = std::min<int64_t>(N, r0 + seg);
+    double a0[kGemvCols], a1[kGemvCols];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) a0[c] = a1[c] = 0.0;
+    auto step = [&](int64_t i, double (&a)[kGemvCols]) __attribute__((always_inline)) {
+        const d2v ua = *reinterpret_cast<const d2v*>(u + i), ub = *reinterpret_cast<const d2v*>(u + i + 2);
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c) {
+            if (c < nc) {
+                const f4v z = *reinterpret_cast<const f4v*>(Z + int64_t(j0 + c) * N + i);
+                a[c] += double(z[0]) * ua[0];
+                a[c] += double(z[1]) * ua[1];
+                a[c] += double(z[2]) * ub[0];
+                a[c] += double(z[3]) * ub[1];
+            }
+        }
+    };
+    int64_t i = r0 + 4 * threadIdx.x;
+    for (; i + 4 * kT < r1; i += 8 * kT) {
+        step(i, a0);
+        step(i + 4 * kT, a1);
+    }
+    if (i < r1) step(i, a0);
+    __shared__ double sh[kGemvCols][kT];
+#pragma unroll
+    for (int c = 0; c < kGemvCols; ++c) sh[c][threadIdx.x] = a0[c] + a1[c];
+    __syncthreads();
+    for (int s2 = kT / 2; s2 > 0; s2 >>= 1) {
+        if (threadIdx.x < s2) {
+#pragma unroll
+            for (int c = 0; c < kGemvCols; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + s2];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < nc) wpart[int64_t(sgi) * k + j0 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
 __global__ void k_gram_fold(const double* __restrict__ part, int nchunk, int k, double diag,
                             double* __restrict__ M) {
     int64_t e = blockIdx.x * int64_t(kT) + threadIdx.x;
@@ -1753,7 +1800,9 @@ void woodbury_apply(Workspace& ws, const double* y, const double* th, const doub
     if (ws.k > 0) {
         hipLaunchKernelGGL(k_wb_in, dim3(nblk(N)), dim3(kT), 0, st, y, th, r, N, ws.tmp.p);
         const dim3 g(unsigned((ws.k + kGemvCols - 1) / kGemvCols), unsigned(ws.nseg));
-        if (ws.Z32)
+        if (ws.Z32 && N % 4 == 0 && ws.seg % 4 == 0)
+            hipLaunchKernelGGL(k_gemv_t_seg4, g, dim3(kT), 0, st, ws.Z32, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
+        else if (ws.Z32)
             hipLaunchKernelGGL(k_gemv_t_seg<float>, g, dim3(kT), 0, st, ws.Z32, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
         else
             hipLaunchKernelGGL(k_gemv_t_seg<double>, g, dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
@@ -1822,7 +1871,8 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
         // solve to fold, and still four blocks per compute unit)
         const int64_t ncb = (k + kGemvCols - 1) / kGemvCols;
         ws.nseg = int(std::max<int64_t>(1, std::min<int64_t>((1024 + ncb - 1) / ncb, (N + 4095) / 4096)));
-        ws.seg = (N + ws.nseg - 1) / ws.nseg;
+        ws.seg = ((N + ws.nseg - 1) / ws.nseg + 3) / 4 * 4;  // whole groups of 4 rows
+        ws.nseg = int((N + ws.seg - 1) / ws.seg);
         ws.wpart.alloc(size_t(ws.nseg) * k);
     }
     ws.tmp.alloc(N + 1);
