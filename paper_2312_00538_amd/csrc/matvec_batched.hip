@@ -960,8 +960,12 @@ __device__ inline bool xcd_group(int nrs, int ne, int ngroups, int& slice, int& 
 }
 
 // fold step B + y and z passes; block per (x slice, window, slice of the rhs)
+// FP64: blocks of 512 threads, whose 256 registers per lane hold the fold's 64
+// loads in flight without spilling (1024-thread blocks have 128)
+template <class T>
+constexpr int fold_conv_threads() { return sizeof(T) == 8 ? 512 : 1024; }
 template <int W, class T>
-__global__ __launch_bounds__(1024) void k_fold_conv_yz_b(const WinDev* __restrict__ wins,
+__global__ __launch_bounds__(fold_conv_threads<T>()) void k_fold_conv_yz_b(const WinDev* __restrict__ wins,
                                                          const double* __restrict__ tmat,
                                                          const int2* __restrict__ crange,
                                                          const T* __restrict__ tgt, T* __restrict__ g1,
@@ -1281,7 +1285,8 @@ void batched_pass_t(Plan& pl, const ColPtrs& cols, int rn, hipStream_t st) {
                                  pl.emax[2] * pad4(pl.emax[2])) * sizeof(T);
     // one block per (slice, window, right-hand-side slice), groups padded to a multiple of 8
     auto xcd_blocks = [&](int64_t ne) { return unsigned((ne * pl.P + 7) / 8 * 8 * pl.b_rsplit); };
-    hipLaunchKernelGGL((k_fold_conv_yz_b<8, T>), dim3(xcd_blocks(pl.emax[0])), dim3(1024), lds_yz, st, pl.wins_d.p,
+    hipLaunchKernelGGL((k_fold_conv_yz_b<8, T>), dim3(xcd_blocks(pl.emax[0])), dim3(fold_conv_threads<T>()), lds_yz, st,
+                       pl.wins_d.p,
                        pl.tmat.p, pl.crange.p, tgt, g1, RH, int(pl.emax[0]), int(pl.P));
     const size_t lds_x = size_t(pl.emax[0] * pl.emax[2] * RH + pl.emax[0] * pad4(pl.emax[0])) * sizeof(T);
     hipLaunchKernelGGL(k_conv_x_b<T>, dim3(xcd_blocks(pl.emax[1])), dim3(1024), lds_x, st, pl.wins_d.p, pl.tmat.p,
