@@ -390,8 +390,12 @@ __global__ __launch_bounds__(256) void k_fold_cols_wide(const MvLaunch ML) {
 // its target line in (a, b) order (only source columns that exist and whose
 // layer range covers the cell contribute), then T_y and T_z are applied in LDS
 // and the slice is written as g1[x][y][z].
+// FP64: blocks of 512 threads, whose 256 registers per lane hold the fold's loads
+// without spilling (1024-thread blocks have 128)
+template <class WT>
+constexpr int fold_conv1_threads() { return sizeof(WT) == 8 ? 512 : 1024; }
 template <int W, class WT>
-__global__ __launch_bounds__(1024) void k_fold_conv_yz(const MvLaunch ML) {
+__global__ __launch_bounds__(fold_conv1_threads<WT>()) void k_fold_conv_yz(const MvLaunch ML) {
     extern __shared__ double sm[];
     int blk = blockIdx.x;
     const MvJob& J = ML.job[job_of(ML, blk)];
@@ -733,7 +737,7 @@ void run_jobs(MvLaunch& L, Plan* prof, hipStream_t st) {
     launch_jobs(L, [](const MvJob& J) { return (J.nflist3 + 3) / 4; }, k_fold_cols<WT>, 256, 0, st);
     launch_jobs(L, [](const MvJob& J) { return J.nflist - J.nflist3; }, k_fold_cols_wide<WT>, 256, 0, st);
     ev();
-    launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[0]) * J.P; }, k_fold_conv_yz<W, WT>, 1024,
+    launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[0]) * J.P; }, k_fold_conv_yz<W, WT>, fold_conv1_threads<WT>(),
                 size_t(2 * e1 * e2 + e1 * e1 + e2 * e2) * sizeof(double), st);
     launch_jobs(L, [](const MvJob& J) { return int64_t(J.emax[1]) * J.P; }, k_conv_x<WT>, 256,
                 size_t(e0 * e2 + e0 * e0) * sizeof(double), st);
