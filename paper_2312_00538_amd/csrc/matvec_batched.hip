@@ -68,21 +68,29 @@ __global__ __launch_bounds__(256) void k_transpose_in(const ColPtrs cols, int R,
 }
 
 // LDS chunks of CHB = 32 consecutive points of a work item, moved by DMA (16
-// bytes per lane per instruction). A record occupies RPB = 32 floats: x taps,
+// bytes per lane per instruction). A record occupies RPB = 36 floats: x taps,
 // y taps, z taps, and the z taps again, so that any 8 cyclically consecutive z
-// taps are 8 consecutive floats. A value row holds the point's 16 right-hand
+// taps are 8 consecutive floats, then 4 floats of padding, so that records of
+// consecutive points start 36 words apart and the 16 points a step reads at the
+// same offset fall on different LDS banks. Slot s (16 bytes) of a chunk holds
+// piece s % 9 of record s / 9. A value row holds the point's 16 right-hand
 // sides. Slots past the item read its last point (finite data; callers mask).
 constexpr int CHB = 32;
-constexpr int RPB = 32;
+constexpr int RPB = 36;
 
 __device__ inline void stage_records(float* lrec, const float* __restrict__ wts, int64_t base, int cstart, int count,
                                      int lane) {
     const float* ub = wts + (base + cstart) * 24;  // uniform; lanes add small offsets
     const int last = count - 1 - cstart;
+    constexpr int NS = CHB * RPB / 4;  // 16-byte slots of a chunk: 288, four 1 KB instructions and a half one
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {  // 8 records per 1 KB instruction
-        const int e = (lane % 8) * 4;
-        dma16(ub + min(j * 8 + lane / 8, last) * 24 + (e < 24 ? e : e - 8), lrec + j * 256);
+    for (int j = 0; j < (NS + 63) / 64; ++j) {
+        const int sl = j * 64 + lane;
+        if (sl < NS) {
+            const int rec = sl / (RPB / 4), piece = sl % (RPB / 4);
+            const int e = piece < 8 ? 4 * piece : 0;
+            dma16(ub + min(rec, last) * 24 + (e < 24 ? e : e - 8), lrec + j * 256);
+        }
     }
 }
 
@@ -467,14 +475,27 @@ __device__ inline void stage_records64(double* lrec, const double* __restrict__ 
 
 // CHB records with the z taps repeated (32 doubles each, 8 KB), so that any 8
 // cyclically consecutive z taps are 8 consecutive doubles: 4 records per slot.
+// Records for the FP64 gather: 16 pieces of 16 bytes (the x and y taps, then the
+// z taps twice, so that 8 consecutive z taps can be read from any start) and a
+// 17th of padding, so that the records of consecutive points start 68 words
+// apart: the 16 points a step reads at the same offset fall on different LDS
+// banks (with records 256 bytes apart they all fell on the same ones). Slot s of
+// a chunk holds piece s % 17 of record s / 17; the 544 slots of a chunk go out
+// as 8 1 KB direct loads and a half one, split between the two wavefronts.
+constexpr int kRecSlots64 = 17;
 __device__ inline void stage_records64_ring(double* lrec, const double* __restrict__ wts, int64_t base, int cstart,
                                             int count, int lane, int w) {
     const int last = count - 1 - cstart;
-    const int e = (lane % 16) * 2;
+    constexpr int NS = CHB * kRecSlots64;  // 16-byte slots of a chunk
 #pragma unroll
-    for (int j2 = 0; j2 < CHB / 8; ++j2) {
+    for (int j2 = 0; j2 < (NS + 127) / 128; ++j2) {
         const int j = 2 * j2 + w;
-        dma16(wts + (base + cstart + min(j * 4 + lane / 16, last)) * REC64 + (e < 24 ? e : e - 8), lrec + j * 128);
+        const int sl = j * 64 + lane;
+        if (j * 64 < NS && sl < NS) {
+            const int rec = sl / kRecSlots64, piece = sl % kRecSlots64;
+            const int e = piece < 12 ? 2 * piece : (piece < 16 ? 2 * piece - 8 : 0);
+            dma16(wts + (base + cstart + min(rec, last)) * REC64 + e, lrec + j * 128);
+        }
     }
 }
 
@@ -680,7 +701,7 @@ __global__ __launch_bounds__(128, 2) void k_gather_mfma64(const int32_t* __restr
                                                          const double* __restrict__ h, int64_t N,
                                                          double* __restrict__ fs) {
     constexpr int STEP = CHB - 16;
-    constexpr int RPD = 32;  // doubles per staged record (z taps repeated)
+    constexpr int RPD = 2 * kRecSlots64;  // doubles per staged record (z taps repeated, one padding piece)
     __shared__ __align__(16) double srec[2][CHB * RPD];
     __shared__ int slot;
     const int lane = threadIdx.x & 63;
