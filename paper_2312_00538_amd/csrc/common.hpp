@@ -98,6 +98,9 @@ double kb_hat(int k, int n, int m, double b);
 
 // ---------------------------------------------------------------- plan
 constexpr int kMaxW = 8;  // 2m for the supported cutoffs m <= 4
+// layers a work item spans at most (its z1 - z0 + 1): its z1 - z0 + 2 layer
+// starts then fit one per lane of a wavefront
+constexpr int kItemLayers = 62;
 
 // elements per point record of Kaiser-Bessel weights (x, y, z taps), padded to
 // a multiple of 16 bytes so records can be moved in 16-byte pieces

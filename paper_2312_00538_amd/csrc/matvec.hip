@@ -68,6 +68,144 @@ __device__ inline void stage_values_async(double* lds, const double* __restrict_
 
 __device__ inline void wait_vmem() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
+// Layer starts of a 3-feature work item (its points of layer z0 + i are
+// [ls[i], ls[i + 1])), held one entry per lane (an item spans at most
+// kItemLayers layers, so its z1 - z0 + 2 entries fit) and read with readlane:
+// the layer index is the same in every lane, so the layer loop issues no
+// memory access for them.
+struct LayerStarts {
+    int v;
+    __device__ LayerStarts(const int32_t* __restrict__ ls, int count, int lane) { v = lane < count ? ls[lane] : 0; }
+    __device__ void get(int i, int& p, int& q) const {
+        p = __builtin_amdgcn_readlane(v, i);
+        q = __builtin_amdgcn_readlane(v, i + 1);
+    }
+};
+
+// LDS reads of staged point data for 8 taps per axis. They are written as asm
+// with the wait for their own completion inside the block: the compiler would
+// otherwise make every LDS read wait for all DMA in flight, the prefetch of the
+// next chunk included. Staged data are read only after the explicit wait at the
+// chunk switch.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t lds_addr(const void* p) { return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p)); }
+
+// one tap's x weight (at xa), an input value (at va) and the 8 y and 8 z
+// weights (16 consecutive elements at yz, 16-byte aligned)
+__device__ inline void lds_point8(uint32_t xa, uint32_t va, uint32_t yz, double& wx, double& v, double (&wy)[8],
+                                  double (&wz)[8]) {
+    d2v q[8];
+    asm volatile(
+        "ds_read_b64 %0, %10\n\t"
+        "ds_read_b64 %1, %11\n\t"
+        "ds_read_b128 %2, %12\n\t"
+        "ds_read_b128 %3, %12 offset:16\n\t"
+        "ds_read_b128 %4, %12 offset:32\n\t"
+        "ds_read_b128 %5, %12 offset:48\n\t"
+        "ds_read_b128 %6, %12 offset:64\n\t"
+        "ds_read_b128 %7, %12 offset:80\n\t"
+        "ds_read_b128 %8, %12 offset:96\n\t"
+        "ds_read_b128 %9, %12 offset:112\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx), "=&v"(v), "=&v"(q[0]), "=&v"(q[1]), "=&v"(q[2]), "=&v"(q[3]), "=&v"(q[4]), "=&v"(q[5]),
+          "=&v"(q[6]), "=&v"(q[7])
+        : "v"(xa), "v"(va), "v"(yz)
+        : "memory");
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        wy[2 * i] = q[i].x;
+        wy[2 * i + 1] = q[i].y;
+        wz[2 * i] = q[4 + i].x;
+        wz[2 * i + 1] = q[4 + i].y;
+    }
+}
+
+__device__ inline void lds_point8(uint32_t xa, uint32_t va, uint32_t yz, float& wx, double& v, float (&wy)[8],
+                                  float (&wz)[8]) {
+    f4v q[4];
+    asm volatile(
+        "ds_read_b32 %0, %6\n\t"
+        "ds_read_b64 %1, %7\n\t"
+        "ds_read_b128 %2, %8\n\t"
+        "ds_read_b128 %3, %8 offset:16\n\t"
+        "ds_read_b128 %4, %8 offset:32\n\t"
+        "ds_read_b128 %5, %8 offset:48\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(wx), "=&v"(v), "=&v"(q[0]), "=&v"(q[1]), "=&v"(q[2]), "=&v"(q[3])
+        : "v"(xa), "v"(va), "v"(yz)
+        : "memory");
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            wy[4 * i + j] = q[i][j];
+            wz[4 * i + j] = q[2 + i][j];
+        }
+}
+
+// Per-layer sums over the 8 lane groups of the 3-feature spread (8 taps, row
+// stride 72 elements): lane l writes its 8 values (y taps b) at red[b * 72 + l]
+// and reads the 8 group values of its own (a, b) at red[b * 72 + g * 8 + a],
+// g = 0..7. The block is one wavefront, whose LDS instructions run in order, so
+// no barrier is needed between the writes and the reads.
+__device__ inline void lds_red8(uint32_t wa, uint32_t ra, const double (&w)[8], double (&r)[8]) {
+    asm volatile(
+        "ds_write_b64 %0, %1\n\t"
+        "ds_write_b64 %0, %2 offset:576\n\t"
+        "ds_write_b64 %0, %3 offset:1152\n\t"
+        "ds_write_b64 %0, %4 offset:1728\n\t"
+        "ds_write_b64 %0, %5 offset:2304\n\t"
+        "ds_write_b64 %0, %6 offset:2880\n\t"
+        "ds_write_b64 %0, %7 offset:3456\n\t"
+        "ds_write_b64 %0, %8 offset:4032"
+        :
+        : "v"(wa), "v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]), "v"(w[6]), "v"(w[7])
+        : "memory");
+    asm volatile(
+        "ds_read_b64 %0, %8\n\t"
+        "ds_read_b64 %1, %8 offset:64\n\t"
+        "ds_read_b64 %2, %8 offset:128\n\t"
+        "ds_read_b64 %3, %8 offset:192\n\t"
+        "ds_read_b64 %4, %8 offset:256\n\t"
+        "ds_read_b64 %5, %8 offset:320\n\t"
+        "ds_read_b64 %6, %8 offset:384\n\t"
+        "ds_read_b64 %7, %8 offset:448\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7])
+        : "v"(ra)
+        : "memory");
+}
+
+__device__ inline void lds_red8(uint32_t wa, uint32_t ra, const float (&w)[8], float (&r)[8]) {
+    asm volatile(
+        "ds_write_b32 %0, %1\n\t"
+        "ds_write_b32 %0, %2 offset:288\n\t"
+        "ds_write_b32 %0, %3 offset:576\n\t"
+        "ds_write_b32 %0, %4 offset:864\n\t"
+        "ds_write_b32 %0, %5 offset:1152\n\t"
+        "ds_write_b32 %0, %6 offset:1440\n\t"
+        "ds_write_b32 %0, %7 offset:1728\n\t"
+        "ds_write_b32 %0, %8 offset:2016"
+        :
+        : "v"(wa), "v"(w[0]), "v"(w[1]), "v"(w[2]), "v"(w[3]), "v"(w[4]), "v"(w[5]), "v"(w[6]), "v"(w[7])
+        : "memory");
+    asm volatile(
+        "ds_read_b32 %0, %8\n\t"
+        "ds_read_b32 %1, %8 offset:32\n\t"
+        "ds_read_b32 %2, %8 offset:64\n\t"
+        "ds_read_b32 %3, %8 offset:96\n\t"
+        "ds_read_b32 %4, %8 offset:128\n\t"
+        "ds_read_b32 %5, %8 offset:160\n\t"
+        "ds_read_b32 %6, %8 offset:192\n\t"
+        "ds_read_b32 %7, %8 offset:224\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7])
+        : "v"(ra)
+        : "memory");
+}
+
 // Block b of a launch belongs to job j with off[j] <= b < off[j + 1]; returns j
 // and turns b into the job's local block index.
 __device__ inline int job_of(const MvLaunch& L, int& b) {
@@ -114,12 +252,12 @@ __device__ __forceinline__ void spread_grp(const MvJob& J, const int blk) {
     constexpr int PADR = (kHalf ? 32 : 16) / int(sizeof(WT));
     constexpr int RS = REC + PADR;
     constexpr int STEP = CH - G;               // chunk c holds points [c*STEP, c*STEP + CH)
-    __shared__ WT stw[2][CH * RS];
-    __shared__ double stv[2][128];
+    __shared__ __align__(16) WT stw[2][CH * RS];
+    __shared__ __align__(16) double stv[2][128];
     // per-layer group sums: plane b holds [g][a] (consecutive lanes write consecutive
     // elements); the plane stride 72 = 64 + 8 spreads the (a, b) readers over all banks
     constexpr int RP = 64 + 8;
-    __shared__ WT red[W * RP];
+    __shared__ __align__(16) WT red[W * RP];
     const int sid = J.wave_items[J.wave_off[3] + blk];
     const Segment sg = segs[sid];
     const int lane = threadIdx.x;
@@ -147,9 +285,24 @@ __device__ __forceinline__ void spread_grp(const MvJob& J, const int blk) {
         tstride = 1;
     }
     int cc = -1;
+    LayerStarts lsw(ls, sg.z1 - sg.z0 + 2, lane);
     stage_records_async<WT, REC, RS, CH>(stw[0], wts, base, 0, sg.count, lane);
     stage_values_async(stv[0], vs, base, 0, sg.count, lane);
     auto flush = [&](int layer, int c) {  // sum acc[.][c] over groups -> row `layer`
+        if constexpr (W == 8) {
+            WT w8[W], r8[W];
+#pragma unroll
+            for (int b = 0; b < W; ++b) w8[b] = acc[b][c];
+            lds_red8(lds_addr(&red[lane]), lds_addr(&red[(lane % W) * RP + lane / W]), w8, r8);
+            WT t = WT(0);
+#pragma unroll
+            for (int q = 0; q < G; ++q) t += r8[q];
+            if (direct)
+                tout[int64_t(layer) * tstride] = t;
+            else
+                out[int64_t(layer) * (W * W) + lane] = t;
+            return;
+        }
         if (lane_ok) {
 #pragma unroll
             for (int b = 0; b < W; ++b) red[b * RP + g * W + a] = acc[b][c];
@@ -168,7 +321,8 @@ __device__ __forceinline__ void spread_grp(const MvJob& J, const int blk) {
         __syncthreads();
     };
     for (int z = sg.z0; z <= sg.z1; ++z) {
-        const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+        int p, q;
+        lsw.get(z - sg.z0, p, q);
         for (int k = p; k < q; k += G) {
             const int c = k / STEP;
             if (c > cc) {  // chunk c has landed; start moving chunk c+1 into the other buffer
@@ -184,15 +338,28 @@ __device__ __forceinline__ void spread_grp(const MvJob& J, const int blk) {
             const int pt = k + g;
             if (lane_ok && pt < q) {
                 const WT* w = &stw[c & 1][(pt - cbase) * RS];
-                const WT vx = WT(stv[c & 1][pt - cbase]) * w[a];
-                WT wz[W];
+                if constexpr (W == 8) {
+                    WT wx, wy[W], wz[W];
+                    double v;
+                    lds_point8(lds_addr(w + a), lds_addr(&stv[c & 1][pt - cbase]), lds_addr(w + W), wx, v, wy, wz);
+                    const WT vx = WT(v) * wx;
 #pragma unroll
-                for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
+                    for (int b = 0; b < W; ++b) {
+                        const WT cb = vx * wy[b];
 #pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    const WT cb = vx * w[W + b];
+                        for (int c = 0; c < W; ++c) acc[b][c] += cb * wz[c];
+                    }
+                } else {
+                    const WT vx = WT(stv[c & 1][pt - cbase]) * w[a];
+                    WT wz[W];
 #pragma unroll
-                    for (int c = 0; c < W; ++c) acc[b][c] += cb * wz[c];
+                    for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        const WT cb = vx * w[W + b];
+#pragma unroll
+                        for (int c = 0; c < W; ++c) acc[b][c] += cb * wz[c];
+                    }
                 }
             }
         }
@@ -458,7 +625,9 @@ __global__ __launch_bounds__(fold_conv1_threads<WT>()) void k_fold_conv_yz(const
     for (int e = threadIdx.x; e < S; e += blockDim.x) {  // z pass
         const int y = e / Ez, z = e % Ez;
         double acc = 0.0;
-        for (int k = 0; k < Ez; ++k) acc += tz[z * Ez + k] * s1[y * Ez + k];
+        // T_z is symmetric (entries depend on |i - k|): read it by column, so
+        // that consecutive lanes (consecutive z) hit consecutive LDS banks
+        for (int k = 0; k < Ez; ++k) acc += tz[k * Ez + z] * s1[y * Ez + k];
         out[e] = WT(acc);
     }
 }
@@ -516,7 +685,7 @@ __device__ __forceinline__ void gather_grp(const MvJob& J, const int blk) {
     constexpr int PADR = (kHalf ? 32 : 16) / int(sizeof(WT));
     constexpr int RS = REC + PADR;
     constexpr int STEP = CH - G;
-    __shared__ WT stw[2][CH * RS];
+    __shared__ __align__(16) WT stw[2][CH * RS];
     const int sid = J.wave_items[J.wave_off[3] + blk];
     const Segment sg = segs[sid];
     const WinDev& wd = wins[sg.win];
@@ -529,15 +698,26 @@ __device__ __forceinline__ void gather_grp(const MvJob& J, const int blk) {
     const int cy = sg.col % wd.nb[1];
     const int Ey = wd.E[1];
     const WT* hp = h + wd.grid_off + int64_t(cx + (lane_ok ? a : 0)) * wd.E[2] * Ey + cy;
-    WT hr[W][W];
+    // hr: the grid values of the current layer's footprint; hn: those of the
+    // z-cell the next layer brings in, loaded one layer ahead
+    WT hr[W][W], hn[W];
 #pragma unroll
     for (int c = 0; c < W; ++c)
 #pragma unroll
         for (int b = 0; b < W; ++b) hr[b][c] = hp[int64_t(sg.z0 + c) * Ey + b];
+    if (sg.z0 < sg.z1) {
+#pragma unroll
+        for (int b = 0; b < W; ++b) hn[b] = hp[int64_t(sg.z0 + W) * Ey + b];
+    }
     int cc = -1;
+    LayerStarts lsw(ls, sg.z1 - sg.z0 + 2, lane);
     stage_records_async<WT, REC, RS, CH>(stw[0], wts, base, 0, sg.count, lane);
+    // the first step waits for the first chunk anyway; waiting here as well
+    // keeps the layer starts out of the waits inside the loop
+    wait_vmem();
     for (int z = sg.z0; z <= sg.z1; ++z) {
-        const int p = ls[z - sg.z0], q = ls[z - sg.z0 + 1];
+        int p, q;
+        lsw.get(z - sg.z0, p, q);
         for (int k = p; k < q; k += G) {
             const int c = k / STEP;
             if (c > cc) {
@@ -553,18 +733,33 @@ __device__ __forceinline__ void gather_grp(const MvJob& J, const int blk) {
             double part = 0.0;
             if (act) {
                 const WT* w = &stw[c & 1][(pt - cbase) * RS];
-                WT wz[W];
+                if constexpr (W == 8) {
+                    WT wx, wy[W], wz[W];
+                    double unused;
+                    lds_point8(lds_addr(w + a), lds_addr(w), lds_addr(w + W), wx, unused, wy, wz);
+                    WT sy = WT(0);
 #pragma unroll
-                for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
-                WT sy = WT(0);
+                    for (int b = 0; b < W; ++b) {
+                        WT t = WT(0);
 #pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    WT t = WT(0);
+                        for (int c = 0; c < W; ++c) t += wz[c] * hr[b][c];
+                        sy += wy[b] * t;
+                    }
+                    part = double(wx * sy);
+                } else {
+                    WT wz[W];
 #pragma unroll
-                    for (int c = 0; c < W; ++c) t += wz[c] * hr[b][c];
-                    sy += w[W + b] * t;
+                    for (int c = 0; c < W; ++c) wz[c] = w[2 * W + c];
+                    WT sy = WT(0);
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        WT t = WT(0);
+#pragma unroll
+                        for (int c = 0; c < W; ++c) t += wz[c] * hr[b][c];
+                        sy += w[W + b] * t;
+                    }
+                    part = double(w[a] * sy);
                 }
-                part = double(w[a] * sy);
             }
             if constexpr ((W & (W - 1)) == 0) {
 #pragma unroll
@@ -582,7 +777,11 @@ __device__ __forceinline__ void gather_grp(const MvJob& J, const int blk) {
             for (int b = 0; b < W; ++b) {
 #pragma unroll
                 for (int c = 0; c < W - 1; ++c) hr[b][c] = hr[b][c + 1];
-                hr[b][W - 1] = hp[int64_t(z + W) * Ey + b];
+                hr[b][W - 1] = hn[b];
+            }
+            if (z + 1 < sg.z1) {
+#pragma unroll
+                for (int b = 0; b < W; ++b) hn[b] = hp[int64_t(z + 1 + W) * Ey + b];
             }
         }
     }

@@ -443,7 +443,10 @@ Plan* create_plan(const double* X, int64_t N, int32_t d, int64_t ldx, const int3
                 sg.start = int32_t(j);
                 sg.z0 = int32_t(kk[j] % nbz);
                 int32_t cnt = 0;
-                while (j < N && int64_t(kk[j] / nbz) == col && cnt < sp) {
+                // at most kItemLayers layers per item, so that a wavefront holds
+                // the item's layer starts in one register (one entry per lane)
+                while (j < N && int64_t(kk[j] / nbz) == col && cnt < sp &&
+                       int32_t(kk[j] % nbz) - sg.z0 < kItemLayers) {
                     ++j;
                     ++cnt;
                 }
