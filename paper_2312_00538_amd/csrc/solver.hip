@@ -960,7 +960,7 @@ __global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double*
 
 // Capacitance factor and solves for k <= kRegCholK. k_chol_reg leaves L in
 // the lower triangle of M and L^T in its strict upper triangle (M[i][j] =
-// L[max(i, j)][min(i, j)]), so that k_chol_solve_w reads only rows of M.
+// L[max(i, j)][min(i, j)]), so that k_chol_solve_b reads only rows of M.
 constexpr int kRegCholK = 256;
 constexpr int kRegWaves = 8;   // slots per wavefront: 12 up to k = 208 (91 blocks), 17 up to k = 256 (136)
 
@@ -1111,155 +1111,127 @@ __device__ __forceinline__ double lane_bcast(double x, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-// t = (L L^T)^{-1} w for k <= kRegCholK with the factor as k_chol_reg leaves
-// it (row stride ldm, a multiple of 16), w the sum of the nseg partial vectors
-// wpart[g][:] (segments in order). One wavefront; lane l holds entries l + 64 r
-// (r = 0..3). Forward sweep, step j: lane j % 64 finishes z_j, a lane broadcast
-// hands it to every lane, and each lane subtracts L[i][j] z_j from its entries
-// i > j, read from row j of M right of the diagonal (L^T's row j). The backward
-// sweep runs the same way down the rows, reading row j left of the diagonal
-// (L's row j). Rows stream into an LDS ring by direct 16-byte loads kSwAhead
-// rows ahead of the step that needs them (two 1 KB pieces per row, rows past the
-// end going to a spare slot so that every step issues the same two), and the
-// steps go in groups of four rows, which one LDS read block serves.
-constexpr int kSwRing = 32, kSwAhead = 24, kSwG = 4;
-static_assert(2 * (kSwAhead + kSwG) <= 63, "loads in flight must fit the vector memory counter");
-
-__device__ __forceinline__ void dma_row(const double* __restrict__ Lm, int k, int ldm, int j, double* slot, int l) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int e = 128 * h + 2 * l;
-        const double* src = Lm + int64_t(j) * ldm + (e < k ? e : 0);
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
-                                         (__attribute__((address_space(3))) void*)(slot + 128 * h), 16, 0, 0);
+// Inverses of the 16 x 16 diagonal blocks of the capacitance factor L (as
+// k_chol_reg leaves it), block J row-major at Dinv + 256 J and transposed at
+// Dinv + 256 (nb + J) (nb blocks); rows and columns past k belong to an
+// identity block. One wavefront per block: lane c < 16 solves L_JJ x = e_c by
+// forward substitution (entries above the diagonal come out as exact zeros).
+__global__ __launch_bounds__(64) void k_diag_inv(const double* __restrict__ Lm, int k, int ldm,
+                                                 double* __restrict__ Dinv) {
+    __shared__ double lb[16][17];
+    const int J = int(blockIdx.x), c0 = 16 * J, l = int(threadIdx.x);
+    for (int e = l; e < 256; e += 64) {
+        const int r = e / 16, i = e % 16;
+        lb[r][i] = (c0 + r < k && c0 + i < k) ? Lm[int64_t(c0 + r) * ldm + c0 + i] : (r == i ? 1.0 : 0.0);
     }
-}
-
-// the lane's four entries of the kSwG rows in ring slots s0 .. s0 + 3 (mod
-// kSwRing), read and waited for in one block
-__device__ __forceinline__ void ring_read(const double* ring, int s0, int l, double (&v)[kSwG][4]) {
-    const unsigned a0 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 0) % kSwRing) * 256 + l)) ;
-    const unsigned a1 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 1) % kSwRing) * 256 + l));
-    const unsigned a2 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 2) % kSwRing) * 256 + l));
-    const unsigned a3 = unsigned(reinterpret_cast<uintptr_t>(ring + ((s0 + 3) % kSwRing) * 256 + l));
-    asm volatile(
-        "ds_read_b64 %0, %16\n\tds_read_b64 %1, %16 offset:512\n\t"
-        "ds_read_b64 %2, %16 offset:1024\n\tds_read_b64 %3, %16 offset:1536\n\t"
-        "ds_read_b64 %4, %17\n\tds_read_b64 %5, %17 offset:512\n\t"
-        "ds_read_b64 %6, %17 offset:1024\n\tds_read_b64 %7, %17 offset:1536\n\t"
-        "ds_read_b64 %8, %18\n\tds_read_b64 %9, %18 offset:512\n\t"
-        "ds_read_b64 %10, %18 offset:1024\n\tds_read_b64 %11, %18 offset:1536\n\t"
-        "ds_read_b64 %12, %19\n\tds_read_b64 %13, %19 offset:512\n\t"
-        "ds_read_b64 %14, %19 offset:1024\n\tds_read_b64 %15, %19 offset:1536\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(v[0][0]), "=&v"(v[0][1]), "=&v"(v[0][2]), "=&v"(v[0][3]), "=&v"(v[1][0]), "=&v"(v[1][1]),
-          "=&v"(v[1][2]), "=&v"(v[1][3]), "=&v"(v[2][0]), "=&v"(v[2][1]), "=&v"(v[2][2]), "=&v"(v[2][3]),
-          "=&v"(v[3][0]), "=&v"(v[3][1]), "=&v"(v[3][2]), "=&v"(v[3][3])
-        : "v"(a0), "v"(a1), "v"(a2), "v"(a3)
-        : "memory");
-}
-
-// kSwG steps on rows j of entry slot RJ (row order as in v); entries whose
-// value must not change read as zero (masked by the caller's predicate)
-template <int RJ, bool FWD>
-__device__ __forceinline__ void sweep_group(double (&b)[4], const double (&rd)[4], const double (&v)[kSwG][4],
-                                            const int (&rows)[kSwG], int k, int l) {
-    const int lo = 64 * RJ;
+    __syncthreads();
+    if (l < 16) {
+        double x[16];
 #pragma unroll
-    for (int q = 0; q < kSwG; ++q) {
-        const int j = rows[q];
-        if (j < k) {
-            const double xj = lane_bcast(b[RJ] * rd[RJ], j - lo);
-            if (l == j - lo) b[RJ] = xj;
+        for (int r = 0; r < 16; ++r) {
+            double v = r == l ? 1.0 : 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = l + 64 * r;
-                if (FWD ? (r >= RJ && i > j && i < k) : (r <= RJ && i < j)) b[r] -= v[q][r] * xj;
-            }
+            for (int i = 0; i < r; ++i) v -= lb[r][i] * x[i];
+            x[r] = v / lb[r][r];
         }
+        const int nb = int(gridDim.x);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dinv[256 * J + 16 * r + l] = x[r];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Dinv[256 * (nb + J) + 16 * l + r] = x[r];
     }
 }
 
-__global__ __launch_bounds__(64) void k_chol_solve_w(const double* __restrict__ Lm, int k, int ldm,
+// t = (L L^T)^{-1} w for k <= kRegCholK with the factor as k_chol_reg leaves
+// it (L on and below the diagonal of M, L^T above it, row stride ldm, a
+// multiple of 16) and the inverses of its diagonal blocks from k_diag_inv; w
+// the sum of the nseg partial vectors wpart[g][:] (segments in order). Both
+// sweeps go over panels of 16 rows: 16 lanes multiply the panel's part of the
+// right-hand side by the inverse of the diagonal block (forward) or by its
+// transpose (backward), so no step waits on another; then every thread
+// subtracts its own row's product with the panel's 16 solved entries (forward:
+// the rows after the panel, reading L left of the diagonal; backward: the rows
+// before it, reading row j right of the diagonal, which holds L^T's row j). A
+// panel's entries are loaded while the panel before it is solved.
+constexpr int kSbT = 256;  // threads; k <= kRegCholK <= kSbT rows, one per thread
+static_assert(kRegCholK <= kSbT, "one thread per row of the capacitance matrix");
+
+// Barrier for the LDS hand-offs of k_chol_solve_b: waits for the wave's LDS
+// accesses only, so that loads issued for later panels stay in flight across it
+// (a __syncthreads would wait for them as well).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" : : : "memory"); }
+
+__global__ __launch_bounds__(kSbT) void k_chol_solve_b(const double* __restrict__ Lm, int k, int ldm,
+                                                      const double* __restrict__ Dinv,
                                                       const double* __restrict__ wpart, int nseg,
                                                       double* __restrict__ t) {
-    __shared__ __attribute__((aligned(16))) double ring[(kSwRing + 1) * 256];
-    double* spare = ring + kSwRing * 256;
-    const int l = threadIdx.x;
-    double b[4], rd[4];
-    // w: the partial vectors added in segment order, the loads of sixteen
-    // segments issued together (a plain loop waits for every load in turn)
+    __shared__ double bv[kSbT];  // right-hand side, then the solution
+    __shared__ double xs[16];    // a panel's solved entries
+    const int tid = int(threadIdx.x);
+    const int nb = (k + 15) / 16;
+    // panel s of the two sweeps (s < nb forward, then nb .. 2 nb - 1 backward)
+    auto panel_col = [&](int s) __attribute__((always_inline)) { return 16 * (s < nb ? s : 2 * nb - 1 - s); };
+    // the thread's row's 16 entries of panel s's columns (rows after the panel
+    // forward, before it backward), and for threads t < 16 row t (forward) or
+    // column t (backward) of the inverse diagonal block. The loads read whole
+    // panels of a row (rows are padded to ldm = 16 nb columns; the users drop
+    // the padding columns and the rows that do not take part), threads past k
+    // reading row 0, so that every load is in bounds and no load has to be
+    // waited for before the panel that uses it.
+    const double* __restrict__ myrow = Lm + int64_t(tid < k ? tid : 0) * ldm;
+    const int dl = tid & 15;
+    auto load_panel = [&](int s, double (&lp)[16], double (&dr)[16]) __attribute__((always_inline)) {
+        const int c0 = panel_col(s < 2 * nb ? s : 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = l + 64 * r;
-        b[r] = 0.0;
-        rd[r] = 1.0 / (i < k ? Lm[int64_t(i) * ldm + i] : 1.0);
-    }
-    for (int g = 0; g < nseg; g += 16) {  // segments past nseg add exact zeros
-        double x[16][4];
+        for (int i = 0; i < 16; ++i) lp[i] = myrow[c0 + i];
+        // forward: row t of the inverse block, from its transpose; backward:
+        // column t; either way lanes read consecutive entries
+        const double* db = Dinv + 256 * (c0 / 16 + (s < nb ? nb : 0));
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
+        for (int i = 0; i < 16; ++i) dr[i] = db[16 * i + dl];
+    };
+    auto panel = [&](int s, const double (&lp)[16], const double (&dr)[16], double (&lpn)[16], double (&drn)[16])
+                     __attribute__((always_inline)) {
+        const bool fwd = s < nb;
+        const int c0 = panel_col(s);
+        load_panel(s + 1, lpn, drn);
+        if (tid < 16) {
+            double acc = 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = l + 64 * r;
-                x[q][r] = (i < k && g + q < nseg) ? wpart[int64_t(g + q) * k + i] : 0.0;
-            }
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) b[r] += x[q][r];
-    }
-    // stream position p of a sweep holds row row_of(p): groups of kSwG aligned
-    // rows (4 g .. 4 g + 3), ascending for the forward sweep and descending
-    // (groups and rows within them) for the backward one; rows >= k are spare
-    const int ng = (k + kSwG - 1) / kSwG, npos = ng * kSwG;
-#pragma unroll
-    for (int sw = 0; sw < 2; ++sw) {
-        const bool fwd = sw == 0;
-        auto row_of = [&](int p) __attribute__((always_inline)) {
-            return fwd ? p : kSwG * (ng - 1 - p / kSwG) + (kSwG - 1 - p % kSwG);
-        };
-        auto issue = [&](int p) __attribute__((always_inline)) {
-            const int j = p < npos ? row_of(p) : k;
-            if (j < k)
-                dma_row(Lm, k, ldm, j, ring + (p % kSwRing) * 256, l);
-            else
-                dma_row(Lm, k, ldm, 0, spare, l);
-        };
-        for (int p = 0; p < kSwAhead; ++p) issue(p);
-        for (int p0 = 0; p0 < npos; p0 += kSwG) {
-#pragma unroll
-            for (int q = 0; q < kSwG; ++q) issue(p0 + kSwAhead + q);
-            // the group's rows have landed once at most 2 kSwAhead pieces are outstanding
-            __builtin_amdgcn_s_waitcnt(0x0F70 | ((2 * kSwAhead) & 15) | (((2 * kSwAhead) >> 4) << 14));
-            double v[kSwG][4];
-            ring_read(ring, p0 % kSwRing, l, v);
-            int rows[kSwG];
-#pragma unroll
-            for (int q = 0; q < kSwG; ++q) rows[q] = row_of(p0 + q);
-            const int rj = (fwd ? rows[0] : rows[kSwG - 1]) >> 6;  // the group's lowest row
-            if (fwd) {
-                switch (rj) {
-                    case 0: sweep_group<0, true>(b, rd, v, rows, k, l); break;
-                    case 1: sweep_group<1, true>(b, rd, v, rows, k, l); break;
-                    case 2: sweep_group<2, true>(b, rd, v, rows, k, l); break;
-                    default: sweep_group<3, true>(b, rd, v, rows, k, l); break;
-                }
-            } else {
-                switch (rj) {
-                    case 0: sweep_group<0, false>(b, rd, v, rows, k, l); break;
-                    case 1: sweep_group<1, false>(b, rd, v, rows, k, l); break;
-                    case 2: sweep_group<2, false>(b, rd, v, rows, k, l); break;
-                    default: sweep_group<3, false>(b, rd, v, rows, k, l); break;
-                }
-            }
+            for (int i = 0; i < 16; ++i) acc += dr[i] * bv[c0 + i];
+            const bool live = c0 + tid < k;
+            if (live) bv[c0 + tid] = acc;
+            xs[tid] = live ? acc : 0.0;
         }
-        // the sweep's trailing spare loads land before the ring is reused
-        __builtin_amdgcn_s_waitcnt(0x0F70);
-    }
+        lds_barrier();
+        double acc = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (l + 64 * r < k) t[l + 64 * r] = b[r];
+        for (int i = 0; i < 16; ++i) acc += (c0 + i < k ? lp[i] : 0.0) * xs[i];
+        if (tid < k && (fwd ? tid >= c0 + 16 : tid < c0)) bv[tid] -= acc;
+        lds_barrier();
+    };
+    double lpa[16], dra[16], lpb[16], drb[16];
+    load_panel(0, lpa, dra);
+    {
+        // w: the partial vectors added in segment order, 32 loads issued together
+        // (in flight with the first panel's)
+        double sum = 0.0;
+        for (int g = 0; g < nseg; g += 32) {
+            double x[32];
+#pragma unroll
+            for (int q = 0; q < 32; ++q) x[q] = (tid < k && g + q < nseg) ? wpart[int64_t(g + q) * k + tid] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 32; ++q) sum += x[q];
+        }
+        bv[tid] = sum;
+    }
+    lds_barrier();
+#pragma unroll 1
+    for (int s = 0; s < 2 * nb; s += 2) {  // 2 nb panels: an even count
+        panel(s, lpa, dra, lpb, drb);
+        panel(s + 1, lpb, drb, lpa, dra);
+    }
+    if (tid < k) t[tid] = bv[tid];
 }
 
 // ------------------------------------------------------------------ IPM vector kernels
@@ -1775,6 +1747,7 @@ struct Workspace {
     const double* Z = nullptr;            // N x k column-major low-rank factor Z^T
     const float* Z32 = nullptr;           // its FP32 copy, when the N x k products run in FP32
     DevBuf<double> M, Mpart, Mgrp, t;     // capacitance (its factor in place), partials, group sums, M^{-1} w
+    DevBuf<double> Dinv;                  // inverses of the factor's 16 x 16 diagonal blocks and their transposes
     DevBuf<int> status;
     DevBuf<double> tmp, kyz;              // N
     DevBuf<double> wpart;                 // per-segment partials of Z^T u
@@ -1807,8 +1780,8 @@ void woodbury_apply(Workspace& ws, const double* y, const double* th, const doub
         else
             hipLaunchKernelGGL(k_gemv_t_seg<double>, g, dim3(kT), 0, st, ws.Z, N, ws.k, ws.tmp.p, ws.seg, ws.wpart.p);
         if (ws.k <= kRegCholK)
-            hipLaunchKernelGGL(k_chol_solve_w, dim3(1), dim3(64), 0, st, ws.M.p, ws.k, ws.ldm, ws.wpart.p, ws.nseg,
-                               ws.t.p);
+            hipLaunchKernelGGL(k_chol_solve_b, dim3(1), dim3(kSbT), 0, st, ws.M.p, ws.k, ws.ldm, ws.Dinv.p, ws.wpart.p,
+                               ws.nseg, ws.t.p);
         else
             hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(256), ws.k * sizeof(double), st, ws.M.p, ws.k,
                                ws.wpart.p, ws.nseg, ws.t.p);
@@ -1838,10 +1811,11 @@ void refresh_capacitance(Workspace& ws, const double* th, hipStream_t st) {
                        ws.nchunk, k, ws.Mgrp.p);
     hipLaunchKernelGGL(k_syrk_fold_fin, dim3(nblk(int64_t(k) * k)), dim3(kT), 0, st, ws.Mgrp.p, ng, k, 1.0, ws.M.p,
                        ws.ldm);
-    if (k <= kRegCholK)
+    if (k <= kRegCholK) {
         hipLaunchKernelGGL(k <= 208 ? k_chol_reg<12> : k_chol_reg<17>, dim3(1), dim3(64 * kRegWaves), 0, st, ws.M.p, k,
                            ws.ldm, ws.status.p);
-    else
+        hipLaunchKernelGGL(k_diag_inv, dim3(unsigned((k + 15) / 16)), dim3(64), 0, st, ws.M.p, k, ws.ldm, ws.Dinv.p);
+    } else
         hipLaunchKernelGGL(k_chol, dim3(1), dim3(kCholT), 0, st, ws.M.p, k, ws.status.p);
     // read back through pinned memory: an asynchronous copy into pageable
     // (here: stack) memory is not guaranteed to have landed when the stream's
@@ -1855,10 +1829,10 @@ void setup_factor_storage(Workspace& ws, int64_t N, int k) {
     ws.N = N;
     ws.k = k;
     if (k > 0) {
-        // rows of the register-resident factor start on 128-byte boundaries (the
-        // solve streams them into LDS in 16-byte pieces)
+        // rows of the register-resident factor padded to whole 16-column panels
         ws.ldm = k <= kRegCholK ? (k + 15) / 16 * 16 : k;
         ws.M.alloc(size_t(k) * ws.ldm);
+        if (k <= kRegCholK) ws.Dinv.alloc(size_t((k + 15) / 16) * 512);
         ws.t.alloc(k);
         ws.status.alloc(1);
         if (k <= kRegCholK)
