@@ -958,6 +958,13 @@ __global__ void k_chol_solve(const double* __restrict__ Lm, int k, const double*
     for (int i = tid; i < k; i += blockDim.x) t[i] = sx[i];
 }
 
+// value of x in lane `lane` (a wave-uniform index), in every lane
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
 // Capacitance factor and solves for k <= kRegCholK. k_chol_reg leaves L in
 // the lower triangle of M and L^T in its strict upper triangle (M[i][j] =
 // L[max(i, j)][min(i, j)]), so that k_chol_solve_b reads only rows of M.
@@ -1039,7 +1046,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
             for (int c = 0; c < 16; ++c) d[c] = (l < 16 && c <= l) ? P[p][l][c] : 0.0;
 #pragma unroll
             for (int c = 0; c < 16; ++c) {
-                double dcc = __shfl(d[c], c, 64);
+                double dcc = lane_bcast(d[c], c);
                 if (!(dcc > 0.0)) {
                     if (l == 0) bad = 1;
                     dcc = 1e-300;
@@ -1050,7 +1057,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
                 else if (l > c) d[c] *= rdc;
 #pragma unroll
                 for (int cc = c + 1; cc < 16; ++cc) {
-                    const double lcc = __shfl(d[c], cc, 64);  // L[cc][c], from lane cc
+                    const double lcc = lane_bcast(d[c], cc);  // L[cc][c], from lane cc
                     if (cc <= l && l < 16) d[cc] -= d[c] * lcc;
                 }
             }
@@ -1105,11 +1112,6 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
     if (t == 0) status[0] = bad;
 }
 
-__device__ __forceinline__ double lane_bcast(double x, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-    return __hiloint2double(hi, lo);
-}
 
 // Inverses of the 16 x 16 diagonal blocks of the capacitance factor L (as
 // k_chol_reg leaves it), block J row-major at Dinv + 256 J and transposed at
