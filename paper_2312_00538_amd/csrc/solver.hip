@@ -381,17 +381,20 @@ __global__ __launch_bounds__(256) void k_syrk_mfma(const ZT* __restrict__ Z, int
 // per row chunk computes every lower 16 x 16 result block over its rows, the
 // blocks dealt to its kSyW wavefronts in turn (block q, counted down the block
 // columns, to wavefront q % kSyW, slot q / kSyW), so that every wavefront issues
-// nearly the same number of matrix-core products. 16-row panels of Z (all k
+// nearly the same number of matrix-core products. Panels of P rows of Z (all k
 // columns) and their weights 1 / theta are staged in LDS, double-buffered; the
-// next panel's loads are in flight while the current one is multiplied.
+// next panel's loads are in flight while the current one is multiplied. P = 32
+// for k <= 208 (half the barriers of 16-row panels: 560 -> 503 us at N = 5e5,
+// k = 200), 16 above, where 32 rows would spill registers.
 constexpr int kSyW = 8;
 constexpr int kSyKP = 256 + 1;  // panel row stride in LDS
-template <int NS>
+constexpr int kSyChunk = 32;    // row chunks are whole panels of either height
+template <int NS, int P>
 __global__ __launch_bounds__(64 * kSyW) void k_syrk_tri(const double* __restrict__ Z, int64_t N, int k,
                                                          const double* __restrict__ theta, int64_t chunk,
                                                          double* __restrict__ part) {
     typedef double d4 __attribute__((ext_vector_type(4)));
-    __shared__ double pz[2][kSP][kSyKP], wt[2][kSP];
+    __shared__ double pz[2][P][kSyKP], wt[2][P];
     __shared__ int blk[kSyW * NS];  // block q: I | J << 8 (-1: none)
     const int t = threadIdx.x, w = t >> 6, l = t & 63;
     const int nb = (k + 15) >> 4, nq = nb * (nb + 1) / 2;
@@ -408,16 +411,16 @@ __global__ __launch_bounds__(64 * kSyW) void k_syrk_tri(const double* __restrict
     }
     const int c = blockIdx.x;
     const int64_t i0 = int64_t(c) * chunk, i1 = std::min<int64_t>(N, i0 + chunk);
-    constexpr int PE = kSP * 256 / (64 * kSyW);  // panel elements per thread
+    constexpr int PE = P * 256 / (64 * kSyW);  // panel elements per thread
     double ra[PE], rw = 0.0;
     auto load_panel = [&](int64_t ib0) __attribute__((always_inline)) {
 #pragma unroll
         for (int m = 0; m < PE; ++m) {
-            const int e = t + 64 * kSyW * m, col = e / kSP, r = e % kSP;
+            const int e = t + 64 * kSyW * m, col = e / P, r = e % P;
             const int64_t i = ib0 + r;
             ra[m] = (col < k && i < i1) ? Z[int64_t(col) * N + i] : 0.0;
         }
-        if (t < kSP) {
+        if (t < P) {
             const int64_t i = ib0 + t;
             rw = (i < i1) ? (theta ? 1.0 / theta[i] : 1.0) : 0.0;
         }
@@ -435,17 +438,17 @@ __global__ __launch_bounds__(64 * kSyW) void k_syrk_tri(const double* __restrict
     }
     if (i0 < i1) load_panel(i0);
     int buf = 0;
-    for (int64_t ib0 = i0; ib0 < i1; ib0 += kSP, buf ^= 1) {
+    for (int64_t ib0 = i0; ib0 < i1; ib0 += P, buf ^= 1) {
 #pragma unroll
         for (int m = 0; m < PE; ++m) {
             const int e = t + 64 * kSyW * m;
-            pz[buf][e % kSP][e / kSP] = ra[m];
+            pz[buf][e % P][e / P] = ra[m];
         }
-        if (t < kSP) wt[buf][t] = rw;
+        if (t < P) wt[buf][t] = rw;
         __syncthreads();
-        if (ib0 + kSP < i1) load_panel(ib0 + kSP);
+        if (ib0 + P < i1) load_panel(ib0 + P);
 #pragma unroll
-        for (int s4 = 0; s4 < kSP / 4; ++s4) {
+        for (int s4 = 0; s4 < P / 4; ++s4) {
             const int r = 4 * s4 + (l >> 4);
             const double wr = wt[buf][r];
 #pragma unroll
@@ -537,7 +540,7 @@ void syrk_tri_chunks(int64_t N, int k, int& nchunk, int64_t& chunk) {
     want = std::min<int64_t>(want, std::max<int64_t>(1, (int64_t(256) << 20) / (int64_t(k) * k * 8)));
     want = std::min<int64_t>(want, std::max<int64_t>(1, N / 256));
     chunk = (N + want - 1) / want;
-    chunk = (chunk + kSP - 1) / kSP * kSP;
+    chunk = (chunk + kSyChunk - 1) / kSyChunk * kSyChunk;
     nchunk = int((N + chunk - 1) / chunk);
 }
 
@@ -1803,7 +1806,7 @@ void refresh_capacitance(Workspace& ws, const double* th, hipStream_t st) {
     // the FP64 factor (holding the FP32 copy's values when there is one): the
     // 128-column panels of the Gram kernel read whole 128-byte rows in FP64
     if (k <= kRegCholK)
-        hipLaunchKernelGGL(k <= 208 ? k_syrk_tri<12> : k_syrk_tri<17>, dim3(unsigned(ws.nchunk)), dim3(64 * kSyW), 0,
+        hipLaunchKernelGGL((k <= 208 ? k_syrk_tri<12, 32> : k_syrk_tri<17, 16>), dim3(unsigned(ws.nchunk)), dim3(64 * kSyW), 0,
                            st, ws.Z, ws.N, k, th, ws.chunk, ws.Mpart.p);
     else
         hipLaunchKernelGGL(k_syrk_mfma<double>, dim3(unsigned(ns * (ns + 1) / 2), unsigned(ws.nchunk)), dim3(256), 0,
@@ -1996,7 +1999,7 @@ struct Gram {
     // (A == B: k <= 256)
     std::vector<double> run(const double* A, const double* B, int64_t N, int k, hipStream_t st) {
         if (A == B && k <= kRegCholK) {
-            hipLaunchKernelGGL(k <= 208 ? k_syrk_tri<12> : k_syrk_tri<17>, dim3(unsigned(nchunk_t)), dim3(64 * kSyW), 0,
+            hipLaunchKernelGGL((k <= 208 ? k_syrk_tri<12, 32> : k_syrk_tri<17, 16>), dim3(unsigned(nchunk_t)), dim3(64 * kSyW), 0,
                                st, A, N, k, (const double*)nullptr, chunk_t, part.p);
             fold_tri(k, false, st);
         } else if (A != B && k <= 208) {
