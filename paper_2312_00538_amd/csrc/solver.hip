@@ -974,6 +974,21 @@ __device__ __forceinline__ double lane_bcast(double x, int lane) {
 constexpr int kRegCholK = 256;
 constexpr int kRegWaves = 8;   // slots per wavefront: 12 up to k = 208 (91 blocks), 17 up to k = 256 (136)
 
+// 1 / sqrt(x) for x > 0 to about one unit in the last place: the hardware
+// estimate refined by two Newton steps y <- y (3/2 - x y^2 / 2)
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y *= fma(-h * y, y, 1.5);
+    y *= fma(-h * y, y, 1.5);
+    return y;
+}
+
+// Barrier for LDS hand-offs between the wavefronts of a block: waits for the
+// wave's LDS accesses only, so that global loads and stores issued earlier stay
+// in flight across it (a __syncthreads would wait for them as well).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" : : : "memory"); }
+
 // In-place Cholesky, one block of kRegWaves wavefronts, blocked by 16 x 16. The
 // nb (nb + 1) / 2 lower blocks stay in registers in the FP64 matrix-core result
 // layout (lane l, element e: row l / 16 + 4 e, column l % 16); block q, counted
@@ -985,7 +1000,9 @@ constexpr int kRegWaves = 8;   // slots per wavefront: 12 up to k = 208 (91 bloc
 // triangles, and every wavefront subtracts P_I P_J^T from its blocks (I, J),
 // J > p, on the matrix cores. The LDS copy is double-buffered: the barriers of
 // (a)-(c) of column p + 1 separate (d) of column p - 1 from the reuse of its
-// buffer. status[0] = 0 ok, 1 = non-positive pivot.
+// buffer. The barriers wait for LDS traffic only (no wavefront reads what another
+// writes to global memory), so (d)'s stores drain while the next column is
+// factored. status[0] = 0 ok, 1 = non-positive pivot.
 template <int NS>
 __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict__ M, int k, int ldm,
                                                               int* __restrict__ status) {
@@ -1041,7 +1058,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
 #pragma unroll
                 for (int e = 0; e < 4; ++e) P[I][(l >> 4) + 4 * e][l & 15] = acc[s][e];
         }
-        __syncthreads();
+        lds_barrier();
         // (b)
         if (w == 0) {
             double d[16];
@@ -1054,9 +1071,11 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
                     if (l == 0) bad = 1;
                     dcc = 1e-300;
                 }
-                dcc = sqrt(dcc);
-                const double rdc = 1.0 / dcc;
-                if (l == c) d[c] = dcc;
+                // 1 / sqrt(pivot) from the hardware estimate and two Newton steps
+                // (each doubles the correct bits), the square root as pivot times it:
+                // a short dependent chain, where sqrt and a division take two long ones
+                const double rdc = rsqrt_nr(dcc);
+                if (l == c) d[c] = dcc * rdc;
                 else if (l > c) d[c] *= rdc;
 #pragma unroll
                 for (int cc = c + 1; cc < 16; ++cc) {
@@ -1070,7 +1089,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
                 rdiag[l] = 1.0 / d[l];
             }
         }
-        __syncthreads();
+        lds_barrier();
         // (c)
         if (t < (nb - 1 - p) * 16) {
             const int I = p + 1 + (t >> 4), r = t & 15;
@@ -1087,7 +1106,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
 #pragma unroll
             for (int c = 0; c < 16; ++c) P[I][r][c] = x[c];
         }
-        __syncthreads();
+        lds_barrier();
         // (d) the finished column, then the trailing update
         for (int idx = t; idx < (nb - p) * 256; idx += 64 * kRegWaves) {
             const int I = p + (idx >> 8), r = (idx >> 4) & 15, c = idx & 15;
@@ -1112,6 +1131,7 @@ __global__ __launch_bounds__(64 * kRegWaves) void k_chol_reg(double* __restrict_
             }
         }
     }
+    lds_barrier();
     if (t == 0) status[0] = bad;
 }
 
@@ -1161,10 +1181,6 @@ __global__ __launch_bounds__(64) void k_diag_inv(const double* __restrict__ Lm, 
 constexpr int kSbT = 256;  // threads; k <= kRegCholK <= kSbT rows, one per thread
 static_assert(kRegCholK <= kSbT, "one thread per row of the capacitance matrix");
 
-// Barrier for the LDS hand-offs of k_chol_solve_b: waits for the wave's LDS
-// accesses only, so that loads issued for later panels stay in flight across it
-// (a __syncthreads would wait for them as well).
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" : : : "memory"); }
 
 __global__ __launch_bounds__(kSbT) void k_chol_solve_b(const double* __restrict__ Lm, int k, int ldm,
                                                       const double* __restrict__ Dinv,
