@@ -995,7 +995,8 @@ __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(
 // down the block columns, belongs to wavefront q % kRegWaves, slot q / kRegWaves. The matrix
 // is padded to whole blocks with the identity. For block column p: (a) its
 // owners copy it to LDS; (b) wavefront 0 factors the diagonal block (lane r
-// holds row r, shuffles broadcast the pivots); (c) one thread per row below it
+// holds row r, lane reads broadcast the pivots and the finished column's
+// entries); (c) one thread per row below it
 // solves x L_pp^T = m; (d) the finished column goes to global memory in both
 // triangles, and every wavefront subtracts P_I P_J^T from its blocks (I, J),
 // J > p, on the matrix cores. The LDS copy is double-buffered: the barriers of
@@ -1180,7 +1181,6 @@ __global__ __launch_bounds__(64) void k_diag_inv(const double* __restrict__ Lm, 
 // panel's entries are loaded while the panel before it is solved.
 constexpr int kSbT = 256;  // threads; k <= kRegCholK <= kSbT rows, one per thread
 static_assert(kRegCholK <= kSbT, "one thread per row of the capacitance matrix");
-
 
 __global__ __launch_bounds__(kSbT) void k_chol_solve_b(const double* __restrict__ Lm, int k, int ldm,
                                                       const double* __restrict__ Dinv,
